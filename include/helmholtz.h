@@ -1,0 +1,198 @@
+/*
+ * helmholtz.h -- C ABI of the MI355X (gfx950) shifted-Laplace preconditioned
+ * Helmholtz solver.
+ *
+ * The library solves the constant-density damped Helmholtz equation
+ *     -Lap u - omega^2 m^2 (1 - j alpha) u = f                     (Eq. 2)
+ * with a first-order absorbing boundary, discretised as H u = W f (Eq. 3),
+ * by right-preconditioned flexible GMRES,
+ *     H M^{-1} z = W f,  u = M^{-1} z                               (Eq. 5-7)
+ * with the shifted Laplacian M = -Lap - (beta1 - j beta2) omega^2 m^2 of Eq. 6
+ * as preconditioner (Kazemi, arXiv:1712.08740, Section "Data modelling").
+ *
+ * Discretisation (the paper prints none): second-order centred differences
+ * (3-point in 1D, 5-point in 2D); boundary condition du/dn + j k u = 0 with
+ * k = omega m, eliminated through a centred ghost node; every boundary row is
+ * multiplied by 1/2 per boundary axis, and the right-hand side by the same row
+ * weights W, which makes H and M exactly complex-symmetric. M^{-1} is applied
+ * exactly in 1D (tridiagonal solve by parallel cyclic reduction) and
+ * approximately in 2D by one V(2,2) multigrid cycle: omega-Jacobi smoothing
+ * (weight 0.8), full-weighting restriction R = P^T / 2^{d_c}, bilinear
+ * prolongation P, Galerkin coarse operators R M P, and a direct (explicit
+ * inverse) solve on the coarsest grid. A dimension of n nodes and spacing h is
+ * coarsened to (n-1)/2+1 nodes when n-1 is even, (n-1)/2 >= 2 and
+ * omega * max(m) * 2h <= pi (two or more nodes per shortest wavelength).
+ *
+ * Layout: real arrays are float64; complex arrays are complex128 stored as
+ * interleaved (re, im) pairs. 1D grids have n nodes; 2D grids are stored
+ * (nz, nx) row-major with x fastest.
+ *
+ * Pointers named *_dev are device pointers on the current HIP device; the
+ * caller owns them. "stream" is a hipStream_t (NULL = the null stream). All
+ * entry points return an hh_status; nothing aborts or throws across the ABI.
+ * On error, hh_last_error() returns a message (thread-local, valid until the
+ * next call on the same thread). A problem handle is not thread-safe; distinct
+ * handles may be used concurrently from distinct threads on distinct streams.
+ */
+#ifndef HH_HELMHOLTZ_H
+#define HH_HELMHOLTZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hh_problem_s* hh_problem;
+
+enum hh_status {
+    HH_OK            =  0,  /* converged / done                                   */
+    HH_NOT_CONVERGED =  1,  /* iteration budget spent; u holds the last iterate   */
+    HH_EINVAL        = -1,  /* invalid argument; nothing was launched             */
+    HH_ENOMEM        = -2,  /* device allocation failed                           */
+    HH_EDEVICE       = -3,  /* a HIP runtime call failed                          */
+    HH_ENUMERIC      = -4,  /* NaN/Inf in a residual norm or breakdown quantity   */
+    HH_EUNSUPPORTED  = -5   /* valid input outside what this build implements     */
+};
+
+/* hh_solve flags */
+#define HH_NO_PRECOND 1u    /* plain GMRES on H (the paper's comparison, Fig. 3b/4) */
+
+/* Largest coarsest-grid size (unknowns) inverted densely. */
+#define HH_MAX_COARSE 4096
+/* Largest 1D grid handled by the single-workgroup tridiagonal solve. */
+#define HH_MAX_1D 1024
+
+/*
+ * hh_create_problem -- set up H for one model and frequency (Eq. 2-3).
+ *   m_dev  : slowness 1/c (s/m), float64, n (1D) or nz*nx (2D) values, finite
+ *            and > 0 (checked on the device; EINVAL otherwise). Copied: the
+ *            caller may free it after the call returns.
+ *   ndim   : 1 or 2.   shape: {n} or {nz, nx}; every entry >= 3; 1D n <= HH_MAX_1D.
+ *   omega  : angular frequency 2 pi f (rad/s), > 0.
+ *   alpha  : damping of Eq. 2, >= 0.
+ *   h      : grid spacing (m), equal in x and z, > 0.
+ *   stream : stream for the set-up work; the call returns after it completes.
+ *   out    : receives the handle. The default shift (beta1, beta2) = (1, 0.5) is
+ *            applied (hh_set_shift).
+ * Returns EINVAL on bad arguments, EUNSUPPORTED when the coarsest multigrid grid
+ * would exceed HH_MAX_COARSE unknowns, ENOMEM/EDEVICE on runtime failure.
+ */
+int hh_create_problem(const double* m_dev, int ndim, const int64_t* shape, double omega,
+                      double alpha, double h, void* stream, hh_problem* out);
+
+/*
+ * hh_set_shift -- choose the shifted-Laplace preconditioner of Eq. 6,
+ * M = -Lap - (beta1 - j beta2) omega^2 m^2 (same absorbing rows as H).
+ * Rebuilds the multigrid hierarchy (Galerkin operators and coarsest inverse,
+ * 2D) or the tridiagonal coefficients (1D) on the device. beta1, beta2 finite.
+ * beta = (1, alpha) gives M = H.
+ */
+int hh_set_shift(hh_problem p, double beta1, double beta2);
+
+/* Bytes of device workspace hh_solve needs for a given restart length. */
+int hh_workspace_bytes(hh_problem p, int restart, size_t* bytes);
+
+/*
+ * hh_solve -- right-preconditioned FGMRES(restart) on H u = W f, x0 = 0.
+ *   f_dev     : complex128 source, grid-shaped (not modified).
+ *   tol       : relative tolerance in (0, 1) on ||W f - H u||_2 / ||W f||_2.
+ *   restart   : Krylov basis length per cycle, 1..1024.
+ *   max_iters : budget of preconditioned operator applications, >= 1.
+ *   flags     : 0 or HH_NO_PRECOND.
+ *   workspace_dev / workspace_bytes : caller-owned device scratch of at least
+ *               hh_workspace_bytes(p, restart) bytes; contents are overwritten.
+ *   u_dev     : complex128 output wavefield, grid-shaped (caller-owned).
+ *   iterations: number of Arnoldi steps taken (may be NULL).
+ *   true_rel_res : recomputed ||W f - H u|| / ||W f|| at exit (may be NULL).
+ *   hist_host : host array; hist[0] = 1, hist[k] = Givens residual estimate
+ *               after step k; at most hist_cap entries written (may be NULL).
+ *   hist_len  : entries available (iterations + 1) (may be NULL).
+ *   stream    : stream for the solve; the call returns after it completes.
+ * Returns HH_OK when the recomputed residual meets tol (a happy breakdown counts),
+ * HH_NOT_CONVERGED when max_iters is spent (u = last iterate), HH_ENUMERIC on
+ * NaN/Inf. W f = 0 returns u = 0 and HH_OK with zero iterations.
+ */
+int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_iters,
+             unsigned flags, void* workspace_dev, size_t workspace_bytes, void* u_dev,
+             int* iterations, double* true_rel_res, double* hist_host, int hist_cap,
+             int* hist_len, void* stream);
+
+/* Releases every device allocation of the handle. NULL is accepted. */
+int hh_destroy_problem(hh_problem p);
+
+/* Static description of a status code (thread-safe). */
+const char* hh_status_string(int status);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* hh_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Single steps of the solve, exported so that each can be checked on its own.
+ * ------------------------------------------------------------------------- */
+
+/* Number of multigrid levels (1 for 1D problems) and one level's grid:
+ * shape2 = {nz, nx} (1D: {1, n}), spacing2 = {hz, hx}. */
+int hh_num_levels(hh_problem p, int* nlevels);
+int hh_level_info(hh_problem p, int level, int64_t* shape2, double* spacing2);
+
+/*
+ * hh_apply_operator -- y = A x on the fine grid, where which = 0 selects H
+ * (Eq. 2-3) and which = 1 the shifted Laplacian M (Eq. 6). x_dev, y_dev:
+ * complex128, grid-shaped, distinct. Matrix-free stencil kernel.
+ */
+int hh_apply_operator(hh_problem p, int which, const void* x_dev, void* y_dev, void* stream);
+
+/*
+ * hh_apply_level_operator -- y = M_l x on multigrid level l (l = 0 is M; l >= 1
+ * the Galerkin operator R M_{l-1} P). Sizes are the level's grid.
+ */
+int hh_apply_level_operator(hh_problem p, int level, const void* x_dev, void* y_dev,
+                            void* stream);
+
+/*
+ * hh_apply_precond -- z = M^{-1} v as used inside the solve (Eq. 7): the exact
+ * tridiagonal solve in 1D, one V(2,2) cycle in 2D. v_dev, z_dev complex128,
+ * grid-shaped, distinct; workspace as for hh_solve (any restart >= 1).
+ */
+int hh_apply_precond(hh_problem p, const void* v_dev, void* z_dev, void* workspace_dev,
+                     size_t workspace_bytes, void* stream);
+
+/*
+ * hh_orthogonalize -- one classical Gram-Schmidt step with reorthogonalisation
+ * (CGS2), the Arnoldi step of GMRES: given k orthonormal complex128 vectors of
+ * length n stored contiguously (V_dev, vector i at V_dev + i*n) and w_dev,
+ * computes h = V^H w, w -= V h, h2 = V^H w, w -= V h2, returns h + h2 in
+ * h_host (k complex128 values, interleaved) and ||w||_2 in *norm_host.
+ * 1 <= k <= 1024; scratch_dev must hold hh_orthogonalize_scratch_bytes(n, k).
+ */
+int hh_orthogonalize_scratch_bytes(int64_t n, int k, size_t* bytes);
+int hh_orthogonalize(const void* V_dev, int64_t n, int k, void* w_dev, void* scratch_dev,
+                     size_t scratch_bytes, double* h_host, double* norm_host, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (measurement support). After hh_kernel_timer_start(p, id),
+ * every launch of that kernel class inside hh_solve on this handle is
+ * bracketed by a pair of HIP events recorded on the solve's stream; the
+ * elapsed times and the algorithmic bytes of each launch (the byte model of
+ * the kernel: data it must read and write once) are accumulated until read.
+ * id = HH_KERNEL_NONE switches timing off.
+ * ------------------------------------------------------------------------- */
+enum hh_kernel_id {
+    HH_KERNEL_NONE    = 0,
+    HH_KERNEL_STENCIL = 1,  /* w = H z, fine grid: 40 B/node (z, m^2 in; w out)          */
+    HH_KERNEL_JACOBI  = 2,  /* fine-grid Jacobi sweep: 56 B/node (b, x, m^2 in; x out)   */
+    HH_KERNEL_DOT     = 3,  /* CGS2 projections V^H w: (k+1)*16 B/node                    */
+    HH_KERNEL_AXPY    = 4,  /* CGS2 update w -= V h: (k+2)*16 B/node                      */
+    HH_KERNEL_GEMV    = 5,  /* coarsest dense inverse times vector: (n^2+2n)*16 B         */
+    HH_KERNEL_PCR     = 6   /* 1D tridiagonal solve: 40 B/node                            */
+};
+int hh_kernel_timer_start(hh_problem p, int kernel_id);
+int hh_kernel_timer_read(hh_problem p, int64_t* launches, double* total_ms,
+                         double* total_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HH_HELMHOLTZ_H */

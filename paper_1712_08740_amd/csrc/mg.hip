@@ -1,0 +1,362 @@
+// Multigrid transfer and set-up kernels for the approximate shifted-Laplace
+// inverse (Eq. 6-7): full-weighting restriction R = P^T / 2^{d_c}, (bi)linear
+// prolongation P, Galerkin coarse operators R M P (9-point), the explicit
+// inverse of the coarsest operator (Gauss-Jordan with partial pivoting) and
+// its application as a dense complex matrix-vector product.
+#include "hh_internal.h"
+
+namespace hh {
+
+namespace {
+
+constexpr int BX = 64;
+constexpr int BZ = 4;
+
+dim3 grid2(int nz, int nx) { return dim3((nx + BX - 1) / BX, (nz + BZ - 1) / BZ); }
+
+// Coarse nodes J with P[q, J] != 0 along one axis, and their weights.
+__device__ __forceinline__ int interp_nodes(int q, int halved, int* J, double* w) {
+    if (!halved) { J[0] = q; w[0] = 1.0; return 1; }
+    if ((q & 1) == 0) { J[0] = q >> 1; w[0] = 1.0; return 1; }
+    J[0] = (q - 1) >> 1; w[0] = 0.5;
+    J[1] = (q + 1) >> 1; w[1] = 0.5;
+    return 2;
+}
+
+__global__ void __launch_bounds__(256) k_restrict(int nzf, int nxf, int hz, int hx,
+                                                  const cplx* __restrict__ rf, int nzc, int nxc,
+                                                  cplx* __restrict__ bc, double scale) {
+    const int Ix = blockIdx.x * BX + threadIdx.x;
+    const int Iz = blockIdx.y * BZ + threadIdx.y;
+    if (Ix >= nxc || Iz >= nzc) return;
+    const int fz = hz ? 2 * Iz : Iz;
+    const int fx = hx ? 2 * Ix : Ix;
+    const int rz = hz ? 1 : 0, rx = hx ? 1 : 0;
+    cplx acc = mk(0.0, 0.0);
+    for (int dz = -rz; dz <= rz; ++dz) {
+        const int qz = fz + dz;
+        if (qz < 0 || qz >= nzf) continue;
+        const double wz = dz == 0 ? 1.0 : 0.5;
+        for (int dx = -rx; dx <= rx; ++dx) {
+            const int qx = fx + dx;
+            if (qx < 0 || qx >= nxf) continue;
+            const double wx = dx == 0 ? 1.0 : 0.5;
+            acc = cadd(acc, cscale(rf[(int64_t)qz * nxf + qx], wz * wx));
+        }
+    }
+    bc[(int64_t)Iz * nxc + Ix] = cscale(acc, scale);
+}
+
+__global__ void __launch_bounds__(256) k_prolong_add(int nzf, int nxf, int hz, int hx,
+                                                     const cplx* __restrict__ ec, int nzc, int nxc,
+                                                     cplx* __restrict__ xf) {
+    const int fx = blockIdx.x * BX + threadIdx.x;
+    const int fz = blockIdx.y * BZ + threadIdx.y;
+    if (fx >= nxf || fz >= nzf) return;
+    int Jz[2], Jx[2];
+    double wz[2], wx[2];
+    const int nzj = interp_nodes(fz, hz, Jz, wz);
+    const int nxj = interp_nodes(fx, hx, Jx, wx);
+    cplx acc = mk(0.0, 0.0);
+    for (int a = 0; a < nzj; ++a)
+        for (int b = 0; b < nxj; ++b)
+            acc = cadd(acc, cscale(ec[(int64_t)Jz[a] * nxc + Jx[b]], wz[a] * wx[b]));
+    const int64_t p = (int64_t)fz * nxf + fx;
+    xf[p] = cadd(xf[p], acc);
+}
+
+// Accumulate R[I,p] * A[p,q] * P[q,J] over the fine rows p of R's support and
+// the entries q of row p; row p is produced by the functor `row(pz, px, emit)`.
+template <class RowFn>
+__device__ __forceinline__ void galerkin_node(int Iz, int Ix, int nzf, int nxf, int hz, int hx,
+                                              double inv2dc, RowFn row, cplx acc[9]) {
+    for (int t = 0; t < 9; ++t) acc[t] = mk(0.0, 0.0);
+    const int fz = hz ? 2 * Iz : Iz;
+    const int fx = hx ? 2 * Ix : Ix;
+    const int rz = hz ? 1 : 0, rx = hx ? 1 : 0;
+    for (int dz = -rz; dz <= rz; ++dz) {
+        const int pz = fz + dz;
+        if (pz < 0 || pz >= nzf) continue;
+        for (int dx = -rx; dx <= rx; ++dx) {
+            const int px = fx + dx;
+            if (px < 0 || px >= nxf) continue;
+            const double rw = (dz == 0 ? 1.0 : 0.5) * (dx == 0 ? 1.0 : 0.5) * inv2dc;
+            row(pz, px, [&](int qz, int qx, cplx a) {
+                int Jz[2], Jx[2];
+                double wz[2], wx[2];
+                const int nzj = interp_nodes(qz, hz, Jz, wz);
+                const int nxj = interp_nodes(qx, hx, Jx, wx);
+                for (int u = 0; u < nzj; ++u)
+                    for (int v = 0; v < nxj; ++v) {
+                        const int t = (Jz[u] - Iz + 1) * 3 + (Jx[v] - Ix + 1);
+                        acc[t] = cadd(acc[t], cscale(a, rw * wz[u] * wx[v]));
+                    }
+            });
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_galerkin_from_fine(FineOp op, int hz, int hx, int nzc,
+                                                            int nxc, cplx* __restrict__ Cc) {
+    const int Ix = blockIdx.x * BX + threadIdx.x;
+    const int Iz = blockIdx.y * BZ + threadIdx.y;
+    if (Ix >= nxc || Iz >= nzc) return;
+    const double inv2dc = 1.0 / (double)((hz ? 2 : 1) * (hx ? 2 : 1));
+    cplx acc[9];
+    auto row = [&](int pz, int px, auto emit) {
+        const int64_t p = (int64_t)pz * op.nx + px;
+        const Coef5 c = fine_coefs(op, pz, px, op.m2[p]);
+        emit(pz, px, c.diag);
+        if (px > 0) emit(pz, px - 1, mk(-c.cx, 0.0));
+        if (px < op.nx - 1) emit(pz, px + 1, mk(-c.cx, 0.0));
+        if (pz > 0) emit(pz - 1, px, mk(-c.cz, 0.0));
+        if (pz < op.nz - 1) emit(pz + 1, px, mk(-c.cz, 0.0));
+    };
+    galerkin_node(Iz, Ix, op.nz, op.nx, hz, hx, inv2dc, row, acc);
+    const int64_t Nc = (int64_t)nzc * nxc;
+    const int64_t P = (int64_t)Iz * nxc + Ix;
+    for (int t = 0; t < 9; ++t) Cc[t * Nc + P] = acc[t];
+}
+
+__global__ void __launch_bounds__(256) k_galerkin_from_coarse(CoarseOp op, int hz, int hx,
+                                                              int nzc, int nxc,
+                                                              cplx* __restrict__ Cc) {
+    const int Ix = blockIdx.x * BX + threadIdx.x;
+    const int Iz = blockIdx.y * BZ + threadIdx.y;
+    if (Ix >= nxc || Iz >= nzc) return;
+    const double inv2dc = 1.0 / (double)((hz ? 2 : 1) * (hx ? 2 : 1));
+    const int64_t Nf = (int64_t)op.nz * op.nx;
+    cplx acc[9];
+    auto row = [&](int pz, int px, auto emit) {
+        const int64_t p = (int64_t)pz * op.nx + px;
+        for (int sz = -1; sz <= 1; ++sz) {
+            const int qz = pz + sz;
+            if (qz < 0 || qz >= op.nz) continue;
+            for (int sx = -1; sx <= 1; ++sx) {
+                const int qx = px + sx;
+                if (qx < 0 || qx >= op.nx) continue;
+                emit(qz, qx, op.C[((sz + 1) * 3 + (sx + 1)) * Nf + p]);
+            }
+        }
+    };
+    galerkin_node(Iz, Ix, op.nz, op.nx, hz, hx, inv2dc, row, acc);
+    const int64_t Nc = (int64_t)nzc * nxc;
+    const int64_t P = (int64_t)Iz * nxc + Ix;
+    for (int t = 0; t < 9; ++t) Cc[t * Nc + P] = acc[t];
+}
+
+// Dense row-major n x n matrix of a level operator (A must be zeroed first).
+__global__ void __launch_bounds__(256) k_dense_from_fine(FineOp op, cplx* __restrict__ A) {
+    const int ix = blockIdx.x * BX + threadIdx.x;
+    const int iz = blockIdx.y * BZ + threadIdx.y;
+    if (ix >= op.nx || iz >= op.nz) return;
+    const int64_t n = (int64_t)op.nz * op.nx;
+    const int64_t p = (int64_t)iz * op.nx + ix;
+    const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
+    cplx* row = A + p * n;
+    row[p] = c.diag;
+    if (ix > 0) row[p - 1] = mk(-c.cx, 0.0);
+    if (ix < op.nx - 1) row[p + 1] = mk(-c.cx, 0.0);
+    if (op.ndim == 2) {
+        if (iz > 0) row[p - op.nx] = mk(-c.cz, 0.0);
+        if (iz < op.nz - 1) row[p + op.nx] = mk(-c.cz, 0.0);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_dense_from_coarse(CoarseOp op, cplx* __restrict__ A) {
+    const int ix = blockIdx.x * BX + threadIdx.x;
+    const int iz = blockIdx.y * BZ + threadIdx.y;
+    if (ix >= op.nx || iz >= op.nz) return;
+    const int64_t n = (int64_t)op.nz * op.nx;
+    const int64_t p = (int64_t)iz * op.nx + ix;
+    cplx* row = A + p * n;
+    for (int sz = -1; sz <= 1; ++sz) {
+        const int qz = iz + sz;
+        if (qz < 0 || qz >= op.nz) continue;
+        for (int sx = -1; sx <= 1; ++sx) {
+            const int qx = ix + sx;
+            if (qx < 0 || qx >= op.nx) continue;
+            row[(int64_t)qz * op.nx + qx] = op.C[((sz + 1) * 3 + (sx + 1)) * n + p];
+        }
+    }
+}
+
+// ---- Gauss-Jordan inversion ------------------------------------------------
+// Step k, part 1 (one workgroup): pivot row p = argmax_{i>=k} |A[i][k]|
+// (smallest index on ties); prow = new row k scaled by 1/pivot with the
+// identity column folded in; pcol = column k after the row swap; rowk = old
+// row k (it becomes row p).
+constexpr int GJ_THREADS = 1024;
+
+__global__ void __launch_bounds__(GJ_THREADS) k_gj_pivot(int n, int k, const cplx* __restrict__ A,
+                                                         cplx* __restrict__ prow,
+                                                         cplx* __restrict__ pcol,
+                                                         cplx* __restrict__ rowk,
+                                                         int* __restrict__ perm) {
+    __shared__ double sval[GJ_THREADS / 64];
+    __shared__ int sidx[GJ_THREADS / 64];
+    __shared__ int s_p;
+    const int tid = threadIdx.x;
+    double best = -1.0;
+    int bidx = n;
+    for (int i = k + tid; i < n; i += GJ_THREADS) {
+        const double v = cabs2(A[(int64_t)i * n + k]);
+        if (v > best) { best = v; bidx = i; }   // strided ascending: first max kept
+    }
+    // wave reduction: larger value wins, smaller index on ties
+    for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_down(best, off, 64);
+        const int oi = __shfl_down(bidx, off, 64);
+        if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+    }
+    if ((tid & 63) == 0) { sval[tid >> 6] = best; sidx[tid >> 6] = bidx; }
+    __syncthreads();
+    if (tid == 0) {
+        double bv = sval[0];
+        int bi = sidx[0];
+        for (int w = 1; w < GJ_THREADS / 64; ++w)
+            if (sval[w] > bv || (sval[w] == bv && sidx[w] < bi)) { bv = sval[w]; bi = sidx[w]; }
+        if (bi < k || bi >= n) bi = k;   // no finite pivot: keep the row (result is not finite)
+        s_p = bi;
+        perm[k] = bi;
+    }
+    __syncthreads();
+    const int p = s_p;
+    const cplx piv = A[(int64_t)p * n + k];
+    const cplx ipiv = crecip(piv);
+    for (int j = tid; j < n; j += GJ_THREADS) {
+        const cplx v = (j == k) ? mk(1.0, 0.0) : A[(int64_t)p * n + j];
+        prow[j] = cmul(v, ipiv);
+        rowk[j] = A[(int64_t)k * n + j];
+    }
+    for (int i = tid; i < n; i += GJ_THREADS) {
+        cplx v;
+        if (i == p) v = A[(int64_t)k * n + k];
+        else v = A[(int64_t)i * n + k];
+        pcol[i] = v;
+    }
+}
+
+// Step k, part 2: every element; reads only its own element and the buffers
+// of part 1, so the in-place update has no cross-workgroup hazard.
+__global__ void __launch_bounds__(256) k_gj_update(int n, int k, cplx* __restrict__ A,
+                                                   const cplx* __restrict__ prow,
+                                                   const cplx* __restrict__ pcol,
+                                                   const cplx* __restrict__ rowk,
+                                                   const int* __restrict__ perm) {
+    const int j = blockIdx.x * BX + threadIdx.x;
+    const int i = blockIdx.y * BZ + threadIdx.y;
+    if (i >= n || j >= n) return;
+    const int p = perm[k];
+    const int64_t e = (int64_t)i * n + j;
+    if (i == k) {
+        A[e] = prow[j];
+        return;
+    }
+    cplx src = (i == p) ? rowk[j] : A[e];
+    if (j == k) src = mk(0.0, 0.0);
+    A[e] = csub(src, cmul(pcol[i], prow[j]));
+}
+
+// Undo the row interchanges as column interchanges, in reverse order.
+__global__ void __launch_bounds__(256) k_gj_unscramble(int n, cplx* __restrict__ A,
+                                                       const int* __restrict__ perm) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cplx* row = A + (int64_t)i * n;
+    for (int k = n - 1; k >= 0; --k) {
+        const int p = perm[k];
+        if (p != k) {
+            const cplx t = row[k];
+            row[k] = row[p];
+            row[p] = t;
+        }
+    }
+}
+
+// y = A x: one 256-thread workgroup per row, fixed-order reduction.
+__global__ void __launch_bounds__(256) k_dense_gemv(int n, const cplx* __restrict__ A,
+                                                    const cplx* __restrict__ x,
+                                                    cplx* __restrict__ y) {
+    __shared__ cplx sh[4];
+    const int i = blockIdx.x;
+    const int tid = threadIdx.x;
+    const cplx* row = A + (int64_t)i * n;
+    cplx acc = mk(0.0, 0.0);
+    for (int j = tid; j < n; j += 256) acc = cadd(acc, cmul(row[j], x[j]));
+    for (int off = 32; off > 0; off >>= 1) {
+        acc.x += __shfl_down(acc.x, off, 64);
+        acc.y += __shfl_down(acc.y, off, 64);
+    }
+    if ((tid & 63) == 0) sh[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) y[i] = cadd(cadd(sh[0], sh[1]), cadd(sh[2], sh[3]));
+}
+
+}  // namespace
+
+hipError_t launch_restrict(int nzf, int nxf, int hz, int hx, const cplx* rf, int nzc, int nxc,
+                           cplx* bc, hipStream_t s) {
+    const double scale = 1.0 / (double)((hz ? 2 : 1) * (hx ? 2 : 1));
+    hipLaunchKernelGGL(k_restrict, grid2(nzc, nxc), dim3(BX, BZ), 0, s, nzf, nxf, hz, hx, rf,
+                       nzc, nxc, bc, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_add(int nzf, int nxf, int hz, int hx, const cplx* ec, int nzc,
+                              int nxc, cplx* xf, hipStream_t s) {
+    hipLaunchKernelGGL(k_prolong_add, grid2(nzf, nxf), dim3(BX, BZ), 0, s, nzf, nxf, hz, hx, ec,
+                       nzc, nxc, xf);
+    return hipGetLastError();
+}
+
+hipError_t launch_galerkin_from_fine(const FineOp& fine, int hz, int hx, int nzc, int nxc,
+                                     cplx* Cc, hipStream_t s) {
+    hipLaunchKernelGGL(k_galerkin_from_fine, grid2(nzc, nxc), dim3(BX, BZ), 0, s, fine, hz, hx,
+                       nzc, nxc, Cc);
+    return hipGetLastError();
+}
+
+hipError_t launch_galerkin_from_coarse(const CoarseOp& fine, int hz, int hx, int nzc, int nxc,
+                                       cplx* Cc, hipStream_t s) {
+    hipLaunchKernelGGL(k_galerkin_from_coarse, grid2(nzc, nxc), dim3(BX, BZ), 0, s, fine, hz, hx,
+                       nzc, nxc, Cc);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_from_fine(const FineOp& op, cplx* A, hipStream_t s) {
+    const size_t n = (size_t)op.nz * op.nx;
+    hipError_t e = hipMemsetAsync(A, 0, n * n * sizeof(cplx), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dense_from_fine, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_from_coarse(const CoarseOp& op, cplx* A, hipStream_t s) {
+    const size_t n = (size_t)op.nz * op.nx;
+    hipError_t e = hipMemsetAsync(A, 0, n * n * sizeof(cplx), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dense_from_coarse, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, A);
+    return hipGetLastError();
+}
+
+hipError_t dense_invert(int n, cplx* A, cplx* scratch, int* perm, hipStream_t s) {
+    cplx* prow = scratch;
+    cplx* pcol = scratch + n;
+    cplx* rowk = scratch + 2 * n;
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(GJ_THREADS), 0, s, n, k, A, prow, pcol,
+                           rowk, perm);
+        hipLaunchKernelGGL(k_gj_update, grid2(n, n), dim3(BX, BZ), 0, s, n, k, A, prow, pcol,
+                           rowk, perm);
+    }
+    hipLaunchKernelGGL(k_gj_unscramble, dim3((n + 255) / 256), dim3(256), 0, s, n, A, perm);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense_gemv(int n, const cplx* A, const cplx* x, cplx* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_dense_gemv, dim3(n), dim3(256), 0, s, n, A, x, y);
+    return hipGetLastError();
+}
+
+}  // namespace hh

@@ -1,0 +1,74 @@
+// Exact 1D shifted-Laplace solve z = M^{-1} d (Eq. 6-7 in 1D, where M is
+// tridiagonal) by parallel cyclic reduction in one workgroup.
+//
+// Row i of M: sub a_i = -1/h^2 (i > 0), super c_i = -1/h^2 (i < n-1), diagonal
+// from the shared operator row. Step s (s = 1, 2, 4, ...) eliminates the
+// couplings to rows i-s and i+s:
+//   k1 = a_i / b_{i-s},  k2 = c_i / b_{i+s}
+//   a_i' = -k1 a_{i-s},  c_i' = -k2 c_{i+s}
+//   b_i' = b_i - k1 c_{i-s} - k2 a_{i+s},  d_i' = d_i - k1 d_{i-s} - k2 d_{i+s}
+// until s >= n, when every row reads b_i z_i = d_i. With Im M > 0 (beta2 > 0)
+// every principal submatrix is nonsingular, so no pivoting is needed.
+// The whole system lives in LDS (4 complex arrays of n entries).
+#include "hh_internal.h"
+
+namespace hh {
+
+namespace {
+
+constexpr int PCR_THREADS = 1024;
+constexpr int PCR_MAXN = 1024;
+
+__global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOp op, const cplx* __restrict__ d_in,
+                                                     cplx* __restrict__ x_out) {
+    __shared__ cplx sa[PCR_MAXN], sb[PCR_MAXN], sc[PCR_MAXN], sd[PCR_MAXN];
+    const int n = op.nx;
+    const int i = threadIdx.x;
+    if (i < n) {
+        const Coef5 c = fine_coefs(op, 0, i, op.m2[i]);
+        sa[i] = mk(i > 0 ? -c.cx : 0.0, 0.0);
+        sc[i] = mk(i < n - 1 ? -c.cx : 0.0, 0.0);
+        sb[i] = c.diag;
+        sd[i] = d_in[i];
+    }
+    __syncthreads();
+    for (int s = 1; s < n; s <<= 1) {
+        cplx na = mk(0.0, 0.0), nb = mk(0.0, 0.0), nc = mk(0.0, 0.0), nd = mk(0.0, 0.0);
+        if (i < n) {
+            const cplx ai = sa[i], ci = sc[i];
+            nb = sb[i];
+            nd = sd[i];
+            if (i - s >= 0) {
+                const cplx k1 = cdiv(ai, sb[i - s]);
+                na = csub(mk(0.0, 0.0), cmul(k1, sa[i - s]));
+                nb = csub(nb, cmul(k1, sc[i - s]));
+                nd = csub(nd, cmul(k1, sd[i - s]));
+            }
+            if (i + s < n) {
+                const cplx k2 = cdiv(ci, sb[i + s]);
+                nc = csub(mk(0.0, 0.0), cmul(k2, sc[i + s]));
+                nb = csub(nb, cmul(k2, sa[i + s]));
+                nd = csub(nd, cmul(k2, sd[i + s]));
+            }
+        }
+        __syncthreads();
+        if (i < n) {
+            sa[i] = na;
+            sb[i] = nb;
+            sc[i] = nc;
+            sd[i] = nd;
+        }
+        __syncthreads();
+    }
+    if (i < n) x_out[i] = cdiv(sd[i], sb[i]);
+}
+
+}  // namespace
+
+hipError_t launch_pcr_solve(const FineOp& op, const cplx* d, cplx* x, hipStream_t s) {
+    if (op.ndim != 1 || op.nx > PCR_MAXN) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pcr, dim3(1), dim3(PCR_THREADS), 0, s, op, d, x);
+    return hipGetLastError();
+}
+
+}  // namespace hh

@@ -1,0 +1,311 @@
+"""ctypes binding of the C ABI in ``include/helmholtz.h`` (argument marshalling
+only: every step of the solve runs in the library's HIP kernels).
+
+Device arrays are PyTorch CUDA (HIP) tensors: slowness ``float64``, fields
+``complex128`` (interleaved), grid-shaped ``(n,)`` or ``(nz, nx)``. The library
+must be built (``python -m paper_1712_08740_amd.build``); importing this module
+without it raises ``ImportError`` -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhh.so")
+
+HH_OK = 0
+HH_NOT_CONVERGED = 1
+HH_EINVAL = -1
+HH_ENOMEM = -2
+HH_EDEVICE = -3
+HH_ENUMERIC = -4
+HH_EUNSUPPORTED = -5
+HH_NO_PRECOND = 1
+HH_MAX_COARSE = 4096
+HH_MAX_1D = 1024
+HH_KERNEL_NONE = 0
+HH_KERNEL_STENCIL = 1
+HH_KERNEL_JACOBI = 2
+HH_KERNEL_DOT = 3
+HH_KERNEL_AXPY = 4
+HH_KERNEL_GEMV = 5
+HH_KERNEL_PCR = 6
+
+EXPORTED = [
+    "hh_create_problem", "hh_set_shift", "hh_workspace_bytes", "hh_solve",
+    "hh_destroy_problem", "hh_status_string", "hh_last_error", "hh_num_levels",
+    "hh_level_info", "hh_apply_operator", "hh_apply_level_operator", "hh_apply_precond",
+    "hh_orthogonalize_scratch_bytes", "hh_orthogonalize", "hh_kernel_timer_start",
+    "hh_kernel_timer_read",
+]
+
+KERNEL_IDS = {"none": HH_KERNEL_NONE, "stencil": HH_KERNEL_STENCIL, "jacobi": HH_KERNEL_JACOBI,
+              "dot": HH_KERNEL_DOT, "axpy": HH_KERNEL_AXPY, "gemv": HH_KERNEL_GEMV,
+              "pcr": HH_KERNEL_PCR}
+
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_size_p = ctypes.POINTER(ctypes.c_size_t)
+_c_i64_p = ctypes.POINTER(ctypes.c_int64)
+_vp = ctypes.c_void_p
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with "
+                          "`python -m paper_1712_08740_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "hh_create_problem": (ctypes.c_int, [_vp, ctypes.c_int, _c_i64_p, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, _vp,
+                                             ctypes.POINTER(_vp)]),
+        "hh_set_shift": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double]),
+        "hh_workspace_bytes": (ctypes.c_int, [_vp, ctypes.c_int, _c_size_p]),
+        "hh_solve": (ctypes.c_int, [_vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_uint, _vp, ctypes.c_size_t, _vp, _c_int_p,
+                                    _c_double_p, _c_double_p, ctypes.c_int, _c_int_p, _vp]),
+        "hh_destroy_problem": (ctypes.c_int, [_vp]),
+        "hh_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "hh_last_error": (ctypes.c_char_p, []),
+        "hh_num_levels": (ctypes.c_int, [_vp, _c_int_p]),
+        "hh_level_info": (ctypes.c_int, [_vp, ctypes.c_int, _c_i64_p, _c_double_p]),
+        "hh_apply_operator": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
+        "hh_apply_level_operator": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
+        "hh_apply_precond": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+        "hh_orthogonalize_scratch_bytes": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int,
+                                                          _c_size_p]),
+        "hh_orthogonalize": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int, _vp, _vp,
+                                            ctypes.c_size_t, _c_double_p, _c_double_p, _vp]),
+        "hh_kernel_timer_start": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "hh_kernel_timer_read": (ctypes.c_int, [_vp, _c_i64_p, _c_double_p, _c_double_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+_lib = _load()
+
+
+class HHError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.hh_last_error().decode() or _lib.hh_status_string(status).decode()
+        super().__init__(f"{where}: status {status} ({_lib.hh_status_string(status).decode()}): {msg}")
+
+
+def _check(status: int, where: str) -> int:
+    if status < 0:
+        raise HHError(status, where)
+    return status
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev_tensor(t: torch.Tensor, dtype, shape, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+@dataclasses.dataclass
+class SolveResult:
+    u: torch.Tensor
+    iterations: int
+    true_rel_res: float
+    history: np.ndarray
+    status: int
+
+    @property
+    def converged(self) -> bool:
+        return self.status == HH_OK
+
+
+class Problem:
+    """``hh_create_problem`` + ``hh_set_shift`` for one slowness model and frequency."""
+
+    def __init__(self, m: torch.Tensor, omega: float, alpha: float, h: float,
+                 beta=(1.0, 0.5), stream=None):
+        if not isinstance(m, torch.Tensor) or not m.is_cuda or m.dtype != torch.float64:
+            raise ValueError("m must be a float64 CUDA tensor")
+        if m.dim() not in (1, 2):
+            raise ValueError("m must be 1D or 2D")
+        m = m.contiguous()
+        self.shape = tuple(m.shape)
+        self.device = m.device
+        self.ndim = m.dim()
+        self._handle = _vp()
+        shape = (ctypes.c_int64 * 2)(*self.shape)
+        self._setup_stream = stream if stream is not None else torch.cuda.current_stream()
+        _check(_lib.hh_create_problem(_vp(m.data_ptr()), m.dim(), shape, float(omega),
+                                      float(alpha), float(h),
+                                      _vp(self._setup_stream.cuda_stream),
+                                      ctypes.byref(self._handle)), "hh_create_problem")
+        self._ws = {}
+        if tuple(beta) != (1.0, 0.5):
+            self.set_shift(*beta)
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_handle", None) and self._handle.value:
+            _lib.hh_destroy_problem(self._handle)
+            self._handle = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- set-up -------------------------------------------------------------
+    def set_shift(self, beta1: float, beta2: float):
+        _check(_lib.hh_set_shift(self._handle, float(beta1), float(beta2)), "hh_set_shift")
+
+    def workspace_bytes(self, restart: int) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib.hh_workspace_bytes(self._handle, int(restart), ctypes.byref(n)),
+               "hh_workspace_bytes")
+        return n.value
+
+    def workspace(self, restart: int) -> torch.Tensor:
+        ws = self._ws.get(restart)
+        if ws is None:
+            ws = torch.empty(self.workspace_bytes(restart), dtype=torch.uint8, device=self.device)
+            self._ws[restart] = ws
+        return ws
+
+    @property
+    def num_levels(self) -> int:
+        n = ctypes.c_int()
+        _check(_lib.hh_num_levels(self._handle, ctypes.byref(n)), "hh_num_levels")
+        return n.value
+
+    def level_info(self, level: int):
+        shape = (ctypes.c_int64 * 2)()
+        spacing = (ctypes.c_double * 2)()
+        _check(_lib.hh_level_info(self._handle, int(level), shape, spacing), "hh_level_info")
+        return (int(shape[0]), int(shape[1])), (float(spacing[0]), float(spacing[1]))
+
+    def level_shape(self, level: int):
+        (nz, nx), _ = self.level_info(level)
+        return (nx,) if self.ndim == 1 else (nz, nx)
+
+    # -- kernel timing ------------------------------------------------------
+    def kernel_timer_start(self, kernel: str):
+        """Bracket every launch of one kernel class in later solves with HIP events."""
+        _check(_lib.hh_kernel_timer_start(self._handle, KERNEL_IDS[kernel]),
+               "hh_kernel_timer_start")
+
+    def kernel_timer_read(self):
+        """``(launches, total_ms, total_algorithmic_bytes)`` since the last start."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(_lib.hh_kernel_timer_read(self._handle, ctypes.byref(n), ctypes.byref(ms),
+                                         ctypes.byref(by)), "hh_kernel_timer_read")
+        return n.value, ms.value, by.value
+
+    # -- steps --------------------------------------------------------------
+    def apply_operator(self, x: torch.Tensor, which: str = "H", y=None, stream=None):
+        _dev_tensor(x, torch.complex128, self.shape, "x")
+        y = torch.empty_like(x) if y is None else _dev_tensor(y, torch.complex128, self.shape, "y")
+        w = {"H": 0, "M": 1}[which]
+        _check(_lib.hh_apply_operator(self._handle, w, _vp(x.data_ptr()), _vp(y.data_ptr()),
+                                      _vp(_stream_ptr(stream))), "hh_apply_operator")
+        return y
+
+    def apply_level_operator(self, level: int, x: torch.Tensor, stream=None):
+        shape = self.level_shape(level)
+        _dev_tensor(x, torch.complex128, shape, "x")
+        y = torch.empty_like(x)
+        _check(_lib.hh_apply_level_operator(self._handle, int(level), _vp(x.data_ptr()),
+                                            _vp(y.data_ptr()), _vp(_stream_ptr(stream))),
+               "hh_apply_level_operator")
+        return y
+
+    def apply_precond(self, v: torch.Tensor, stream=None):
+        _dev_tensor(v, torch.complex128, self.shape, "v")
+        z = torch.empty_like(v)
+        ws = self.workspace(1)
+        _check(_lib.hh_apply_precond(self._handle, _vp(v.data_ptr()), _vp(z.data_ptr()),
+                                     _vp(ws.data_ptr()), ws.numel(), _vp(_stream_ptr(stream))),
+               "hh_apply_precond")
+        return z
+
+    def solve(self, f: torch.Tensor, tol: float = 1e-6, restart: int = 30,
+              max_iters: int = 2000, no_precond: bool = False, u: Optional[torch.Tensor] = None,
+              workspace: Optional[torch.Tensor] = None, stream=None,
+              hist_cap: Optional[int] = None) -> SolveResult:
+        _dev_tensor(f, torch.complex128, self.shape, "f")
+        if u is None:
+            u = torch.empty_like(f)
+        else:
+            _dev_tensor(u, torch.complex128, self.shape, "u")
+        ws = workspace if workspace is not None else self.workspace(restart)
+        need = self.workspace_bytes(restart)
+        if ws.numel() * ws.element_size() < need:
+            raise ValueError(f"workspace needs {need} bytes")
+        cap = (max_iters + 1) if hist_cap is None else int(hist_cap)
+        hist = np.zeros(max(cap, 1), dtype=np.float64)
+        its = ctypes.c_int()
+        rel = ctypes.c_double()
+        hlen = ctypes.c_int()
+        flags = HH_NO_PRECOND if no_precond else 0
+        st = _check(_lib.hh_solve(self._handle, _vp(f.data_ptr()), float(tol), int(restart),
+                                  int(max_iters), flags, _vp(ws.data_ptr()),
+                                  ws.numel() * ws.element_size(), _vp(u.data_ptr()),
+                                  ctypes.byref(its), ctypes.byref(rel),
+                                  hist.ctypes.data_as(_c_double_p), cap, ctypes.byref(hlen),
+                                  _vp(_stream_ptr(stream))), "hh_solve")
+        return SolveResult(u=u, iterations=its.value, true_rel_res=rel.value,
+                           history=hist[: min(hlen.value, cap)].copy(), status=st)
+
+
+def orthogonalize(V: torch.Tensor, w: torch.Tensor, stream=None):
+    """CGS2 step (``hh_orthogonalize``): ``V`` is ``(k, n)`` complex128 with
+    orthonormal rows, ``w`` ``(n,)`` is orthogonalised in place. Returns
+    ``(h, ||w||)`` with ``h`` the ``k`` projection coefficients (numpy)."""
+    if V.dim() != 2:
+        raise ValueError("V must be (k, n)")
+    k, n = V.shape
+    _dev_tensor(V, torch.complex128, (k, n), "V")
+    _dev_tensor(w, torch.complex128, (n,), "w")
+    need = ctypes.c_size_t()
+    _check(_lib.hh_orthogonalize_scratch_bytes(n, k, ctypes.byref(need)),
+           "hh_orthogonalize_scratch_bytes")
+    scratch = torch.empty(need.value, dtype=torch.uint8, device=V.device)
+    h = np.zeros(2 * k, dtype=np.float64)
+    nrm = ctypes.c_double()
+    _check(_lib.hh_orthogonalize(_vp(V.data_ptr()), n, k, _vp(w.data_ptr()),
+                                 _vp(scratch.data_ptr()), need.value,
+                                 h.ctypes.data_as(_c_double_p), ctypes.byref(nrm),
+                                 _vp(_stream_ptr(stream))), "hh_orthogonalize")
+    return h.view(np.complex128), nrm.value
+
+
+def status_string(status: int) -> str:
+    return _lib.hh_status_string(int(status)).decode()

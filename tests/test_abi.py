@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every entry point that
+include/helmholtz.h declares; host-side argument checks that run before any
+device work. CPU only (no kernel is launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "helmholtz.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hh_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1712_08740_amd import hh
+    return hh
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib._lib, n), n
+    assert sorted(lib.EXPORTED) == names
+
+
+def test_constants_match_header(lib):
+    src = open(HEADER).read()
+    for name in ("HH_MAX_COARSE", "HH_MAX_1D", "HH_NO_PRECOND"):
+        v = int(re.search(rf"#define {name} (\d+)", src).group(1))
+        assert getattr(lib, name) == v
+    for name, val in re.findall(r"(HH_[A-Z_]+)\s*=\s*(-?\d+)", src):
+        assert getattr(lib, name) == int(val), name
+
+
+def test_status_strings(lib):
+    for st in (0, 1, -1, -2, -3, -4, -5, 99):
+        assert isinstance(lib.status_string(st), str) and lib.status_string(st)
+
+
+def test_create_rejects_bad_arguments_before_device_work(lib):
+    L = lib._lib
+    out = ctypes.c_void_p()
+    shape = (ctypes.c_int64 * 2)(9, 11)
+    fake = ctypes.c_void_p(0x1000)     # never dereferenced: validation fails first
+    assert L.hh_create_problem(fake, 3, shape, 60.0, 0.01, 10.0, None, ctypes.byref(out)) == -1
+    assert L.hh_create_problem(None, 2, shape, 60.0, 0.01, 10.0, None, ctypes.byref(out)) == -1
+    assert L.hh_create_problem(fake, 2, shape, -1.0, 0.01, 10.0, None, ctypes.byref(out)) == -1
+    assert L.hh_create_problem(fake, 2, shape, 60.0, -0.1, 10.0, None, ctypes.byref(out)) == -1
+    assert L.hh_create_problem(fake, 2, shape, 60.0, 0.01, 0.0, None, ctypes.byref(out)) == -1
+    small = (ctypes.c_int64 * 2)(2, 11)
+    assert L.hh_create_problem(fake, 2, small, 60.0, 0.01, 10.0, None, ctypes.byref(out)) == -1
+    big1d = (ctypes.c_int64 * 2)(lib.HH_MAX_1D + 1, 0)
+    assert L.hh_create_problem(fake, 1, big1d, 60.0, 0.01, 10.0, None, ctypes.byref(out)) == -5
+    assert "1D" in L.hh_last_error().decode()
+    assert out.value is None
+
+
+def test_null_handles_rejected(lib):
+    L = lib._lib
+    n = ctypes.c_size_t()
+    assert L.hh_workspace_bytes(None, 30, ctypes.byref(n)) == -1
+    assert L.hh_set_shift(None, 1.0, 0.5) == -1
+    assert L.hh_destroy_problem(None) == 0
+    assert L.hh_orthogonalize_scratch_bytes(1000, 0, ctypes.byref(n)) == -1
+    assert L.hh_orthogonalize_scratch_bytes(1000, 4, ctypes.byref(n)) == 0 and n.value > 0
