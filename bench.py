@@ -38,8 +38,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grf_401x201",
                     choices=["grf_401x201", "layered_1d_well"])
-    ap.add_argument("--kernel", default="dot",
-                    help="kernel class for the roofline figure (dot, axpy, stencil, jacobi, gemv, pcr)")
+    ap.add_argument("--kernel", default="axpy_dot",
+                    help="kernel class for the roofline figure (apply_dot, axpy_dot, axpy_norm, "
+                         "presmooth, postsmooth, gemv, pcr)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample")

@@ -173,20 +173,22 @@ int hh_orthogonalize(const void* V_dev, int64_t n, int k, void* w_dev, void* scr
 
 /* ---------------------------------------------------------------------------
  * Kernel timing (measurement support). After hh_kernel_timer_start(p, id),
- * every launch of that kernel class inside hh_solve on this handle is
- * bracketed by a pair of HIP events recorded on the solve's stream; the
- * elapsed times and the algorithmic bytes of each launch (the byte model of
- * the kernel: data it must read and write once) are accumulated until read.
- * id = HH_KERNEL_NONE switches timing off.
+ * every launch of that kernel class inside hh_solve on this handle is made
+ * with hipExtLaunchKernelGGL and a pair of HIP events that the runtime stamps
+ * at the dispatch's own start and end, on the solve's stream. Durations and
+ * the algorithmic bytes of each launch (the kernel's byte model: the data it
+ * must read and write once; k = number of basis vectors touched) are summed
+ * over the launches that did work until read. HH_KERNEL_NONE switches it off.
  * ------------------------------------------------------------------------- */
 enum hh_kernel_id {
-    HH_KERNEL_NONE    = 0,
-    HH_KERNEL_STENCIL = 1,  /* w = H z, fine grid: 40 B/node (z, m^2 in; w out)          */
-    HH_KERNEL_JACOBI  = 2,  /* fine-grid Jacobi sweep: 56 B/node (b, x, m^2 in; x out)   */
-    HH_KERNEL_DOT     = 3,  /* CGS2 projections V^H w: (k+1)*16 B/node                    */
-    HH_KERNEL_AXPY    = 4,  /* CGS2 update w -= V h: (k+2)*16 B/node                      */
-    HH_KERNEL_GEMV    = 5,  /* coarsest dense inverse times vector: (n^2+2n)*16 B         */
-    HH_KERNEL_PCR     = 6   /* 1D tridiagonal solve: 40 B/node                            */
+    HH_KERNEL_NONE       = 0,
+    HH_KERNEL_APPLY_DOT  = 1,  /* w = H z and the first projections V^H w: (40 + 16k) B/node */
+    HH_KERNEL_AXPY_DOT   = 2,  /* w -= V h and the second projections: (k + 2) * 16 B/node   */
+    HH_KERNEL_AXPY_NORM  = 3,  /* w -= V h and ||w||^2: (k + 2) * 16 B/node                  */
+    HH_KERNEL_PRESMOOTH  = 4,  /* fine-grid two Jacobi sweeps from zero: 56 B/node           */
+    HH_KERNEL_POSTSMOOTH = 5,  /* fine-grid last Jacobi sweep: 56 B/node                     */
+    HH_KERNEL_GEMV       = 6,  /* coarsest dense inverse times vector: (n^2 + 2n) * 16 B     */
+    HH_KERNEL_PCR        = 7   /* 1D tridiagonal solve: 56 B/node                            */
 };
 int hh_kernel_timer_start(hh_problem p, int kernel_id);
 int hh_kernel_timer_read(hh_problem p, int64_t* launches, double* total_ms,

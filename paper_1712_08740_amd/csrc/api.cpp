@@ -1,15 +1,27 @@
 // C ABI of the solver (include/helmholtz.h): problem set-up, the
 // shifted-Laplace preconditioner hierarchy, and the right-preconditioned
-// flexible GMRES driver (Eq. 5-7). The host only sequences kernels and reads
-// back the scalars that decide convergence; every arithmetic step runs on
-// the device.
+// flexible GMRES driver (Eq. 5-7).
+//
+// Control flow of a solve lives on the device: the Givens kernel decides when
+// a restart cycle stops, the cycle-start kernel decides when the solve is
+// done, and every Arnoldi-step kernel returns at once when its cycle is
+// closed. The host enqueues work a bounded number of steps ahead and paces
+// itself on a progress record that the device writes into pinned host memory;
+// it never waits on the stream inside the iteration.
 #include "helmholtz.h"
 #include "hh_internal.h"
 
+#include <immintrin.h>
+
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
+
+namespace hh {
+thread_local LaunchEvents g_launch_events;
+}
 
 using namespace hh;
 
@@ -38,6 +50,8 @@ int fail(int code, const std::string& msg) {
 
 constexpr double kJacobiWeight = 0.8;
 constexpr int kMaxRestart = 1024;
+constexpr int kLookahead = 2;          // Arnoldi steps enqueued ahead of the device
+constexpr double kStallSeconds = 120.0;
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -47,6 +61,11 @@ struct LevelData {
     int halve_z = 0, halve_x = 0;   // halving flags towards the next coarser level
     cplx* C = nullptr;              // 9-point Galerkin operator (levels >= 1)
     int64_t size() const { return (int64_t)nz * nx; }
+};
+
+struct PendingTime {
+    int cycle, j;                   // Arnoldi step that made the launch
+    double bytes;
 };
 
 }  // namespace
@@ -64,19 +83,22 @@ struct hh_problem_s {
     int nc = 0;
     cplx* gj_scratch = nullptr;
     int* gj_perm = nullptr;
+    cplx* fin_partial = nullptr;    // block sums for the finiteness check of cinv
     int* dflag = nullptr;           // device scratch for checks
     double* dpartial = nullptr;
-    GivensState* st_host = nullptr; // pinned
     cplx* nrm2_host = nullptr;      // pinned
+    HostRecord* rec = nullptr;      // pinned, written by the device
+    double* hist = nullptr;         // pinned, written by the device
+    int hist_cap = 0;
     hipStream_t stream = nullptr;
-    // per-launch event timing of one kernel class (hh_kernel_timer_*)
+    // dispatch-stamped timing of one kernel class (hh_kernel_timer_*)
     struct {
         int kid = HH_KERNEL_NONE;
         std::vector<hipEvent_t> pool;
-        int used = 0;
-        std::vector<double> pending_bytes;
+        std::vector<PendingTime> pending;
         int64_t launches = 0;
         double total_ms = 0.0, total_bytes = 0.0;
+        int cycle = 0, j = 0;       // step being enqueued
     } kt;
 };
 
@@ -111,53 +133,56 @@ CoarseOp coarse_op(const LevelData& L) {
 // ---------------------------------------------------------------------------
 // kernel timer
 // ---------------------------------------------------------------------------
-int kt_begin(hh_problem_s* p, int kid, hipStream_t s) {
-    if (p->kt.kid != kid) return HH_OK;
-    while ((int)p->kt.pool.size() < p->kt.used + 2) {
+bool kt_arm(hh_problem_s* p, int kid) {
+    if (p->kt.kid == HH_KERNEL_NONE || p->kt.kid != kid) return false;
+    const size_t used = 2 * p->kt.pending.size();
+    while (p->kt.pool.size() < used + 2) {
         hipEvent_t e;
-        HIPCHK(hipEventCreate(&e));
+        if (hipEventCreate(&e) != hipSuccess) return false;
         p->kt.pool.push_back(e);
     }
-    HIPCHK(hipEventRecord(p->kt.pool[p->kt.used], s));
-    return HH_OK;
+    g_launch_events.start = p->kt.pool[used];
+    g_launch_events.stop = p->kt.pool[used + 1];
+    return true;
 }
 
-int kt_end(hh_problem_s* p, int kid, hipStream_t s, double bytes) {
-    if (p->kt.kid != kid) return HH_OK;
-    HIPCHK(hipEventRecord(p->kt.pool[p->kt.used + 1], s));
-    p->kt.pending_bytes.push_back(bytes);
-    p->kt.used += 2;
-    return HH_OK;
+void kt_done(hh_problem_s* p, double bytes) {
+    p->kt.pending.push_back(PendingTime{p->kt.cycle, p->kt.j, bytes});
 }
 
-// after a stream synchronisation: fold the completed event pairs in
-int kt_harvest(hh_problem_s* p) {
-    for (int i = 0; i < p->kt.used / 2; ++i) {
+// After the stream is idle: keep the launches of steps that did work.
+int kt_harvest(hh_problem_s* p, const std::vector<int>& executed) {
+    for (size_t i = 0; i < p->kt.pending.size(); ++i) {
+        const PendingTime& t = p->kt.pending[i];
+        const bool did_work = t.cycle >= 1 && t.cycle <= (int)executed.size() &&
+                              t.j < executed[t.cycle - 1];
+        if (!did_work) continue;
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, p->kt.pool[2 * i], p->kt.pool[2 * i + 1]));
         p->kt.total_ms += ms;
-        p->kt.total_bytes += p->kt.pending_bytes[i];
+        p->kt.total_bytes += t.bytes;
         p->kt.launches += 1;
     }
-    p->kt.used = 0;
-    p->kt.pending_bytes.clear();
+    p->kt.pending.clear();
     return HH_OK;
 }
 
-#define TIMED(KID, BYTES, EXPR)                     \
-    do {                                            \
-        CHK(kt_begin(p, (KID), s));                 \
-        HIPCHK(EXPR);                               \
-        CHK(kt_end(p, (KID), s, (double)(BYTES)));  \
+#define TIMED(KID, BYTES, EXPR)                      \
+    do {                                             \
+        const bool armed_ = kt_arm(p, (KID));        \
+        const hipError_t e2_ = (EXPR);               \
+        g_launch_events = LaunchEvents();            \
+        HIPCHK(e2_);                                 \
+        if (armed_) kt_done(p, (double)(BYTES));     \
     } while (0)
 
 // ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t V, Z, b, partial, h1, h2, nrm2, R, cs, sn, g, y, inv_beta, st, total;
-    std::vector<size_t> t, r, bc, ec;   // per level
-    int nb;
+    size_t V, Z, b, w, partial, h1, h2, R, cs, sn, g, y, st, total;
+    std::vector<size_t> t, bc, ec;   // per level
+    int nbA, nbN, nbmax;
 };
 
 Layout layout(const hh_problem_s* p, int m) {
@@ -173,37 +198,33 @@ Layout layout(const hh_problem_s* p, int m) {
     L.V = take((size_t)(m + 1) * N * c);
     L.Z = take((size_t)m * N * c);
     L.b = take(N * c);
+    L.w = take(N * c);
     const int nl = (int)p->levels.size();
     L.t.assign(nl, 0);
-    L.r.assign(nl, 0);
     L.bc.assign(nl, 0);
     L.ec.assign(nl, 0);
     if (p->ndim == 2) {
         for (int l = 0; l < nl; ++l) {
             const size_t n = (size_t)p->levels[l].size();
-            if (l < nl - 1) {
-                L.t[l] = take(n * c);
-                L.r[l] = take(n * c);
-            }
+            if (l < nl - 1) L.t[l] = take(n * c);
             if (l >= 1) {
                 L.bc[l] = take(n * c);
                 L.ec[l] = take(n * c);
             }
         }
     }
-    L.nb = reduce_blocks(p->N);
-    const int kmax = m + 1 > 1 ? m + 1 : 1;
-    L.partial = take((size_t)L.nb * kmax * c);
-    L.h1 = take((size_t)kmax * c);
-    L.h2 = take((size_t)kmax * c);
-    L.nrm2 = take(c);
+    L.nbA = apply_blocks(op_H(p));
+    L.nbN = node_blocks(p->N);
+    L.nbmax = L.nbA > L.nbN ? L.nbA : L.nbN;
+    L.partial = take((size_t)L.nbmax * (m + 1) * c);
+    L.h1 = take((size_t)(m + 1) * c);
+    L.h2 = take((size_t)(m + 1) * c);
     L.R = take((size_t)(m + 1) * m * c);
     L.cs = take((size_t)m * sizeof(double));
     L.sn = take((size_t)m * c);
     L.g = take((size_t)(m + 1) * c);
     L.y = take((size_t)m * c);
-    L.inv_beta = take(sizeof(double));
-    L.st = take(sizeof(GivensState));
+    L.st = take(sizeof(SolveState));
     L.total = off;
     return L;
 }
@@ -213,66 +234,74 @@ T* at(void* base, size_t off) {
     return reinterpret_cast<T*>(static_cast<char*>(base) + off);
 }
 
-// ||x||^2 into out[0].x
-int norm2_async(const cplx* x, int64_t n, cplx* partial, int nb, cplx* out, hipStream_t s) {
-    HIPCHK(launch_dot_partials(x, n, 1, x, partial, nb, s));
-    HIPCHK(launch_reduce_partials(partial, nb, 1, out, s));
-    return HH_OK;
-}
-
 // ---------------------------------------------------------------------------
 // preconditioner
 // ---------------------------------------------------------------------------
-// One V(2,2) cycle on level l: out = V(l, b). b and out are distinct.
-int vcycle(hh_problem_s* p, const Layout& L, void* ws, int l, const cplx* b, cplx* out,
-           hipStream_t s) {
+// One V(2,2) cycle on level l >= 1: ec_l = V(l, bc_l).
+int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* active,
+                  hipStream_t s) {
     const int nl = (int)p->levels.size();
-    const LevelData& lv = p->levels[l];
+    cplx* b = at<cplx>(ws, L.bc[l]);
+    cplx* x = at<cplx>(ws, L.ec[l]);
     if (l == nl - 1) {
         const double nc = p->nc;
         TIMED(HH_KERNEL_GEMV, (nc * nc + 2 * nc) * sizeof(cplx),
-              launch_dense_gemv(p->nc, p->cinv, b, out, s));
+              launch_vc_gemv(p->nc, p->cinv, b, x, active, s));
         return HH_OK;
     }
-    cplx* t = at<cplx>(ws, L.t[l]);
-    cplx* r = at<cplx>(ws, L.r[l]);
+    const LevelData& lv = p->levels[l];
     const LevelData& nx = p->levels[l + 1];
-    cplx* bc = at<cplx>(ws, L.bc[l + 1]);
-    cplx* ec = at<cplx>(ws, L.ec[l + 1]);
-    const double jac_bytes = 56.0 * (double)lv.size();
-    if (l == 0) {
-        const FineOp M = op_M(p);
-        HIPCHK(launch_fine_jacobi0(M, kJacobiWeight, b, t, s));
-        TIMED(HH_KERNEL_JACOBI, jac_bytes, launch_fine_jacobi(M, kJacobiWeight, b, t, out, s));
-        HIPCHK(launch_fine_residual(M, b, out, r, s));
-    } else {
-        const CoarseOp A = coarse_op(lv);
-        HIPCHK(launch_coarse_jacobi0(A, kJacobiWeight, b, t, s));
-        HIPCHK(launch_coarse_jacobi(A, kJacobiWeight, b, t, out, s));
-        HIPCHK(launch_coarse_residual(A, b, out, r, s));
-    }
-    HIPCHK(launch_restrict(lv.nz, lv.nx, lv.halve_z, lv.halve_x, r, nx.nz, nx.nx, bc, s));
-    CHK(vcycle(p, L, ws, l + 1, bc, ec, s));
-    HIPCHK(launch_prolong_add(lv.nz, lv.nx, lv.halve_z, lv.halve_x, ec, nx.nz, nx.nx, out, s));
-    if (l == 0) {
-        const FineOp M = op_M(p);
-        TIMED(HH_KERNEL_JACOBI, jac_bytes, launch_fine_jacobi(M, kJacobiWeight, b, out, t, s));
-        TIMED(HH_KERNEL_JACOBI, jac_bytes, launch_fine_jacobi(M, kJacobiWeight, b, t, out, s));
-    } else {
-        const CoarseOp A = coarse_op(lv);
-        HIPCHK(launch_coarse_jacobi(A, kJacobiWeight, b, out, t, s));
-        HIPCHK(launch_coarse_jacobi(A, kJacobiWeight, b, t, out, s));
-    }
+    const CoarseOp A = coarse_op(lv);
+    cplx* t = at<cplx>(ws, L.t[l]);
+    HIPCHK(launch_vc_coarse_presmooth(A, kJacobiWeight, b, x, active, s));
+    HIPCHK(launch_vc_coarse_resid_restrict(A, lv.halve_z, lv.halve_x, b, x, nx.nz, nx.nx,
+                                           at<cplx>(ws, L.bc[l + 1]), active, s));
+    CHK(vcycle_coarse(p, L, ws, l + 1, active, s));
+    HIPCHK(launch_vc_coarse_prolong_post1(A, kJacobiWeight, lv.halve_z, lv.halve_x, b, x,
+                                          at<cplx>(ws, L.ec[l + 1]), nx.nx, t, active, s));
+    HIPCHK(launch_vc_coarse_post2(A, kJacobiWeight, b, t, x, active, s));
     return HH_OK;
 }
 
-int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* v, cplx* z,
-            hipStream_t s) {
+// z = M^{-1} v. Inside a solve (st given) v = st->scale * src is also written
+// to vout (the normalised Krylov basis vector) and every kernel is predicated
+// on st->active; stand-alone (st == NULL) v = src.
+int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const SolveState* st,
+            cplx* vout, cplx* z, hipStream_t s) {
+    const double N = (double)p->N;
+    const double* scale = st ? &st->scale : nullptr;
+    const int* active = st ? &st->active : nullptr;
     if (p->ndim == 1) {
-        TIMED(HH_KERNEL_PCR, 40.0 * (double)p->N, launch_pcr_solve(op_M(p), v, z, s));
+        TIMED(HH_KERNEL_PCR, 56.0 * N, launch_pcr_norm(op_M(p), src, scale, vout, z, active, s));
         return HH_OK;
     }
-    return vcycle(p, L, ws, 0, v, z, s);
+    const int nl = (int)p->levels.size();
+    const FineOp M = op_M(p);
+    if (nl == 1) {   // the fine grid is the coarsest: dense inverse only
+        const cplx* b = src;
+        if (st) {
+            HIPCHK(launch_normalize_pred(src, st, vout, p->N, s));
+            b = vout;
+        }
+        const double nc = p->nc;
+        TIMED(HH_KERNEL_GEMV, (nc * nc + 2 * nc) * sizeof(cplx),
+              launch_vc_gemv(p->nc, p->cinv, b, z, active, s));
+        return HH_OK;
+    }
+    const LevelData& lv = p->levels[0];
+    const LevelData& nx = p->levels[1];
+    cplx* t = at<cplx>(ws, L.t[0]);
+    TIMED(HH_KERNEL_PRESMOOTH, 56.0 * N,
+          launch_vc_fine_presmooth(M, kJacobiWeight, src, scale, vout, z, active, s));
+    const cplx* b = vout ? vout : src;
+    HIPCHK(launch_vc_fine_resid_restrict(M, lv.halve_z, lv.halve_x, b, z, nx.nz, nx.nx,
+                                         at<cplx>(ws, L.bc[1]), active, s));
+    CHK(vcycle_coarse(p, L, ws, 1, active, s));
+    HIPCHK(launch_vc_fine_prolong_post1(M, kJacobiWeight, lv.halve_z, lv.halve_x, b, z,
+                                        at<cplx>(ws, L.ec[1]), nx.nx, t, active, s));
+    TIMED(HH_KERNEL_POSTSMOOTH, 56.0 * N,
+          launch_vc_fine_post2(M, kJacobiWeight, b, t, z, active, s));
+    return HH_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -327,6 +356,7 @@ int build_hierarchy(hh_problem_s* p) {
     HIPCHK(hipMalloc(&p->cinv, (size_t)nc * nc * sizeof(cplx)));
     HIPCHK(hipMalloc(&p->gj_scratch, 3 * (size_t)nc * sizeof(cplx)));
     HIPCHK(hipMalloc(&p->gj_perm, (size_t)nc * sizeof(int)));
+    HIPCHK(hipMalloc(&p->fin_partial, (size_t)node_blocks(nc * nc) * sizeof(cplx)));
     return HH_OK;
 }
 
@@ -349,13 +379,13 @@ int apply_shift(hh_problem_s* p) {
     else
         HIPCHK(launch_dense_from_coarse(coarse_op(p->levels.back()), p->cinv, s));
     HIPCHK(dense_invert(p->nc, p->cinv, p->gj_scratch, p->gj_perm, s));
-    // the inverse must be finite: ||cinv||^2 over the whole matrix
+    // the inverse must be finite: sum of |entries|^2
     const int64_t nn = (int64_t)p->nc * p->nc;
-    const int nb = reduce_blocks(nn);
-    cplx* partial = reinterpret_cast<cplx*>(p->dpartial);
-    std::vector<cplx> tmp(1);
-    cplx* out = partial + nb;
-    CHK(norm2_async(p->cinv, nn, partial, nb, out, s));
+    const int nb = node_blocks(nn);
+    cplx* partial = p->fin_partial;
+    cplx* out = reinterpret_cast<cplx*>(p->dpartial);
+    HIPCHK(launch_dot_blocks(p->cinv, nn, 1, p->cinv, partial, s));
+    HIPCHK(launch_reduce_pred(partial, nb, 1, out, nullptr, s));
     HIPCHK(hipMemcpyAsync(p->nrm2_host, out, sizeof(cplx), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (!std::isfinite(p->nrm2_host->x))
@@ -370,19 +400,81 @@ void destroy(hh_problem_s* p) {
     if (p->cinv) (void)hipFree(p->cinv);
     if (p->gj_scratch) (void)hipFree(p->gj_scratch);
     if (p->gj_perm) (void)hipFree(p->gj_perm);
+    if (p->fin_partial) (void)hipFree(p->fin_partial);
     if (p->dflag) (void)hipFree(p->dflag);
     if (p->dpartial) (void)hipFree(p->dpartial);
-    if (p->st_host) (void)hipHostFree(p->st_host);
     if (p->nrm2_host) (void)hipHostFree(p->nrm2_host);
+    if (p->rec) (void)hipHostFree(p->rec);
+    if (p->hist) (void)hipHostFree(p->hist);
     for (hipEvent_t e : p->kt.pool) (void)hipEventDestroy(e);
     delete p;
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
-int check_vec_args(const void* a, const char* name) {
+int check_ptr(const void* a, const char* name) {
     if (!a) return fail(HH_EINVAL, std::string(name) + " is NULL");
     return HH_OK;
+}
+
+// pinned, device-visible memory written by kernels and polled by the host
+int ensure_host_buffers(hh_problem_s* p, int max_iters) {
+    if (!p->rec)
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->rec), sizeof(HostRecord),
+                             hipHostMallocCoherent | hipHostMallocMapped));
+    if (p->hist_cap < max_iters + 1) {
+        if (p->hist) {
+            HIPCHK(hipHostFree(p->hist));
+            p->hist = nullptr;
+            p->hist_cap = 0;
+        }
+        const int cap = max_iters + 1 > 1024 ? max_iters + 1 : 1024;
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hist), (size_t)cap * sizeof(double),
+                             hipHostMallocCoherent | hipHostMallocMapped));
+        p->hist_cap = cap;
+    }
+    return HH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host pacing on the device-written record
+// ---------------------------------------------------------------------------
+struct RecView {
+    int done, cycles, jstep, stops;
+};
+
+RecView read_rec(const HostRecord* r) {
+    const volatile HostRecord* v = r;
+    RecView o;
+    o.stops = v->stops;
+    o.done = v->done;
+    o.cycles = v->cycles;
+    _mm_lfence();
+    o.jstep = v->jstep;
+    return o;
+}
+
+// Spin until pred(record) holds; fails when the stream drained without it
+// (lost progress), on a stream error, or after kStallSeconds.
+template <class Pred>
+int wait_for(const hh_problem_s* p, hipStream_t s, Pred pred) {
+    auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spin = 0;; ++spin) {
+        if (pred(read_rec(p->rec))) return HH_OK;
+        if ((spin & 1023) == 1023) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) {
+                if (pred(read_rec(p->rec))) return HH_OK;
+                return fail(HH_EDEVICE, "device stopped without reaching the awaited state");
+            }
+            if (q != hipErrorNotReady)
+                return fail(HH_EDEVICE, std::string("stream error: ") + hipGetErrorString(q));
+            const double el =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (el > kStallSeconds) return fail(HH_EDEVICE, "no progress for too long");
+        }
+        _mm_pause();
+    }
 }
 
 }  // namespace
@@ -417,6 +509,8 @@ int hh_create_problem(const double* m_dev, int ndim, const int64_t* shape, doubl
             return fail(HH_EINVAL, "every grid dimension must be in [3, 2^24]");
     if (ndim == 1 && shape[0] > HH_MAX_1D)
         return fail(HH_EUNSUPPORTED, "1D grids are limited to HH_MAX_1D nodes");
+    if (ndim == 2 && shape[0] * shape[1] > (int64_t(1) << 31))
+        return fail(HH_EUNSUPPORTED, "grids are limited to 2^31 nodes");
     if (!finite_pos(omega)) return fail(HH_EINVAL, "omega must be finite and > 0");
     if (!(std::isfinite(alpha) && alpha >= 0.0)) return fail(HH_EINVAL, "alpha must be >= 0");
     if (!finite_pos(h)) return fail(HH_EINVAL, "h must be finite and > 0");
@@ -434,13 +528,12 @@ int hh_create_problem(const double* m_dev, int ndim, const int64_t* shape, doubl
         destroy(p);
         return code;
     };
-    const int nb = reduce_blocks(p->N);
+    int nb = (int)((p->N + 2047) / 2048);
+    if (nb > 512) nb = 512;
     hipError_t e;
     if ((e = hipMalloc(&p->m2, p->N * sizeof(double))) != hipSuccess ||
         (e = hipMalloc(&p->dflag, sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&p->dpartial, 4096 * sizeof(cplx))) != hipSuccess ||
-        (e = hipHostMalloc(reinterpret_cast<void**>(&p->st_host), sizeof(GivensState))) !=
-            hipSuccess ||
         (e = hipHostMalloc(reinterpret_cast<void**>(&p->nrm2_host), 64 * sizeof(cplx))) !=
             hipSuccess)
         return bail(fail(e == hipErrorOutOfMemory ? HH_ENOMEM : HH_EDEVICE,
@@ -512,8 +605,8 @@ int hh_level_info(hh_problem p, int level, int64_t* shape2, double* spacing2) {
 int hh_apply_operator(hh_problem p, int which, const void* x_dev, void* y_dev, void* stream) {
     g_err.clear();
     if (!p) return fail(HH_EINVAL, "problem is NULL");
-    CHK(check_vec_args(x_dev, "x_dev"));
-    CHK(check_vec_args(y_dev, "y_dev"));
+    CHK(check_ptr(x_dev, "x_dev"));
+    CHK(check_ptr(y_dev, "y_dev"));
     if (x_dev == y_dev) return fail(HH_EINVAL, "x_dev and y_dev must be distinct");
     if (which != 0 && which != 1) return fail(HH_EINVAL, "which must be 0 (H) or 1 (M)");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -527,8 +620,8 @@ int hh_apply_level_operator(hh_problem p, int level, const void* x_dev, void* y_
                             void* stream) {
     g_err.clear();
     if (!p) return fail(HH_EINVAL, "problem is NULL");
-    CHK(check_vec_args(x_dev, "x_dev"));
-    CHK(check_vec_args(y_dev, "y_dev"));
+    CHK(check_ptr(x_dev, "x_dev"));
+    CHK(check_ptr(y_dev, "y_dev"));
     if (x_dev == y_dev) return fail(HH_EINVAL, "x_dev and y_dev must be distinct");
     if (level < 0 || level >= (int)p->levels.size()) return fail(HH_EINVAL, "level out of range");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -546,22 +639,22 @@ int hh_apply_precond(hh_problem p, const void* v_dev, void* z_dev, void* workspa
                      size_t workspace_bytes, void* stream) {
     g_err.clear();
     if (!p) return fail(HH_EINVAL, "problem is NULL");
-    CHK(check_vec_args(v_dev, "v_dev"));
-    CHK(check_vec_args(z_dev, "z_dev"));
-    CHK(check_vec_args(workspace_dev, "workspace_dev"));
+    CHK(check_ptr(v_dev, "v_dev"));
+    CHK(check_ptr(z_dev, "z_dev"));
+    CHK(check_ptr(workspace_dev, "workspace_dev"));
     if (v_dev == z_dev) return fail(HH_EINVAL, "v_dev and z_dev must be distinct");
     const Layout L = layout(p, 1);
     if (workspace_bytes < L.total) return fail(HH_EINVAL, "workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    CHK(precond(p, L, workspace_dev, static_cast<const cplx*>(v_dev), static_cast<cplx*>(z_dev),
-                s));
+    CHK(precond(p, L, workspace_dev, static_cast<const cplx*>(v_dev), nullptr, nullptr,
+                static_cast<cplx*>(z_dev), s));
     HIPCHK(hipStreamSynchronize(s));
     return HH_OK;
 }
 
 int hh_orthogonalize_scratch_bytes(int64_t n, int k, size_t* bytes) {
     if (!bytes || n < 1 || k < 1 || k > kMaxRestart + 1) return fail(HH_EINVAL, "bad argument");
-    const int nb = reduce_blocks(n);
+    const int nb = node_blocks(n);
     *bytes = align_up((size_t)nb * k * sizeof(cplx)) + 3 * align_up((size_t)k * sizeof(cplx));
     return HH_OK;
 }
@@ -575,20 +668,19 @@ int hh_orthogonalize(const void* V_dev, int64_t n, int k, void* w_dev, void* scr
         return fail(HH_EINVAL, "NULL argument");
     if (scratch_bytes < need) return fail(HH_EINVAL, "scratch too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int nb = reduce_blocks(n);
+    const int nb = node_blocks(n);
     cplx* partial = static_cast<cplx*>(scratch_dev);
     cplx* h1 = at<cplx>(scratch_dev, align_up((size_t)nb * k * sizeof(cplx)));
     cplx* h2 = h1 + align_up((size_t)k * sizeof(cplx)) / sizeof(cplx);
     cplx* nr = h2 + align_up((size_t)k * sizeof(cplx)) / sizeof(cplx);
     const cplx* V = static_cast<const cplx*>(V_dev);
     cplx* w = static_cast<cplx*>(w_dev);
-    HIPCHK(launch_dot_partials(V, n, k, w, partial, nb, s));
-    HIPCHK(launch_reduce_partials(partial, nb, k, h1, s));
-    HIPCHK(launch_multi_axpy(V, n, k, h1, w, s));
-    HIPCHK(launch_dot_partials(V, n, k, w, partial, nb, s));
-    HIPCHK(launch_reduce_partials(partial, nb, k, h2, s));
-    HIPCHK(launch_multi_axpy(V, n, k, h2, w, s));
-    CHK(norm2_async(w, n, partial, nb, nr, s));
+    HIPCHK(launch_dot_blocks(V, n, k, w, partial, s));
+    HIPCHK(launch_reduce_pred(partial, nb, k, h1, nullptr, s));
+    HIPCHK(launch_axpy_dot(V, n, k, h1, w, partial, nullptr, s));
+    HIPCHK(launch_reduce_pred(partial, nb, k, h2, nullptr, s));
+    HIPCHK(launch_axpy_norm(V, n, k, h2, w, partial, nullptr, s));
+    HIPCHK(launch_reduce_pred(partial, nb, 1, nr, nullptr, s));
     std::vector<cplx> a(k), b(k);
     cplx nrm;
     HIPCHK(hipMemcpyAsync(a.data(), h1, k * sizeof(cplx), hipMemcpyDeviceToHost, s));
@@ -609,12 +701,12 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
              int* hist_len, void* stream) {
     g_err.clear();
     if (!p) return fail(HH_EINVAL, "problem is NULL");
-    CHK(check_vec_args(f_dev, "f_dev"));
-    CHK(check_vec_args(u_dev, "u_dev"));
-    CHK(check_vec_args(workspace_dev, "workspace_dev"));
+    CHK(check_ptr(f_dev, "f_dev"));
+    CHK(check_ptr(u_dev, "u_dev"));
+    CHK(check_ptr(workspace_dev, "workspace_dev"));
     if (!(tol > 0.0 && tol < 1.0)) return fail(HH_EINVAL, "tol must be in (0, 1)");
     if (restart < 1 || restart > kMaxRestart) return fail(HH_EINVAL, "restart must be in [1, 1024]");
-    if (max_iters < 1) return fail(HH_EINVAL, "max_iters must be >= 1");
+    if (max_iters < 1 || max_iters > (1 << 28)) return fail(HH_EINVAL, "max_iters must be in [1, 2^28]");
     if (flags & ~HH_NO_PRECOND) return fail(HH_EINVAL, "unknown flag");
     if (hist_cap < 0 || (hist_cap > 0 && !hist_host)) return fail(HH_EINVAL, "bad history buffer");
     if (f_dev == u_dev) return fail(HH_EINVAL, "f_dev and u_dev must be distinct");
@@ -622,106 +714,103 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
     const Layout L = layout(p, m);
     if (workspace_bytes < L.total) return fail(HH_EINVAL, "workspace too small");
     const bool no_prec = (flags & HH_NO_PRECOND) != 0;
+    CHK(ensure_host_buffers(p, max_iters));
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     void* ws = workspace_dev;
     const int64_t N = p->N;
-    const size_t vbytes = (size_t)N * sizeof(cplx);
     cplx* V = at<cplx>(ws, L.V);
     cplx* Z = at<cplx>(ws, L.Z);
     cplx* b = at<cplx>(ws, L.b);
+    cplx* w = at<cplx>(ws, L.w);
     cplx* partial = at<cplx>(ws, L.partial);
     cplx* h1 = at<cplx>(ws, L.h1);
     cplx* h2 = at<cplx>(ws, L.h2);
-    cplx* nrm2 = at<cplx>(ws, L.nrm2);
     cplx* R = at<cplx>(ws, L.R);
     double* cs = at<double>(ws, L.cs);
     cplx* sn = at<cplx>(ws, L.sn);
     cplx* g = at<cplx>(ws, L.g);
     cplx* y = at<cplx>(ws, L.y);
-    double* inv_beta = at<double>(ws, L.inv_beta);
-    GivensState* st = at<GivensState>(ws, L.st);
+    SolveState* st = at<SolveState>(ws, L.st);
+    const int* active = &st->active;
     cplx* u = static_cast<cplx*>(u_dev);
     const FineOp H = op_H(p);
-    const int nb = L.nb;
+    double* dhist = nullptr;
+    HostRecord* drec = nullptr;
+    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&dhist), p->hist, 0));
+    HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&drec), p->rec, 0));
+    std::memset(p->rec, 0, sizeof(HostRecord));
+    p->kt.pending.clear();
 
-    std::vector<double> hist;
-    hist.push_back(1.0);
-    int it = 0;
-    int status = HH_OK;
-    double rel = 0.0;
-    auto finish = [&](int code) {
-        if (iterations) *iterations = it;
-        if (true_rel_res) *true_rel_res = rel;
-        if (hist_len) *hist_len = (int)hist.size();
-        for (int i = 0; i < (int)hist.size() && i < hist_cap; ++i) hist_host[i] = hist[i];
-        return code;
-    };
-
+    // prologue: b = W f, ||b||, u = 0
     HIPCHK(launch_weight_rhs(H, static_cast<const cplx*>(f_dev), b, s));
-    CHK(norm2_async(b, N, partial, nb, nrm2, s));
-    HIPCHK(hipMemcpyAsync(p->nrm2_host, nrm2, sizeof(cplx), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemsetAsync(u, 0, vbytes, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const double beta0 = std::sqrt(p->nrm2_host->x);
-    if (!std::isfinite(beta0)) return finish(fail(HH_ENUMERIC, "source is not finite"));
-    if (beta0 == 0.0) return finish(HH_OK);
+    HIPCHK(launch_dot_blocks(b, N, 1, b, partial, s));
+    HIPCHK(launch_solve_init(st, partial, L.nbN, m, max_iters, tol, drec, dhist, s));
+    HIPCHK(hipMemsetAsync(u, 0, (size_t)N * sizeof(cplx), s));
 
-    for (;;) {
-        // true residual r = b - H u into v_1
-        HIPCHK(launch_fine_residual(H, b, u, V, s));
-        CHK(norm2_async(V, N, partial, nb, nrm2, s));
-        HIPCHK(hipMemcpyAsync(p->nrm2_host, nrm2, sizeof(cplx), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        CHK(kt_harvest(p));
-        const double beta = std::sqrt(p->nrm2_host->x);
-        rel = beta / beta0;
-        if (!std::isfinite(rel)) return finish(fail(HH_ENUMERIC, "residual is not finite"));
-        if (rel <= tol) return finish(HH_OK);
-        if (it >= max_iters) return finish(HH_NOT_CONVERGED);
-        HIPCHK(launch_cycle_init(st, m, beta0, nrm2, g, inv_beta, s));
-        HIPCHK(launch_scale_dev(V, inv_beta, V, N, s));
-        int k = 0;
+    std::vector<int> executed;   // Arnoldi steps that did work, per cycle
+    double last_est = 1.0;
+    for (int cycle = 1;; ++cycle) {
+        p->kt.cycle = cycle;
+        HIPCHK(launch_residual_norm(H, b, u, w, partial, &st->done, s));
+        HIPCHK(launch_cycle_start(st, partial, L.nbA, g, drec, s));
+        // close to convergence: learn whether this cycle opens before enqueuing it
+        if (last_est <= tol)
+            CHK(wait_for(p, s, [&](const RecView& r) { return r.done || r.cycles >= cycle; }));
+        bool closed = false;
         for (int j = 0; j < m; ++j) {
+            if (j >= kLookahead)
+                CHK(wait_for(p, s, [&](const RecView& r) {
+                    return r.done || r.stops >= cycle ||
+                           (r.cycles >= cycle && r.jstep >= j - kLookahead + 1);
+                }));
+            const RecView r = read_rec(p->rec);
+            if (r.done || r.stops >= cycle) {
+                closed = true;
+                break;
+            }
+            p->kt.j = j;
+            const int kk = j + 1;
             cplx* vj = V + (size_t)j * N;
-            cplx* w = V + (size_t)(j + 1) * N;
             const cplx* zj = vj;
-            if (!no_prec) {
+            if (no_prec) {
+                HIPCHK(launch_normalize_pred(w, st, vj, N, s));
+            } else {
                 cplx* zz = Z + (size_t)j * N;
-                CHK(precond(p, L, ws, vj, zz, s));
+                CHK(precond(p, L, ws, w, st, vj, zz, s));
                 zj = zz;
             }
-            TIMED(HH_KERNEL_STENCIL, 40.0 * (double)N, launch_fine_apply(H, zj, w, s));
-            // CGS2 against v_1..v_{j+1}
-            const int kk = j + 1;
-            const double dot_bytes = (kk + 1) * 16.0 * (double)N;
-            const double axpy_bytes = (kk + 2) * 16.0 * (double)N;
-            TIMED(HH_KERNEL_DOT, dot_bytes, launch_dot_partials(V, N, kk, w, partial, nb, s));
-            HIPCHK(launch_reduce_partials(partial, nb, kk, h1, s));
-            TIMED(HH_KERNEL_AXPY, axpy_bytes, launch_multi_axpy(V, N, kk, h1, w, s));
-            TIMED(HH_KERNEL_DOT, dot_bytes, launch_dot_partials(V, N, kk, w, partial, nb, s));
-            HIPCHK(launch_reduce_partials(partial, nb, kk, h2, s));
-            TIMED(HH_KERNEL_AXPY, axpy_bytes, launch_multi_axpy(V, N, kk, h2, w, s));
-            CHK(norm2_async(w, N, partial, nb, nrm2, s));
-            HIPCHK(launch_givens(st, h1, h2, nrm2, R, cs, sn, g, s));
-            HIPCHK(launch_scale_dev(w, &st->inv_hn, w, N, s));
-            HIPCHK(hipMemcpyAsync(p->st_host, st, sizeof(GivensState), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            CHK(kt_harvest(p));
-            ++it;
-            const GivensState gs = *p->st_host;
-            hist.push_back(gs.est);
-            k = j + 1;
-            if (gs.bad) {
-                rel = NAN;
-                return finish(fail(HH_ENUMERIC, "non-finite value in the Arnoldi step"));
-            }
-            if (gs.breakdown || gs.est <= tol || it >= max_iters) break;
+            TIMED(HH_KERNEL_APPLY_DOT, (40.0 + 16.0 * kk) * (double)N,
+                  launch_apply_dot(H, zj, w, V, kk, partial, active, s));
+            HIPCHK(launch_reduce_pred(partial, L.nbA, kk, h1, active, s));
+            TIMED(HH_KERNEL_AXPY_DOT, (kk + 2) * 16.0 * (double)N,
+                  launch_axpy_dot(V, N, kk, h1, w, partial, active, s));
+            HIPCHK(launch_reduce_pred(partial, L.nbN, kk, h2, active, s));
+            TIMED(HH_KERNEL_AXPY_NORM, (kk + 2) * 16.0 * (double)N,
+                  launch_axpy_norm(V, N, kk, h2, w, partial, active, s));
+            HIPCHK(launch_givens_step(st, h1, h2, partial, L.nbN, R, cs, sn, g, drec, dhist, s));
         }
-        HIPCHK(launch_backsub(k, m, R, g, y, s));
-        HIPCHK(launch_update_x(no_prec ? V : Z, N, k, y, u, s));
+        (void)closed;
+        // the cycle closes on a step (or the solve ended at its start)
+        CHK(wait_for(p, s, [&](const RecView& r) { return r.done || r.stops >= cycle; }));
+        const RecView r = read_rec(p->rec);
+        executed.push_back(r.stops >= cycle ? r.jstep : 0);
+        last_est = ((const volatile HostRecord*)p->rec)->est;
+        if (r.stops < cycle) break;                 // finished at the cycle start
+        HIPCHK(launch_cycle_finish(st, R, g, y, no_prec ? V : Z, N, u, s));
+        if (r.done) break;                          // non-finite value inside the cycle
     }
-    return finish(status);
+    HIPCHK(hipStreamSynchronize(s));
+    SolveState fin;
+    HIPCHK(hipMemcpy(&fin, st, sizeof(SolveState), hipMemcpyDeviceToHost));
+    CHK(kt_harvest(p, executed));
+    const int it = fin.it;
+    if (iterations) *iterations = it;
+    if (true_rel_res) *true_rel_res = fin.rel;
+    if (hist_len) *hist_len = it + 1;
+    for (int i = 0; i <= it && i < hist_cap; ++i) hist_host[i] = p->hist[i];
+    if (fin.status == -4) return fail(HH_ENUMERIC, "non-finite value in the iteration");
+    return fin.status == 1 ? HH_NOT_CONVERGED : HH_OK;
 }
 
 int hh_kernel_timer_start(hh_problem p, int kernel_id) {
@@ -730,8 +819,7 @@ int hh_kernel_timer_start(hh_problem p, int kernel_id) {
     if (kernel_id < HH_KERNEL_NONE || kernel_id > HH_KERNEL_PCR)
         return fail(HH_EINVAL, "unknown kernel id");
     p->kt.kid = kernel_id;
-    p->kt.used = 0;
-    p->kt.pending_bytes.clear();
+    p->kt.pending.clear();
     p->kt.launches = 0;
     p->kt.total_ms = 0.0;
     p->kt.total_bytes = 0.0;

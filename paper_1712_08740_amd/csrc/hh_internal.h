@@ -3,10 +3,32 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstddef>
 #include <cstdint>
 
 namespace hh {
+
+// When set (by the solve driver, for the one kernel class being timed), the
+// next launch goes through hipExtLaunchKernelGGL with these events, which the
+// runtime stamps at the dispatch's own start and end.
+struct LaunchEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+#define HH_LAUNCH(KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                                  \
+    do {                                                                                    \
+        if (::hh::g_launch_events.start) {                                                  \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM,                       \
+                                  ::hh::g_launch_events.start, ::hh::g_launch_events.stop,  \
+                                  0, __VA_ARGS__);                                          \
+            ::hh::g_launch_events = ::hh::LaunchEvents();                                   \
+        } else {                                                                            \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);            \
+        }                                                                                   \
+    } while (0)
 
 // ---------------------------------------------------------------------------
 // complex128 as double2 (x = re, y = im)
@@ -106,32 +128,8 @@ struct Level {
 // ---------------------------------------------------------------------------
 // y = A x (fine operator)
 hipError_t launch_fine_apply(const FineOp& op, const cplx* x, cplx* y, hipStream_t s);
-// r = b - A x
-hipError_t launch_fine_residual(const FineOp& op, const cplx* b, const cplx* x, cplx* r,
-                                hipStream_t s);
-// x_out = omega_j D^{-1} b            (first sweep from x = 0)
-hipError_t launch_fine_jacobi0(const FineOp& op, double wj, const cplx* b, cplx* xo,
-                               hipStream_t s);
-// x_out = x_in + omega_j D^{-1} (b - A x_in)
-hipError_t launch_fine_jacobi(const FineOp& op, double wj, const cplx* b, const cplx* xi,
-                              cplx* xo, hipStream_t s);
 hipError_t launch_coarse_apply(const CoarseOp& op, const cplx* x, cplx* y, hipStream_t s);
-hipError_t launch_coarse_residual(const CoarseOp& op, const cplx* b, const cplx* x, cplx* r,
-                                  hipStream_t s);
-hipError_t launch_coarse_jacobi0(const CoarseOp& op, double wj, const cplx* b, cplx* xo,
-                                 hipStream_t s);
-hipError_t launch_coarse_jacobi(const CoarseOp& op, double wj, const cplx* b, const cplx* xi,
-                                cplx* xo, hipStream_t s);
 
-// ---------------------------------------------------------------------------
-// launchers (mg.hip)
-// ---------------------------------------------------------------------------
-// b_c = R r_f, R = P^T / 2^{d_c}
-hipError_t launch_restrict(int nzf, int nxf, int hz, int hx, const cplx* rf, int nzc, int nxc,
-                           cplx* bc, hipStream_t s);
-// x_f += P e_c
-hipError_t launch_prolong_add(int nzf, int nxf, int hz, int hx, const cplx* ec, int nzc,
-                              int nxc, cplx* xf, hipStream_t s);
 // Galerkin coarse operator from the fine operator (src level 0) or from a
 // coarse 9-point operator
 hipError_t launch_galerkin_from_fine(const FineOp& fine, int hz, int hx, int nzc, int nxc,
@@ -144,59 +142,109 @@ hipError_t launch_dense_from_coarse(const CoarseOp& op, cplx* A, hipStream_t s);
 // in-place inverse by Gauss-Jordan elimination with partial pivoting;
 // scratch: 3n complex + n ints
 hipError_t dense_invert(int n, cplx* A, cplx* scratch, int* perm, hipStream_t s);
-// y = A x, A dense n x n row-major
-hipError_t launch_dense_gemv(int n, const cplx* A, const cplx* x, cplx* y, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // launchers (pcr.hip): exact solve of the 1D tridiagonal shifted Laplacian
 // ---------------------------------------------------------------------------
 hipError_t launch_pcr_solve(const FineOp& op, const cplx* d, cplx* x, hipStream_t s);
 
-// ---------------------------------------------------------------------------
-// launchers (krylov.hip)
-// ---------------------------------------------------------------------------
-// number of partial-sum blocks used for a length-n reduction
-int reduce_blocks(int64_t n);
-// partial[i*nb + blk] = sum over the block's share of conj(V_i) w,  i < k
-hipError_t launch_dot_partials(const cplx* V, int64_t n, int k, const cplx* w, cplx* partial,
-                               int nb, hipStream_t s);
-// out[i] = sum_blk partial[i*nb + blk], summed in a fixed order
-hipError_t launch_reduce_partials(const cplx* partial, int nb, int k, cplx* out,
-                                  hipStream_t s);
-// w -= sum_i V_i h_i
-hipError_t launch_multi_axpy(const cplx* V, int64_t n, int k, const cplx* h, cplx* w,
-                             hipStream_t s);
-// y = a * x with a read from device (real); a = *scale
-hipError_t launch_scale_dev(const cplx* x, const double* scale, cplx* y, int64_t n,
-                            hipStream_t s);
 // b = W f
 hipError_t launch_weight_rhs(const FineOp& op, const cplx* f, cplx* b, hipStream_t s);
-// x += sum_i Z_i y_i
-hipError_t launch_update_x(const cplx* Z, int64_t n, int k, const cplx* y, cplx* x,
-                           hipStream_t s);
 // validation of the slowness: flags[0] |= any non-finite or <= 0, mmax[0] = max
 hipError_t launch_check_slowness(const double* m, int64_t n, double* m2, int* flag,
                                  double* mmax_partial, int nb, hipStream_t s);
 
-// Device-side GMRES least-squares state (one restart cycle).
-struct GivensState {
-    int j;                // current column
-    int m;                // restart length
-    double beta0;         // ||b||
-    double est;           // last residual estimate |g_{j+1}| / beta0
-    double hn;            // h_{j+1,j}
-    double inv_hn;        // 1 / h_{j+1,j}
-    int breakdown;        // h_{j+1,j} == 0
-    int bad;              // NaN/Inf seen
+// Device-side control of a solve: every Arnoldi-step kernel reads `active`
+// and returns at once when it is 0; the solve-level kernels read `done`.
+struct SolveState {
+    int active;      // a restart cycle is open: Arnoldi steps run
+    int done;        // the solve has finished
+    int status;      // 0 converged, 1 budget spent, -4 non-finite
+    int j;           // steps taken in the current cycle
+    int k;           // columns of the current least-squares problem
+    int m;           // restart length
+    int it;          // Arnoldi steps taken in the solve
+    int max_iters;
+    double tol;
+    double beta0;    // ||W f||
+    double rel;      // last recomputed relative residual
+    double scale;    // 1/||w|| for the vector the next step normalises
 };
-// Givens step on column j = st->j: the column is h1 + h2 (the two CGS2
-// passes) with h_{j+1,j} = sqrt(nrm2[0].x); R is (m+1) x m column-major.
-hipError_t launch_givens(GivensState* st, const cplx* h1, const cplx* h2, const cplx* nrm2,
-                         cplx* R, double* cs, cplx* sn, cplx* g, hipStream_t s);
-// y = R(1:k,1:k)^{-1} g(1:k)
-hipError_t launch_backsub(int k, int m, const cplx* R, const cplx* g, cplx* y, hipStream_t s);
-// state init for a new cycle: g = [beta, 0...], st->j = 0
-hipError_t launch_cycle_init(GivensState* st, int m, double beta0, const cplx* nrm2, cplx* g,
-                             double* inv_beta, hipStream_t s);
+
+// Progress record in pinned host memory, written by the device, polled by the
+// host to decide how far ahead to enqueue.
+struct HostRecord {
+    int seq;         // bumped by every record write
+    int done;
+    int status;
+    int it;
+    int cycles;      // restart cycles opened (or closed as done) so far
+    int jstep;       // steps finished in the current cycle
+    int stops;       // cycles closed by a step (converged estimate, full basis, budget)
+    int pad;
+    double est;      // last residual estimate
+    double rel;      // last recomputed relative residual
+};
+
+
+// ---- fused, predicated Arnoldi kernels (krylov.hip) -----------------------
+// w = H z and partial[i*nb + blk] = block sums of conj(V_i) w (nb = apply_blocks)
+hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx* V, int k,
+                            cplx* partial, const int* active, hipStream_t s);
+int apply_blocks(const FineOp& op);
+int node_blocks(int64_t n);
+hipError_t launch_dot_blocks(const cplx* V, int64_t n, int k, const cplx* w, cplx* partial,
+                             hipStream_t s);
+// w -= V h; partial = block sums of conj(V_i) w (nb = node_blocks(n))
+hipError_t launch_axpy_dot(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
+                           const int* active, hipStream_t s);
+// w -= V h; partial[blk].x = block sums of |w|^2
+hipError_t launch_axpy_norm(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
+                            const int* active, hipStream_t s);
+hipError_t launch_reduce_pred(const cplx* partial, int nb, int k, cplx* out, const int* active,
+                              hipStream_t s);
+// r = b - H u; partial[blk].x = block sums of |r|^2 (skipped when *done)
+hipError_t launch_residual_norm(const FineOp& op, const cplx* b, const cplx* u, cplx* r,
+                                cplx* partial, const int* done, hipStream_t s);
+hipError_t launch_cycle_start(SolveState* st, const cplx* partial, int nb, cplx* g,
+                              HostRecord* rec, hipStream_t s);
+hipError_t launch_givens_step(SolveState* st, const cplx* h1, const cplx* h2, const cplx* partial,
+                              int nb, cplx* R, double* cs, cplx* sn, cplx* g, HostRecord* rec,
+                              double* hist, hipStream_t s);
+// y = R^{-1} g, x += Z y for the st->k columns of the cycle, then st->k = 0
+hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
+                               const cplx* Z, int64_t n, cplx* x, hipStream_t s);
+hipError_t launch_normalize_pred(const cplx* w, const SolveState* st, cplx* v, int64_t n,
+                                 hipStream_t s);
+hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
+                             double tol, HostRecord* rec, double* hist, hipStream_t s);
+
+// ---- fused V-cycle kernels (vcycle.hip) -------------------------------------
+hipError_t launch_vc_fine_presmooth(const FineOp& op, double wj, const cplx* src,
+                                    const double* scale, cplx* bout, cplx* xo, const int* active,
+                                    hipStream_t s);
+hipError_t launch_vc_fine_resid_restrict(const FineOp& op, int hz, int hx, const cplx* b,
+                                         const cplx* x, int nzc, int nxc, cplx* bc,
+                                         const int* active, hipStream_t s);
+hipError_t launch_vc_fine_prolong_post1(const FineOp& op, double wj, int hz, int hx,
+                                        const cplx* b, const cplx* x, const cplx* e, int nxc,
+                                        cplx* xo, const int* active, hipStream_t s);
+hipError_t launch_vc_fine_post2(const FineOp& op, double wj, const cplx* b, const cplx* x,
+                                cplx* xo, const int* active, hipStream_t s);
+hipError_t launch_vc_coarse_presmooth(const CoarseOp& op, double wj, const cplx* b, cplx* xo,
+                                      const int* active, hipStream_t s);
+hipError_t launch_vc_coarse_resid_restrict(const CoarseOp& op, int hz, int hx, const cplx* b,
+                                           const cplx* x, int nzc, int nxc, cplx* bc,
+                                           const int* active, hipStream_t s);
+hipError_t launch_vc_coarse_prolong_post1(const CoarseOp& op, double wj, int hz, int hx,
+                                          const cplx* b, const cplx* x, const cplx* e, int nxc,
+                                          cplx* xo, const int* active, hipStream_t s);
+hipError_t launch_vc_coarse_post2(const CoarseOp& op, double wj, const cplx* b, const cplx* x,
+                                  cplx* xo, const int* active, hipStream_t s);
+hipError_t launch_vc_gemv(int n, const cplx* A, const cplx* x, cplx* y, const int* active,
+                          hipStream_t s);
+// PCR with the normalisation of the Arnoldi vector folded in (vout = s*src, x = M^{-1} vout)
+hipError_t launch_pcr_norm(const FineOp& op, const cplx* src, const double* scale, cplx* vout,
+                           cplx* x, const int* active, hipStream_t s);
 
 }  // namespace hh

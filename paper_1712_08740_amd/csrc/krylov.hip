@@ -29,50 +29,6 @@ __device__ __forceinline__ cplx block_sum(cplx v, cplx* sh) {
     return r;
 }
 
-__global__ void __launch_bounds__(RB) k_dot_partials(const cplx* __restrict__ V, int64_t n,
-                                                     const cplx* __restrict__ w,
-                                                     cplx* __restrict__ partial, int nb) {
-    __shared__ cplx sh[RB / 64];
-    const int i = blockIdx.y;
-    const cplx* vi = V + (int64_t)i * n;
-    cplx acc = mk(0.0, 0.0);
-    for (int64_t p = (int64_t)blockIdx.x * RB + threadIdx.x; p < n; p += (int64_t)nb * RB)
-        acc = cadd(acc, cmulc(vi[p], w[p]));
-    const cplx s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[(int64_t)i * nb + blockIdx.x] = s;
-}
-
-__global__ void __launch_bounds__(64) k_reduce_partials(const cplx* __restrict__ partial, int nb,
-                                                        cplx* __restrict__ out) {
-    const int i = blockIdx.x;
-    const cplx* pi = partial + (int64_t)i * nb;
-    cplx acc = mk(0.0, 0.0);
-    for (int t = threadIdx.x; t < nb; t += 64) acc = cadd(acc, pi[t]);
-    for (int off = 32; off > 0; off >>= 1) {
-        acc.x += __shfl_down(acc.x, off, 64);
-        acc.y += __shfl_down(acc.y, off, 64);
-    }
-    if (threadIdx.x == 0) out[i] = acc;
-}
-
-__global__ void __launch_bounds__(EB) k_multi_axpy(const cplx* __restrict__ V, int64_t n, int k,
-                                                   const cplx* __restrict__ h,
-                                                   cplx* __restrict__ w) {
-    const int64_t p = (int64_t)blockIdx.x * EB + threadIdx.x;
-    if (p >= n) return;
-    cplx acc = w[p];
-    for (int i = 0; i < k; ++i) acc = csub(acc, cmul(V[(int64_t)i * n + p], h[i]));
-    w[p] = acc;
-}
-
-__global__ void __launch_bounds__(EB) k_scale_dev(const cplx* x,
-                                                  const double* __restrict__ scale,
-                                                  cplx* y, int64_t n) {
-    const int64_t p = (int64_t)blockIdx.x * EB + threadIdx.x;
-    if (p >= n) return;
-    y[p] = cscale(x[p], scale[0]);
-}
-
 __global__ void __launch_bounds__(EB) k_weight_rhs(FineOp op, const cplx* __restrict__ f,
                                                    cplx* __restrict__ b) {
     const int64_t p = (int64_t)blockIdx.x * EB + threadIdx.x;
@@ -83,16 +39,6 @@ __global__ void __launch_bounds__(EB) k_weight_rhs(FineOp op, const cplx* __rest
     double w = (ix == 0 || ix == op.nx - 1) ? 0.5 : 1.0;
     if (op.ndim == 2 && (iz == 0 || iz == op.nz - 1)) w *= 0.5;
     b[p] = cscale(f[p], w);
-}
-
-__global__ void __launch_bounds__(EB) k_update_x(const cplx* __restrict__ Z, int64_t n, int k,
-                                                 const cplx* __restrict__ y,
-                                                 cplx* __restrict__ x) {
-    const int64_t p = (int64_t)blockIdx.x * EB + threadIdx.x;
-    if (p >= n) return;
-    cplx acc = x[p];
-    for (int i = 0; i < k; ++i) acc = cadd(acc, cmul(Z[(int64_t)i * n + p], y[i]));
-    x[p] = acc;
 }
 
 __global__ void __launch_bounds__(RB) k_check_slowness(const double* __restrict__ m, int64_t n,
@@ -115,19 +61,314 @@ __global__ void __launch_bounds__(RB) k_check_slowness(const double* __restrict_
     if (threadIdx.x == 0) partial[blockIdx.x] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
-// One Givens step on column j (single thread; j <= m is small).
-__global__ void k_givens(GivensState* st, const cplx* __restrict__ h1,
-                         const cplx* __restrict__ h2, const cplx* __restrict__ nrm2,
-                         cplx* __restrict__ R, double* __restrict__ cs, cplx* __restrict__ sn,
-                         cplx* __restrict__ g) {
+// ---------------------------------------------------------------------------
+// Fused Arnoldi kernels (device-side control: every kernel returns at once
+// when st->active == 0, so the host may enqueue ahead of the decision).
+// ---------------------------------------------------------------------------
+constexpr int KC = 8;   // projections reduced per LDS pass
+
+// Block reduction of KC complex values per thread (256 threads, linear tid):
+// out[c] (valid in thread (c * 32)) = sum over threads, fixed order.
+__device__ __forceinline__ void block_multi_sum(const cplx v[KC], cplx* lds, int tid,
+                                                cplx* out_c, int* out_idx) {
+    for (int c = 0; c < KC; ++c) lds[c * 256 + tid] = v[c];
+    __syncthreads();
+    const int g = tid >> 5, l = tid & 31;
+    cplx acc = mk(0.0, 0.0);
+    for (int r = 0; r < 8; ++r) acc = cadd(acc, lds[g * 256 + l + 32 * r]);
+    for (int off = 16; off > 0; off >>= 1) {
+        acc.x += __shfl_down(acc.x, off, 32);
+        acc.y += __shfl_down(acc.y, off, 32);
+    }
+    *out_c = acc;
+    *out_idx = (l == 0) ? g : -1;
+    __syncthreads();
+}
+
+// partial[i*nb + blk] = sum over the block's nodes of conj(V_i[p]) w_p, i < k
+__device__ __forceinline__ void block_dots(const cplx* V, int64_t n, int k, bool valid, int64_t p,
+                                           cplx wp, cplx* partial, int nb, int blk, cplx* lds,
+                                           int tid) {
+    for (int c0 = 0; c0 < k; c0 += KC) {
+        cplx v[KC];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            const int i = c0 + c;
+            v[c] = (valid && i < k) ? cmulc(V[(int64_t)i * n + p], wp) : mk(0.0, 0.0);
+        }
+        cplx sum;
+        int idx;
+        block_multi_sum(v, lds, tid, &sum, &idx);
+        if (idx >= 0 && c0 + idx < k) partial[(int64_t)(c0 + idx) * nb + blk] = sum;
+    }
+}
+
+__device__ __forceinline__ bool off(const int* active) { return active && *active == 0; }
+
+// w = H z (fine operator) and the first projections V^H w
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const cplx* __restrict__ z,
+                                                   cplx* __restrict__ w,
+                                                   const cplx* __restrict__ V, int k,
+                                                   cplx* __restrict__ partial,
+                                                   const int* __restrict__ active) {
+    if (off(active)) return;
+    __shared__ cplx lds[KC * 256];
+    int ix, iz, tid;
+    if (NDIM == 2) {
+        ix = blockIdx.x * 64 + threadIdx.x;
+        iz = blockIdx.y * 4 + threadIdx.y;
+        tid = threadIdx.y * 64 + threadIdx.x;
+    } else {
+        ix = blockIdx.x * 256 + threadIdx.x;
+        iz = 0;
+        tid = threadIdx.x;
+    }
+    const int nb = gridDim.x * gridDim.y;
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    const bool valid = ix < op.nx && iz < op.nz;
+    const int64_t n = (int64_t)op.nz * op.nx;
+    const int64_t p = valid ? (int64_t)iz * op.nx + ix : 0;
+    cplx wp = mk(0.0, 0.0);
+    if (valid) {
+        const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
+        cplx sx = mk(0.0, 0.0);
+        if (ix > 0) sx = cadd(sx, z[p - 1]);
+        if (ix < op.nx - 1) sx = cadd(sx, z[p + 1]);
+        wp = csub(cmul(c.diag, z[p]), cscale(sx, c.cx));
+        if (NDIM == 2) {
+            cplx sz = mk(0.0, 0.0);
+            if (iz > 0) sz = cadd(sz, z[p - op.nx]);
+            if (iz < op.nz - 1) sz = cadd(sz, z[p + op.nx]);
+            wp = csub(wp, cscale(sz, c.cz));
+        }
+        w[p] = wp;
+    }
+    block_dots(V, n, k, valid, p, wp, partial, nb, blk, lds, tid);
+}
+
+// plain projections V^H w (for the stand-alone orthogonalisation entry point)
+__global__ void __launch_bounds__(256) k_dot_blocks(const cplx* __restrict__ V, int64_t n, int k,
+                                                    const cplx* __restrict__ w,
+                                                    cplx* __restrict__ partial) {
+    __shared__ cplx lds[KC * 256];
+    const int tid = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * 256 + tid;
+    const bool valid = p < n;
+    const cplx wp = valid ? w[p] : mk(0.0, 0.0);
+    block_dots(V, n, k, valid, valid ? p : 0, wp, partial, gridDim.x, blockIdx.x, lds, tid);
+}
+
+// w -= V h with the basis loads issued KC at a time (independent loads in
+// flight rather than one dependent round trip per vector)
+__device__ __forceinline__ cplx axpy_chunked(const cplx* V, int64_t n, int k, const cplx* h,
+                                             int64_t p, cplx wp) {
+    for (int c0 = 0; c0 < k; c0 += KC) {
+        cplx v[KC];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) v[c] = (c0 + c < k) ? V[(int64_t)(c0 + c) * n + p] : mk(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < KC; ++c)
+            if (c0 + c < k) wp = csub(wp, cmul(v[c], h[c0 + c]));
+    }
+    return wp;
+}
+
+// w -= V h, then the second projections V^H w. For k <= KMAX the basis
+// values stay in registers between the update and the projections.
+template <int KMAX>
+__global__ void __launch_bounds__(256) k_axpy_dot(const cplx* __restrict__ V, int64_t n, int k,
+                                                  const cplx* __restrict__ h,
+                                                  cplx* __restrict__ w,
+                                                  cplx* __restrict__ partial,
+                                                  const int* __restrict__ active) {
+    if (off(active)) return;
+    __shared__ cplx lds[KC * 256];
+    const int tid = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * 256 + tid;
+    const bool valid = p < n;
+    const int64_t pp = valid ? p : 0;
+    const int nb = gridDim.x, blk = blockIdx.x;
+    if (KMAX > 0 && k <= KMAX) {
+        cplx v[KMAX > 0 ? KMAX : 1];
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i)
+            v[i] = (valid && i < k) ? V[(int64_t)i * n + pp] : mk(0.0, 0.0);
+        cplx wp = valid ? w[pp] : mk(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i)
+            if (i < k) wp = csub(wp, cmul(v[i], h[i]));
+        if (valid) w[pp] = wp;
+#pragma unroll
+        for (int c0 = 0; c0 < KMAX; c0 += KC) {
+            if (c0 >= k) break;
+            cplx d[KC];
+#pragma unroll
+            for (int c = 0; c < KC; ++c) d[c] = cmulc(v[c0 + c], wp);
+            cplx sum;
+            int idx;
+            block_multi_sum(d, lds, tid, &sum, &idx);
+            if (idx >= 0 && c0 + idx < k) partial[(int64_t)(c0 + idx) * nb + blk] = sum;
+        }
+    } else {
+        cplx wp = mk(0.0, 0.0);
+        if (valid) {
+            wp = axpy_chunked(V, n, k, h, pp, w[pp]);
+            w[pp] = wp;
+        }
+        block_dots(V, n, k, valid, pp, wp, partial, nb, blk, lds, tid);
+    }
+}
+
+// w -= V h, then ||w||^2 per block
+__global__ void __launch_bounds__(256) k_axpy_norm(const cplx* __restrict__ V, int64_t n, int k,
+                                                   const cplx* __restrict__ h,
+                                                   cplx* __restrict__ w,
+                                                   cplx* __restrict__ partial,
+                                                   const int* __restrict__ active) {
+    if (off(active)) return;
+    __shared__ cplx sh[4];
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    cplx acc = mk(0.0, 0.0);
+    if (p < n) {
+        const cplx wp = axpy_chunked(V, n, k, h, p, w[p]);
+        w[p] = wp;
+        acc = mk(cabs2(wp), 0.0);
+    }
+    const cplx s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// predicated fixed-order reduction of partial sums (k blocks of 64 threads)
+__global__ void __launch_bounds__(64) k_reduce_pred(const cplx* __restrict__ partial, int nb,
+                                                    cplx* __restrict__ out,
+                                                    const int* __restrict__ active) {
+    if (off(active)) return;
+    const int i = blockIdx.x;
+    const cplx* pi = partial + (int64_t)i * nb;
+    cplx acc = mk(0.0, 0.0);
+    for (int t = threadIdx.x; t < nb; t += 64) acc = cadd(acc, pi[t]);
+    for (int o = 32; o > 0; o >>= 1) {
+        acc.x += __shfl_down(acc.x, o, 64);
+        acc.y += __shfl_down(acc.y, o, 64);
+    }
+    if (threadIdx.x == 0) out[i] = acc;
+}
+
+// r = b - H u (true residual) with ||r||^2 per block; predicated on !done
+template <int NDIM>
+__global__ void __launch_bounds__(256) k_residual_norm(FineOp op, const cplx* __restrict__ b,
+                                                       const cplx* __restrict__ u,
+                                                       cplx* __restrict__ r,
+                                                       cplx* __restrict__ partial,
+                                                       const int* __restrict__ done) {
+    if (*done) return;
+    __shared__ cplx sh[4];
+    int ix, iz;
+    if (NDIM == 2) {
+        ix = blockIdx.x * 64 + threadIdx.x;
+        iz = blockIdx.y * 4 + threadIdx.y;
+    } else {
+        ix = blockIdx.x * 256 + threadIdx.x;
+        iz = 0;
+    }
+    cplx acc = mk(0.0, 0.0);
+    if (ix < op.nx && iz < op.nz) {
+        const int64_t p = (int64_t)iz * op.nx + ix;
+        const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
+        cplx sx = mk(0.0, 0.0);
+        if (ix > 0) sx = cadd(sx, u[p - 1]);
+        if (ix < op.nx - 1) sx = cadd(sx, u[p + 1]);
+        cplx au = csub(cmul(c.diag, u[p]), cscale(sx, c.cx));
+        if (NDIM == 2) {
+            cplx sz = mk(0.0, 0.0);
+            if (iz > 0) sz = cadd(sz, u[p - op.nx]);
+            if (iz < op.nz - 1) sz = cadd(sz, u[p + op.nx]);
+            au = csub(au, cscale(sz, c.cz));
+        }
+        const cplx rp = csub(b[p], au);
+        r[p] = rp;
+        acc = mk(cabs2(rp), 0.0);
+    }
+    // block of 256 threads (linear id)
+    const int tid = NDIM == 2 ? threadIdx.y * 64 + threadIdx.x : threadIdx.x;
+    for (int o = 32; o > 0; o >>= 1) acc.x += __shfl_down(acc.x, o, 64);
+    if ((tid & 63) == 0) sh[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+        partial[blk] = mk(sh[0].x + sh[1].x + sh[2].x + sh[3].x, 0.0);
+    }
+}
+
+// fixed-order sum of nb real partials (x components) by one 256-thread block
+__device__ __forceinline__ double block_sum_partials(const cplx* partial, int nb, double* sh) {
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < nb; t += 256) acc += partial[t].x;
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Start of a restart cycle: beta = ||b - H u||; decide whether the solve is
+// finished; otherwise reset the least-squares state and open the cycle.
+__global__ void __launch_bounds__(256) k_cycle_start(SolveState* st, const cplx* __restrict__ partial,
+                                                     int nb, cplx* __restrict__ g,
+                                                     HostRecord* rec) {
+    if (st->done) return;
+    __shared__ double sh[4];
+    const double beta = sqrt(block_sum_partials(partial, nb, sh));
+    if (threadIdx.x != 0) return;
+    const double rel = beta / st->beta0;
+    st->rel = rel;
+    int done = 0, status = 0;
+    if (!isfinite(rel)) { done = 1; status = -4; }
+    else if (rel <= st->tol) { done = 1; status = 0; }
+    else if (st->it >= st->max_iters) { done = 1; status = 1; }
+    st->k = 0;
+    st->j = 0;
+    if (done) {
+        st->done = 1;
+        st->active = 0;
+        st->status = status;
+    } else {
+        st->active = 1;
+        st->scale = 1.0 / beta;
+        g[0] = mk(beta, 0.0);
+        for (int i = 1; i <= st->m; ++i) g[i] = mk(0.0, 0.0);
+    }
+    rec->rel = rel;
+    rec->status = status;
+    rec->it = st->it;
+    rec->jstep = 0;
+    __threadfence_system();
+    rec->cycles += 1;
+    rec->done = st->done;
+    rec->seq += 1;
+    __threadfence_system();
+}
+
+// Givens step on column j (single block): ||w|| from the per-block partials,
+// column = h1 + h2, previous rotations, new rotation, residual estimate,
+// stop decision, history entry for the host.
+__global__ void __launch_bounds__(256) k_givens_step(SolveState* st, const cplx* __restrict__ h1,
+                                                     const cplx* __restrict__ h2,
+                                                     const cplx* __restrict__ partial, int nb,
+                                                     cplx* __restrict__ R, double* __restrict__ cs,
+                                                     cplx* __restrict__ sn, cplx* __restrict__ g,
+                                                     HostRecord* rec, double* hist) {
+    if (st->active == 0) return;
+    __shared__ double sh[4];
+    const double hn2 = block_sum_partials(partial, nb, sh);
     if (threadIdx.x != 0) return;
     const int j = st->j;
     const int ld = st->m + 1;
     cplx* col = R + (int64_t)j * ld;
     for (int i = 0; i <= j; ++i) col[i] = cadd(h1[i], h2[i]);
-    const double hn = sqrt(nrm2[0].x);
+    const double hn = sqrt(hn2);
     col[j + 1] = mk(hn, 0.0);
-    for (int i = 0; i < j; ++i) {           // previous rotations
+    for (int i = 0; i < j; ++i) {
         const cplx p = col[i], q = col[i + 1];
         col[i] = cadd(cscale(p, cs[i]), cmul(sn[i], q));
         col[i + 1] = csub(cscale(q, cs[i]), cmulc(sn[i], p));
@@ -153,109 +394,221 @@ __global__ void k_givens(GivensState* st, const cplx* __restrict__ h1,
     g[j + 1] = csub(mk(0.0, 0.0), cmulc(s, gj));
     g[j] = cscale(gj, c);
     const double est = sqrt(cabs2(g[j + 1])) / st->beta0;
-    st->est = est;
-    st->hn = hn;
-    st->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
-    st->breakdown = hn == 0.0;
-    st->bad = !(isfinite(est) && isfinite(hn));
+    const int it = st->it + 1;
+    const int bad = !(isfinite(est) && isfinite(hn));
+    const int stop = bad || hn == 0.0 || est <= st->tol || it >= st->max_iters || j + 1 >= st->m;
+    st->it = it;
     st->j = j + 1;
+    st->k = j + 1;
+    st->scale = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (stop) st->active = 0;
+    if (bad) {
+        st->done = 1;
+        st->status = -4;
+    }
+    hist[it] = est;
+    rec->it = it;
+    rec->est = est;
+    __threadfence_system();
+    rec->jstep = j + 1;
+    if (stop) rec->stops += 1;
+    rec->done = st->done;
+    rec->status = st->status;
+    rec->seq += 1;
+    __threadfence_system();
 }
 
-__global__ void k_backsub(int k, int m, const cplx* __restrict__ R, const cplx* __restrict__ g,
-                          cplx* __restrict__ y) {
-    if (threadIdx.x != 0) return;
-    const int ld = m + 1;
+// y = R^{-1} g (k = st->k columns), then u += Z y; one block of 256 threads
+// solves the triangle (column-oriented, g kept in LDS), the update is separate.
+__global__ void __launch_bounds__(256) k_backsub_pred(const SolveState* st,
+                                                      const cplx* __restrict__ R,
+                                                      const cplx* __restrict__ g,
+                                                      cplx* __restrict__ y) {
+    const int k = st->k;
+    if (k == 0) return;
+    const int ld = st->m + 1;
+    __shared__ cplx gs[1025];
+    for (int i = threadIdx.x; i < k; i += 256) gs[i] = g[i];
+    __syncthreads();
     for (int i = k - 1; i >= 0; --i) {
-        cplx acc = g[i];
-        for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(R[i + (int64_t)l * ld], y[l]));
-        y[i] = cdiv(acc, R[i + (int64_t)i * ld]);
+        const cplx yi = cdiv(gs[i], R[i + (int64_t)i * ld]);
+        __syncthreads();
+        for (int l = threadIdx.x; l < i; l += 256)
+            gs[l] = csub(gs[l], cmul(R[l + (int64_t)i * ld], yi));
+        if (threadIdx.x == 0) y[i] = yi;
+        __syncthreads();
     }
 }
 
-__global__ void k_cycle_init(GivensState* st, int m, double beta0, const cplx* __restrict__ nrm2,
-                             cplx* __restrict__ g, double* __restrict__ inv_beta) {
-    const double beta = sqrt(nrm2[0].x);
-    for (int i = threadIdx.x; i <= m; i += blockDim.x) g[i] = mk(i == 0 ? beta : 0.0, 0.0);
-    if (threadIdx.x == 0) {
-        inv_beta[0] = 1.0 / beta;
-        st->j = 0;
-        st->m = m;
-        st->beta0 = beta0;
-        st->est = beta / beta0;
-        st->hn = 0.0;
-        st->inv_hn = 0.0;
-        st->breakdown = 0;
-        st->bad = 0;
+__global__ void __launch_bounds__(256) k_update_pred(const SolveState* st,
+                                                     const cplx* __restrict__ Z, int64_t n,
+                                                     const cplx* __restrict__ y,
+                                                     cplx* __restrict__ x) {
+    const int k = st->k;
+    if (k == 0) return;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    cplx acc = x[p];
+    for (int c0 = 0; c0 < k; c0 += KC) {
+        cplx v[KC];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) v[c] = (c0 + c < k) ? Z[(int64_t)(c0 + c) * n + p] : mk(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < KC; ++c)
+            if (c0 + c < k) acc = cadd(acc, cmul(v[c], y[c0 + c]));
     }
+    x[p] = acc;
+}
+
+// after the update of a cycle: mark k = 0 so a repeated end-of-cycle is a no-op
+__global__ void k_cycle_end(SolveState* st) {
+    if (threadIdx.x == 0) st->k = 0;
+}
+
+// v_j = s * w (normalisation, used when no preconditioner reads w first)
+__global__ void __launch_bounds__(256) k_normalize_pred(const cplx* __restrict__ w,
+                                                        const SolveState* st,
+                                                        cplx* __restrict__ v, int64_t n) {
+    if (st->active == 0) return;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    v[p] = cscale(w[p], st->scale);
+}
+
+// solve prologue: beta0 = ||b|| from partials; sets done when b == 0 or not finite
+__global__ void __launch_bounds__(256) k_solve_init(SolveState* st, const cplx* __restrict__ partial,
+                                                    int nb, int m, int max_iters, double tol,
+                                                    HostRecord* rec, double* hist) {
+    __shared__ double sh[4];
+    const double b2 = block_sum_partials(partial, nb, sh);
+    if (threadIdx.x != 0) return;
+    const double beta0 = sqrt(b2);
+    st->beta0 = beta0;
+    st->m = m;
+    st->max_iters = max_iters;
+    st->tol = tol;
+    st->it = 0;
+    st->j = 0;
+    st->k = 0;
+    st->active = 0;
+    st->scale = 0.0;
+    st->rel = 0.0;
+    st->done = 0;
+    st->status = 0;
+    if (!isfinite(beta0)) { st->done = 1; st->status = -4; st->rel = beta0; }
+    else if (beta0 == 0.0) { st->done = 1; st->status = 0; }
+    hist[0] = 1.0;
+    rec->it = 0;
+    rec->est = 1.0;
+    rec->rel = st->rel;
+    rec->status = st->status;
+    rec->cycles = 0;
+    rec->jstep = 0;
+    rec->stops = 0;
+    __threadfence_system();
+    rec->done = st->done;
+    rec->seq = 1;
+    __threadfence_system();
 }
 
 inline unsigned eblocks(int64_t n) { return (unsigned)((n + EB - 1) / EB); }
 
 }  // namespace
 
-int reduce_blocks(int64_t n) {
-    int64_t nb = (n + 2047) / 2048;
-    if (nb < 1) nb = 1;
-    if (nb > 512) nb = 512;
-    return (int)nb;
-}
-
-hipError_t launch_dot_partials(const cplx* V, int64_t n, int k, const cplx* w, cplx* partial,
-                               int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_dot_partials, dim3(nb, k), dim3(RB), 0, s, V, n, w, partial, nb);
-    return hipGetLastError();
-}
-
-hipError_t launch_reduce_partials(const cplx* partial, int nb, int k, cplx* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(k), dim3(64), 0, s, partial, nb, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_multi_axpy(const cplx* V, int64_t n, int k, const cplx* h, cplx* w,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_multi_axpy, dim3(eblocks(n)), dim3(EB), 0, s, V, n, k, h, w);
-    return hipGetLastError();
-}
-
-hipError_t launch_scale_dev(const cplx* x, const double* scale, cplx* y, int64_t n,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_scale_dev, dim3(eblocks(n)), dim3(EB), 0, s, x, scale, y, n);
-    return hipGetLastError();
-}
-
 hipError_t launch_weight_rhs(const FineOp& op, const cplx* f, cplx* b, hipStream_t s) {
     const int64_t n = (int64_t)op.nz * op.nx;
-    hipLaunchKernelGGL(k_weight_rhs, dim3(eblocks(n)), dim3(EB), 0, s, op, f, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_update_x(const cplx* Z, int64_t n, int k, const cplx* y, cplx* x,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_update_x, dim3(eblocks(n)), dim3(EB), 0, s, Z, n, k, y, x);
+    HH_LAUNCH(k_weight_rhs, dim3(eblocks(n)), dim3(EB), 0, s, op, f, b);
     return hipGetLastError();
 }
 
 hipError_t launch_check_slowness(const double* m, int64_t n, double* m2, int* flag,
                                  double* mmax_partial, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_check_slowness, dim3(nb), dim3(RB), 0, s, m, n, m2, flag, mmax_partial,
+    HH_LAUNCH(k_check_slowness, dim3(nb), dim3(RB), 0, s, m, n, m2, flag, mmax_partial,
                        nb);
     return hipGetLastError();
 }
 
-hipError_t launch_givens(GivensState* st, const cplx* h1, const cplx* h2, const cplx* nrm2,
-                         cplx* R, double* cs, cplx* sn, cplx* g, hipStream_t s) {
-    hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, st, h1, h2, nrm2, R, cs, sn, g);
+hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx* V, int k,
+                            cplx* partial, const int* active, hipStream_t s) {
+    if (op.ndim == 2)
+        HH_LAUNCH(k_apply_dot<2>, dim3((op.nx + 63) / 64, (op.nz + 3) / 4), dim3(64, 4), 0,
+                           s, op, z, w, V, k, partial, active);
+    else
+        HH_LAUNCH(k_apply_dot<1>, dim3((op.nx + 255) / 256), dim3(256), 0, s, op, z, w, V,
+                           k, partial, active);
     return hipGetLastError();
 }
-
-hipError_t launch_backsub(int k, int m, const cplx* R, const cplx* g, cplx* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_backsub, dim3(1), dim3(64), 0, s, k, m, R, g, y);
+int apply_blocks(const FineOp& op) {
+    return op.ndim == 2 ? ((op.nx + 63) / 64) * ((op.nz + 3) / 4) : (op.nx + 255) / 256;
+}
+int node_blocks(int64_t n) { return (int)((n + 255) / 256); }
+hipError_t launch_dot_blocks(const cplx* V, int64_t n, int k, const cplx* w, cplx* partial,
+                             hipStream_t s) {
+    HH_LAUNCH(k_dot_blocks, dim3(node_blocks(n)), dim3(256), 0, s, V, n, k, w, partial);
     return hipGetLastError();
 }
-
-hipError_t launch_cycle_init(GivensState* st, int m, double beta0, const cplx* nrm2, cplx* g,
-                             double* inv_beta, hipStream_t s) {
-    hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, s, st, m, beta0, nrm2, g, inv_beta);
+hipError_t launch_axpy_dot(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
+                           const int* active, hipStream_t s) {
+    const dim3 g(node_blocks(n)), b(256);
+    if (k <= 8)
+        HH_LAUNCH(k_axpy_dot<8>, g, b, 0, s, V, n, k, h, w, partial, active);
+    else if (k <= 16)
+        HH_LAUNCH(k_axpy_dot<16>, g, b, 0, s, V, n, k, h, w, partial, active);
+    else if (k <= 32)
+        HH_LAUNCH(k_axpy_dot<32>, g, b, 0, s, V, n, k, h, w, partial, active);
+    else
+        HH_LAUNCH(k_axpy_dot<0>, g, b, 0, s, V, n, k, h, w, partial, active);
+    return hipGetLastError();
+}
+hipError_t launch_axpy_norm(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
+                            const int* active, hipStream_t s) {
+    HH_LAUNCH(k_axpy_norm, dim3(node_blocks(n)), dim3(256), 0, s, V, n, k, h, w, partial,
+                       active);
+    return hipGetLastError();
+}
+hipError_t launch_reduce_pred(const cplx* partial, int nb, int k, cplx* out, const int* active,
+                              hipStream_t s) {
+    HH_LAUNCH(k_reduce_pred, dim3(k), dim3(64), 0, s, partial, nb, out, active);
+    return hipGetLastError();
+}
+hipError_t launch_residual_norm(const FineOp& op, const cplx* b, const cplx* u, cplx* r,
+                                cplx* partial, const int* done, hipStream_t s) {
+    if (op.ndim == 2)
+        HH_LAUNCH(k_residual_norm<2>, dim3((op.nx + 63) / 64, (op.nz + 3) / 4), dim3(64, 4),
+                           0, s, op, b, u, r, partial, done);
+    else
+        HH_LAUNCH(k_residual_norm<1>, dim3((op.nx + 255) / 256), dim3(256), 0, s, op, b, u,
+                           r, partial, done);
+    return hipGetLastError();
+}
+hipError_t launch_cycle_start(SolveState* st, const cplx* partial, int nb, cplx* g,
+                              HostRecord* rec, hipStream_t s) {
+    HH_LAUNCH(k_cycle_start, dim3(1), dim3(256), 0, s, st, partial, nb, g, rec);
+    return hipGetLastError();
+}
+hipError_t launch_givens_step(SolveState* st, const cplx* h1, const cplx* h2, const cplx* partial,
+                              int nb, cplx* R, double* cs, cplx* sn, cplx* g, HostRecord* rec,
+                              double* hist, hipStream_t s) {
+    HH_LAUNCH(k_givens_step, dim3(1), dim3(256), 0, s, st, h1, h2, partial, nb, R, cs, sn,
+                       g, rec, hist);
+    return hipGetLastError();
+}
+hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
+                               const cplx* Z, int64_t n, cplx* x, hipStream_t s) {
+    HH_LAUNCH(k_backsub_pred, dim3(1), dim3(256), 0, s, st, R, g, y);
+    HH_LAUNCH(k_update_pred, dim3(node_blocks(n)), dim3(256), 0, s, st, Z, n, y, x);
+    HH_LAUNCH(k_cycle_end, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+hipError_t launch_normalize_pred(const cplx* w, const SolveState* st, cplx* v, int64_t n,
+                                 hipStream_t s) {
+    HH_LAUNCH(k_normalize_pred, dim3(node_blocks(n)), dim3(256), 0, s, w, st, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
+                             double tol, HostRecord* rec, double* hist, hipStream_t s) {
+    HH_LAUNCH(k_solve_init, dim3(1), dim3(256), 0, s, st, partial, nb, m, max_iters, tol,
+                       rec, hist);
     return hipGetLastError();
 }
 

@@ -23,48 +23,6 @@ __device__ __forceinline__ int interp_nodes(int q, int halved, int* J, double* w
     return 2;
 }
 
-__global__ void __launch_bounds__(256) k_restrict(int nzf, int nxf, int hz, int hx,
-                                                  const cplx* __restrict__ rf, int nzc, int nxc,
-                                                  cplx* __restrict__ bc, double scale) {
-    const int Ix = blockIdx.x * BX + threadIdx.x;
-    const int Iz = blockIdx.y * BZ + threadIdx.y;
-    if (Ix >= nxc || Iz >= nzc) return;
-    const int fz = hz ? 2 * Iz : Iz;
-    const int fx = hx ? 2 * Ix : Ix;
-    const int rz = hz ? 1 : 0, rx = hx ? 1 : 0;
-    cplx acc = mk(0.0, 0.0);
-    for (int dz = -rz; dz <= rz; ++dz) {
-        const int qz = fz + dz;
-        if (qz < 0 || qz >= nzf) continue;
-        const double wz = dz == 0 ? 1.0 : 0.5;
-        for (int dx = -rx; dx <= rx; ++dx) {
-            const int qx = fx + dx;
-            if (qx < 0 || qx >= nxf) continue;
-            const double wx = dx == 0 ? 1.0 : 0.5;
-            acc = cadd(acc, cscale(rf[(int64_t)qz * nxf + qx], wz * wx));
-        }
-    }
-    bc[(int64_t)Iz * nxc + Ix] = cscale(acc, scale);
-}
-
-__global__ void __launch_bounds__(256) k_prolong_add(int nzf, int nxf, int hz, int hx,
-                                                     const cplx* __restrict__ ec, int nzc, int nxc,
-                                                     cplx* __restrict__ xf) {
-    const int fx = blockIdx.x * BX + threadIdx.x;
-    const int fz = blockIdx.y * BZ + threadIdx.y;
-    if (fx >= nxf || fz >= nzf) return;
-    int Jz[2], Jx[2];
-    double wz[2], wx[2];
-    const int nzj = interp_nodes(fz, hz, Jz, wz);
-    const int nxj = interp_nodes(fx, hx, Jx, wx);
-    cplx acc = mk(0.0, 0.0);
-    for (int a = 0; a < nzj; ++a)
-        for (int b = 0; b < nxj; ++b)
-            acc = cadd(acc, cscale(ec[(int64_t)Jz[a] * nxc + Jx[b]], wz[a] * wx[b]));
-    const int64_t p = (int64_t)fz * nxf + fx;
-    xf[p] = cadd(xf[p], acc);
-}
-
 // Accumulate R[I,p] * A[p,q] * P[q,J] over the fine rows p of R's support and
 // the entries q of row p; row p is produced by the functor `row(pz, px, emit)`.
 template <class RowFn>
@@ -274,52 +232,18 @@ __global__ void __launch_bounds__(256) k_gj_unscramble(int n, cplx* __restrict__
     }
 }
 
-// y = A x: one 256-thread workgroup per row, fixed-order reduction.
-__global__ void __launch_bounds__(256) k_dense_gemv(int n, const cplx* __restrict__ A,
-                                                    const cplx* __restrict__ x,
-                                                    cplx* __restrict__ y) {
-    __shared__ cplx sh[4];
-    const int i = blockIdx.x;
-    const int tid = threadIdx.x;
-    const cplx* row = A + (int64_t)i * n;
-    cplx acc = mk(0.0, 0.0);
-    for (int j = tid; j < n; j += 256) acc = cadd(acc, cmul(row[j], x[j]));
-    for (int off = 32; off > 0; off >>= 1) {
-        acc.x += __shfl_down(acc.x, off, 64);
-        acc.y += __shfl_down(acc.y, off, 64);
-    }
-    if ((tid & 63) == 0) sh[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) y[i] = cadd(cadd(sh[0], sh[1]), cadd(sh[2], sh[3]));
-}
-
 }  // namespace
-
-hipError_t launch_restrict(int nzf, int nxf, int hz, int hx, const cplx* rf, int nzc, int nxc,
-                           cplx* bc, hipStream_t s) {
-    const double scale = 1.0 / (double)((hz ? 2 : 1) * (hx ? 2 : 1));
-    hipLaunchKernelGGL(k_restrict, grid2(nzc, nxc), dim3(BX, BZ), 0, s, nzf, nxf, hz, hx, rf,
-                       nzc, nxc, bc, scale);
-    return hipGetLastError();
-}
-
-hipError_t launch_prolong_add(int nzf, int nxf, int hz, int hx, const cplx* ec, int nzc,
-                              int nxc, cplx* xf, hipStream_t s) {
-    hipLaunchKernelGGL(k_prolong_add, grid2(nzf, nxf), dim3(BX, BZ), 0, s, nzf, nxf, hz, hx, ec,
-                       nzc, nxc, xf);
-    return hipGetLastError();
-}
 
 hipError_t launch_galerkin_from_fine(const FineOp& fine, int hz, int hx, int nzc, int nxc,
                                      cplx* Cc, hipStream_t s) {
-    hipLaunchKernelGGL(k_galerkin_from_fine, grid2(nzc, nxc), dim3(BX, BZ), 0, s, fine, hz, hx,
+    HH_LAUNCH(k_galerkin_from_fine, grid2(nzc, nxc), dim3(BX, BZ), 0, s, fine, hz, hx,
                        nzc, nxc, Cc);
     return hipGetLastError();
 }
 
 hipError_t launch_galerkin_from_coarse(const CoarseOp& fine, int hz, int hx, int nzc, int nxc,
                                        cplx* Cc, hipStream_t s) {
-    hipLaunchKernelGGL(k_galerkin_from_coarse, grid2(nzc, nxc), dim3(BX, BZ), 0, s, fine, hz, hx,
+    HH_LAUNCH(k_galerkin_from_coarse, grid2(nzc, nxc), dim3(BX, BZ), 0, s, fine, hz, hx,
                        nzc, nxc, Cc);
     return hipGetLastError();
 }
@@ -328,7 +252,7 @@ hipError_t launch_dense_from_fine(const FineOp& op, cplx* A, hipStream_t s) {
     const size_t n = (size_t)op.nz * op.nx;
     hipError_t e = hipMemsetAsync(A, 0, n * n * sizeof(cplx), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dense_from_fine, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, A);
+    HH_LAUNCH(k_dense_from_fine, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, A);
     return hipGetLastError();
 }
 
@@ -336,7 +260,7 @@ hipError_t launch_dense_from_coarse(const CoarseOp& op, cplx* A, hipStream_t s) 
     const size_t n = (size_t)op.nz * op.nx;
     hipError_t e = hipMemsetAsync(A, 0, n * n * sizeof(cplx), s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dense_from_coarse, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, A);
+    HH_LAUNCH(k_dense_from_coarse, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, A);
     return hipGetLastError();
 }
 
@@ -345,17 +269,12 @@ hipError_t dense_invert(int n, cplx* A, cplx* scratch, int* perm, hipStream_t s)
     cplx* pcol = scratch + n;
     cplx* rowk = scratch + 2 * n;
     for (int k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(GJ_THREADS), 0, s, n, k, A, prow, pcol,
+        HH_LAUNCH(k_gj_pivot, dim3(1), dim3(GJ_THREADS), 0, s, n, k, A, prow, pcol,
                            rowk, perm);
-        hipLaunchKernelGGL(k_gj_update, grid2(n, n), dim3(BX, BZ), 0, s, n, k, A, prow, pcol,
+        HH_LAUNCH(k_gj_update, grid2(n, n), dim3(BX, BZ), 0, s, n, k, A, prow, pcol,
                            rowk, perm);
     }
-    hipLaunchKernelGGL(k_gj_unscramble, dim3((n + 255) / 256), dim3(256), 0, s, n, A, perm);
-    return hipGetLastError();
-}
-
-hipError_t launch_dense_gemv(int n, const cplx* A, const cplx* x, cplx* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_dense_gemv, dim3(n), dim3(256), 0, s, n, A, x, y);
+    HH_LAUNCH(k_gj_unscramble, dim3((n + 255) / 256), dim3(256), 0, s, n, A, perm);
     return hipGetLastError();
 }
 

@@ -19,17 +19,26 @@ namespace {
 constexpr int PCR_THREADS = 1024;
 constexpr int PCR_MAXN = 1024;
 
-__global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOp op, const cplx* __restrict__ d_in,
-                                                     cplx* __restrict__ x_out) {
+// d = s * src (s = *scale, or 1); vout = d when vout != nullptr (the normalised
+// Arnoldi vector); x = M^{-1} d. Returns at once when *active == 0.
+__global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOp op, const cplx* __restrict__ src,
+                                                     const double* __restrict__ scale,
+                                                     cplx* __restrict__ vout,
+                                                     cplx* __restrict__ x_out,
+                                                     const int* __restrict__ active) {
+    if (active && *active == 0) return;
     __shared__ cplx sa[PCR_MAXN], sb[PCR_MAXN], sc[PCR_MAXN], sd[PCR_MAXN];
     const int n = op.nx;
     const int i = threadIdx.x;
+    const double sv = scale ? scale[0] : 1.0;
     if (i < n) {
         const Coef5 c = fine_coefs(op, 0, i, op.m2[i]);
         sa[i] = mk(i > 0 ? -c.cx : 0.0, 0.0);
         sc[i] = mk(i < n - 1 ? -c.cx : 0.0, 0.0);
         sb[i] = c.diag;
-        sd[i] = d_in[i];
+        const cplx d = cscale(src[i], sv);
+        sd[i] = d;
+        if (vout) vout[i] = d;
     }
     __syncthreads();
     for (int s = 1; s < n; s <<= 1) {
@@ -66,8 +75,13 @@ __global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOp op, const cplx* __re
 }  // namespace
 
 hipError_t launch_pcr_solve(const FineOp& op, const cplx* d, cplx* x, hipStream_t s) {
+    return launch_pcr_norm(op, d, nullptr, nullptr, x, nullptr, s);
+}
+
+hipError_t launch_pcr_norm(const FineOp& op, const cplx* src, const double* scale, cplx* vout,
+                           cplx* x, const int* active, hipStream_t s) {
     if (op.ndim != 1 || op.nx > PCR_MAXN) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_pcr, dim3(1), dim3(PCR_THREADS), 0, s, op, d, x);
+    HH_LAUNCH(k_pcr, dim3(1), dim3(PCR_THREADS), 0, s, op, src, scale, vout, x, active);
     return hipGetLastError();
 }
 

@@ -55,43 +55,6 @@ __global__ void __launch_bounds__(256) k_fine_apply(FineOp op, const cplx* __res
     y[p] = cadd(cmul(c.diag, x[p]), fine_offdiag<NDIM>(op, c, x, iz, ix, p));
 }
 
-template <int NDIM>
-__global__ void __launch_bounds__(256) k_fine_residual(FineOp op, const cplx* __restrict__ b,
-                                                       const cplx* __restrict__ x,
-                                                       cplx* __restrict__ r) {
-    int iz, ix;
-    if (!node_of_thread<NDIM>(op, iz, ix)) return;
-    const int64_t p = (int64_t)iz * op.nx + ix;
-    const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
-    const cplx ax = cadd(cmul(c.diag, x[p]), fine_offdiag<NDIM>(op, c, x, iz, ix, p));
-    r[p] = csub(b[p], ax);
-}
-
-template <int NDIM>
-__global__ void __launch_bounds__(256) k_fine_jacobi0(FineOp op, double wj,
-                                                      const cplx* __restrict__ b,
-                                                      cplx* __restrict__ xo) {
-    int iz, ix;
-    if (!node_of_thread<NDIM>(op, iz, ix)) return;
-    const int64_t p = (int64_t)iz * op.nx + ix;
-    const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
-    xo[p] = cscale(cdiv(b[p], c.diag), wj);
-}
-
-template <int NDIM>
-__global__ void __launch_bounds__(256) k_fine_jacobi(FineOp op, double wj,
-                                                     const cplx* __restrict__ b,
-                                                     const cplx* __restrict__ xi,
-                                                     cplx* __restrict__ xo) {
-    int iz, ix;
-    if (!node_of_thread<NDIM>(op, iz, ix)) return;
-    const int64_t p = (int64_t)iz * op.nx + ix;
-    const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
-    const cplx xp = xi[p];
-    const cplx ax = cadd(cmul(c.diag, xp), fine_offdiag<NDIM>(op, c, xi, iz, ix, p));
-    xo[p] = cadd(xp, cscale(cdiv(csub(b[p], ax), c.diag), wj));
-}
-
 // ---- 9-point coarse operators ---------------------------------------------
 __device__ __forceinline__ bool coarse_node(const CoarseOp& op, int& iz, int& ix) {
     ix = blockIdx.x * BX + threadIdx.x;
@@ -128,37 +91,6 @@ __global__ void __launch_bounds__(256) k_coarse_apply(CoarseOp op, const cplx* _
     y[p] = coarse_row(op, x, iz, ix, p, nullptr);
 }
 
-__global__ void __launch_bounds__(256) k_coarse_residual(CoarseOp op, const cplx* __restrict__ b,
-                                                         const cplx* __restrict__ x,
-                                                         cplx* __restrict__ r) {
-    int iz, ix;
-    if (!coarse_node(op, iz, ix)) return;
-    const int64_t p = (int64_t)iz * op.nx + ix;
-    r[p] = csub(b[p], coarse_row(op, x, iz, ix, p, nullptr));
-}
-
-__global__ void __launch_bounds__(256) k_coarse_jacobi0(CoarseOp op, double wj,
-                                                        const cplx* __restrict__ b,
-                                                        cplx* __restrict__ xo) {
-    int iz, ix;
-    if (!coarse_node(op, iz, ix)) return;
-    const int64_t p = (int64_t)iz * op.nx + ix;
-    const int64_t N = (int64_t)op.nz * op.nx;
-    xo[p] = cscale(cdiv(b[p], op.C[4 * N + p]), wj);
-}
-
-__global__ void __launch_bounds__(256) k_coarse_jacobi(CoarseOp op, double wj,
-                                                       const cplx* __restrict__ b,
-                                                       const cplx* __restrict__ xi,
-                                                       cplx* __restrict__ xo) {
-    int iz, ix;
-    if (!coarse_node(op, iz, ix)) return;
-    const int64_t p = (int64_t)iz * op.nx + ix;
-    cplx d = mk(1.0, 0.0);
-    const cplx ax = coarse_row(op, xi, iz, ix, p, &d);
-    xo[p] = cadd(xi[p], cscale(cdiv(csub(b[p], ax), d), wj));
-}
-
 dim3 grid2(int nz, int nx) { return dim3((nx + BX - 1) / BX, (nz + BZ - 1) / BZ); }
 
 }  // namespace
@@ -166,10 +98,10 @@ dim3 grid2(int nz, int nx) { return dim3((nx + BX - 1) / BX, (nz + BZ - 1) / BZ)
 #define HH_FINE_LAUNCH(KERNEL, ...)                                                        \
     do {                                                                                   \
         if (op.ndim == 2)                                                                  \
-            hipLaunchKernelGGL(KERNEL<2>, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s,         \
+            HH_LAUNCH(KERNEL<2>, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s,         \
                                __VA_ARGS__);                                               \
         else                                                                               \
-            hipLaunchKernelGGL(KERNEL<1>, dim3((op.nx + B1 - 1) / B1), dim3(B1), 0, s,     \
+            HH_LAUNCH(KERNEL<1>, dim3((op.nx + B1 - 1) / B1), dim3(B1), 0, s,     \
                                __VA_ARGS__);                                               \
         return hipGetLastError();                                                          \
     } while (0)
@@ -177,38 +109,8 @@ dim3 grid2(int nz, int nx) { return dim3((nx + BX - 1) / BX, (nz + BZ - 1) / BZ)
 hipError_t launch_fine_apply(const FineOp& op, const cplx* x, cplx* y, hipStream_t s) {
     HH_FINE_LAUNCH(k_fine_apply, op, x, y);
 }
-hipError_t launch_fine_residual(const FineOp& op, const cplx* b, const cplx* x, cplx* r,
-                                hipStream_t s) {
-    HH_FINE_LAUNCH(k_fine_residual, op, b, x, r);
-}
-hipError_t launch_fine_jacobi0(const FineOp& op, double wj, const cplx* b, cplx* xo,
-                               hipStream_t s) {
-    HH_FINE_LAUNCH(k_fine_jacobi0, op, wj, b, xo);
-}
-hipError_t launch_fine_jacobi(const FineOp& op, double wj, const cplx* b, const cplx* xi,
-                              cplx* xo, hipStream_t s) {
-    HH_FINE_LAUNCH(k_fine_jacobi, op, wj, b, xi, xo);
-}
-
 hipError_t launch_coarse_apply(const CoarseOp& op, const cplx* x, cplx* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_apply, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, x, y);
+    HH_LAUNCH(k_coarse_apply, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, x, y);
     return hipGetLastError();
 }
-hipError_t launch_coarse_residual(const CoarseOp& op, const cplx* b, const cplx* x, cplx* r,
-                                  hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_residual, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, b, x, r);
-    return hipGetLastError();
-}
-hipError_t launch_coarse_jacobi0(const CoarseOp& op, double wj, const cplx* b, cplx* xo,
-                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_jacobi0, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, wj, b, xo);
-    return hipGetLastError();
-}
-hipError_t launch_coarse_jacobi(const CoarseOp& op, double wj, const cplx* b, const cplx* xi,
-                                cplx* xo, hipStream_t s) {
-    hipLaunchKernelGGL(k_coarse_jacobi, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, wj, b, xi,
-                       xo);
-    return hipGetLastError();
-}
-
 }  // namespace hh

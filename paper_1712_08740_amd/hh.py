@@ -30,12 +30,13 @@ HH_NO_PRECOND = 1
 HH_MAX_COARSE = 4096
 HH_MAX_1D = 1024
 HH_KERNEL_NONE = 0
-HH_KERNEL_STENCIL = 1
-HH_KERNEL_JACOBI = 2
-HH_KERNEL_DOT = 3
-HH_KERNEL_AXPY = 4
-HH_KERNEL_GEMV = 5
-HH_KERNEL_PCR = 6
+HH_KERNEL_APPLY_DOT = 1
+HH_KERNEL_AXPY_DOT = 2
+HH_KERNEL_AXPY_NORM = 3
+HH_KERNEL_PRESMOOTH = 4
+HH_KERNEL_POSTSMOOTH = 5
+HH_KERNEL_GEMV = 6
+HH_KERNEL_PCR = 7
 
 EXPORTED = [
     "hh_create_problem", "hh_set_shift", "hh_workspace_bytes", "hh_solve",
@@ -45,9 +46,10 @@ EXPORTED = [
     "hh_kernel_timer_read",
 ]
 
-KERNEL_IDS = {"none": HH_KERNEL_NONE, "stencil": HH_KERNEL_STENCIL, "jacobi": HH_KERNEL_JACOBI,
-              "dot": HH_KERNEL_DOT, "axpy": HH_KERNEL_AXPY, "gemv": HH_KERNEL_GEMV,
-              "pcr": HH_KERNEL_PCR}
+KERNEL_IDS = {"none": HH_KERNEL_NONE, "apply_dot": HH_KERNEL_APPLY_DOT,
+              "axpy_dot": HH_KERNEL_AXPY_DOT, "axpy_norm": HH_KERNEL_AXPY_NORM,
+              "presmooth": HH_KERNEL_PRESMOOTH, "postsmooth": HH_KERNEL_POSTSMOOTH,
+              "gemv": HH_KERNEL_GEMV, "pcr": HH_KERNEL_PCR}
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_double_p = ctypes.POINTER(ctypes.c_double)

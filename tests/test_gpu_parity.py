@@ -278,3 +278,25 @@ def test_solve_is_bitwise_reproducible(hh):
     b = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
     assert np.array_equal(ua, _np(b.u))
     assert np.array_equal(a.history, b.history)
+
+
+def test_kernel_timer_counts_working_launches(hh):
+    """The dispatch-stamped timer counts one launch per Arnoldi step that did work
+    (steps enqueued ahead and skipped on the device are not counted) and sums the
+    byte model (k + 2) * 16 B per node."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    N = w.slowness.size
+    P.kernel_timer_start("axpy_dot")
+    res = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    launches, ms, nbytes = P.kernel_timer_read()
+    assert launches == res.iterations
+    # step j of a cycle touches k = j + 1 basis vectors
+    ks = []
+    left = res.iterations
+    while left > 0:
+        ks += list(range(1, min(left, w.restart) + 1))
+        left -= w.restart
+    assert nbytes == pytest.approx(sum((k + 2) * 16.0 * N for k in ks), rel=1e-12)
+    assert 0 < ms < 1e3
+    P.kernel_timer_start("none")
