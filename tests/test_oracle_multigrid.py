@@ -25,8 +25,49 @@ def test_level_shapes_of_workload_grids():
     assert mg.level_shapes((9, 9), (1.0, 1.0), 1e-3) == [(9, 9), (5, 5), (3, 3)]
     assert mg.level_shapes((17, 9), (1.0, 1.0), 1e-3) == [(17, 9), (9, 5), (5, 3), (3, 3)]
     assert mg.level_shapes((8, 9), (1.0, 1.0), 1e-3) == [(8, 9), (8, 5), (8, 3)]
-    # the coarse grid keeps >= 2 nodes per shortest wavelength
+    # the coarse grid keeps >= 2 nodes per shortest wavelength ...
     assert mg.level_shapes((33, 33), (1.0, 1.0), np.pi / 4 + 1e-9)[-1] == (17, 17)
+    # ... unless the grid is still too large for the direct coarsest solve
+    assert mg.level_shapes((129, 129), (1.0, 1.0), 10.0, max_coarse=4096) == [
+        (129, 129), (65, 65), (33, 33)]
+    assert mg.level_shapes((129, 129), (1.0, 1.0), 10.0, max_coarse=100) == [
+        (129, 129), (65, 65), (33, 33), (17, 17), (9, 9)]
+    # 401 x 201 at 15 Hz: 2 nodes per wavelength stops at 51 x 101 (5151 > 4096 nodes),
+    # so one more (under-resolved) level follows
+    w = wl.random_field_2d(401, 201, 10.0, seed=2, freq_hz=15.0, src=(200, 5))
+    kmax = w.omega * w.slowness.max()
+    assert mg.level_shapes((201, 401), (10.0, 10.0), kmax) == [
+        (201, 401), (101, 201), (51, 101), (26, 51)]
+
+
+def test_smoothing_weight_per_level():
+    """omega_J = 0.8 where omega*max(m)*max(h) < 2, else 0.5."""
+    w = wl.grf_401x201()
+    V = mg.VCycle(w.slowness, w.omega, 1.0, 0.5, w.h)
+    assert [l.omega_j for l in V.levels[:-1]] == [0.8, 0.8, 0.8]
+    w15 = wl.random_field_2d(401, 201, 10.0, seed=2, freq_hz=15.0, src=(200, 5))
+    V15 = mg.VCycle(w15.slowness, w15.omega, 1.0, 0.5, w15.h)
+    kmax = w15.omega * w15.slowness.max()
+    for lev in V15.levels:
+        expect = 0.8 if kmax * max(lev.spacing) < 2.0 else 0.5
+        assert lev.omega_j == expect
+    assert [l.omega_j for l in V15.levels[:-1]] == [0.8, 0.8, 0.5]
+
+
+def test_under_resolved_levels_need_the_smaller_weight():
+    """With the under-resolved level smoothed at 0.8 the cycle is a poor
+    preconditioner (FGMRES stalls); with the per-level rule it converges."""
+    from oracle import gmres as gm
+    w = wl.random_field_2d(401, 201, 10.0, seed=2, freq_hz=15.0, src=(200, 5))
+    H = op.helmholtz(w.slowness, w.omega, w.alpha, w.h)
+    b = op.weighted_rhs(w.source)
+    V = mg.VCycle(w.slowness, w.omega, 1.0, 0.5, w.h)
+    good = gm.gmres(lambda v: H @ v, b, 1e-6, 30, 150, prec=V)
+    assert good.status == gm.OK
+    for lev in V.levels:
+        lev.omega_j = 0.8
+    bad = gm.gmres(lambda v: H @ v, b, 1e-6, 30, 150, prec=V)
+    assert bad.status == gm.NOT_CONVERGED
 
 
 @pytest.mark.parametrize("fine,halved", [((9, 11), (True, True)), ((9, 8), (True, False)),
@@ -104,7 +145,8 @@ def test_two_grid_error_propagation():
     B = V.as_matrix()
     M = lev0.M.toarray()
     N = M.shape[0]
-    S = np.eye(N) - 0.8 * np.diag(1.0 / np.diag(M)) @ M
+    assert lev0.omega_j == 0.8
+    S = np.eye(N) - lev0.omega_j * np.diag(1.0 / np.diag(M)) @ M
     P = lev0.P.toarray()
     R = lev0.R.toarray()
     Mc = R @ M @ P
@@ -139,3 +181,24 @@ def test_vcycle_converges_on_definite_problem():
         rates.append((np.linalg.norm(b - M @ x) / r0) ** (1 / 8))
     assert max(rates) < 0.15, rates
     assert abs(rates[0] - rates[1]) < 0.05, rates
+
+
+def test_three_level_cycle_uses_each_levels_weight():
+    """Three levels with weights (0.8, 0.5): the cycle matrix B satisfies
+    I - B M0 = S0^2 (I - P0 B1 R0 M0) S0^2 with B1 the two-grid cycle of level 1
+    (its own smoother S1 = I - 0.5 D1^{-1} M1, exact coarsest solve)."""
+    m = wl.smooth_slowness_2d(9, 9, 10.0, 6)
+    V = mg.VCycle(m, 2 * np.pi * 3, 1.0, 0.5, 10.0)
+    assert len(V.levels) == 3
+    V.levels[1].omega_j = 0.5
+    B = V.as_matrix()
+    L0, L1, L2 = V.levels
+    M0, M1, M2 = (L.M.toarray() for L in V.levels)
+    I0, I1 = np.eye(M0.shape[0]), np.eye(M1.shape[0])
+    S0 = I0 - 0.8 * np.diag(1 / np.diag(M0)) @ M0
+    S1 = I1 - 0.5 * np.diag(1 / np.diag(M1)) @ M1
+    P0, R0, P1, R1 = (x.toarray() for x in (L0.P, L0.R, L1.P, L1.R))
+    E1 = S1 @ S1 @ (I1 - P1 @ sla.solve(M2, R1 @ M1)) @ S1 @ S1
+    B1 = (I1 - E1) @ sla.inv(M1)
+    E0 = S0 @ S0 @ (I0 - P0 @ B1 @ R0 @ M0) @ S0 @ S0
+    assert np.abs((I0 - B @ M0) - E0).max() < 1e-10
