@@ -40,7 +40,7 @@ def parse():
                     choices=["grf_401x201", "layered_1d_well"])
     ap.add_argument("--kernel", default="axpy_dot",
                     help="kernel class for the roofline figure (apply_dot, axpy_dot, axpy_norm, "
-                         "presmooth, postsmooth, gemv, pcr)")
+                         "vc_down, vc_up, gemv, pcr)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample")

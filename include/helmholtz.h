@@ -17,11 +17,13 @@
  * weights W, which makes H and M exactly complex-symmetric. M^{-1} is applied
  * exactly in 1D (tridiagonal solve by parallel cyclic reduction) and
  * approximately in 2D by one V(2,2) multigrid cycle: omega-Jacobi smoothing
- * (weight 0.8), full-weighting restriction R = P^T / 2^{d_c}, bilinear
- * prolongation P, Galerkin coarse operators R M P, and a direct (explicit
- * inverse) solve on the coarsest grid. A dimension of n nodes and spacing h is
- * coarsened to (n-1)/2+1 nodes when n-1 is even, (n-1)/2 >= 2 and
- * omega * max(m) * 2h <= pi (two or more nodes per shortest wavelength).
+ * (weight 0.8, or 0.5 on levels with omega * max(m) * max(h) >= 2),
+ * full-weighting restriction R = P^T / 2^{d_c}, bilinear prolongation P,
+ * Galerkin coarse operators R M P, and a direct (explicit inverse) solve on the
+ * coarsest grid. A dimension of n nodes and spacing h is coarsened to
+ * (n-1)/2+1 nodes when n-1 is even, (n-1)/2 >= 2, and either
+ * omega * max(m) * 2h <= pi (two or more nodes per shortest wavelength) or the
+ * grid still has more than HH_MAX_COARSE nodes.
  *
  * Layout: real arrays are float64; complex arrays are complex128 stored as
  * interleaved (re, im) pairs. 1D grids have n nodes; 2D grids are stored
@@ -185,8 +187,10 @@ enum hh_kernel_id {
     HH_KERNEL_APPLY_DOT  = 1,  /* w = H z and the first projections V^H w: (40 + 16k) B/node */
     HH_KERNEL_AXPY_DOT   = 2,  /* w -= V h and the second projections: (k + 2) * 16 B/node   */
     HH_KERNEL_AXPY_NORM  = 3,  /* w -= V h and ||w||^2: (k + 2) * 16 B/node                  */
-    HH_KERNEL_PRESMOOTH  = 4,  /* fine-grid two Jacobi sweeps from zero: 56 B/node           */
-    HH_KERNEL_POSTSMOOTH = 5,  /* fine-grid last Jacobi sweep: 56 B/node                     */
+    HH_KERNEL_VC_DOWN    = 4,  /* fine-grid V-cycle down leg (2 sweeps, residual, restriction):
+                                  60 B/node (b, m^2 in; v, x2 out; restricted rhs 1/4)     */
+    HH_KERNEL_VC_UP      = 5,  /* fine-grid V-cycle up leg (prolongation, 2 sweeps):
+                                  60 B/node (x2, b, m^2 in, correction 1/4; z out)         */
     HH_KERNEL_GEMV       = 6,  /* coarsest dense inverse times vector: (n^2 + 2n) * 16 B     */
     HH_KERNEL_PCR        = 7   /* 1D tridiagonal solve: 56 B/node                            */
 };

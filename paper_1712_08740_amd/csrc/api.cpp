@@ -48,7 +48,9 @@ int fail(int code, const std::string& msg) {
         if (r_ != HH_OK) return r_;     \
     } while (0)
 
-constexpr double kJacobiWeight = 0.8;
+constexpr double kJacobiWeight = 0.8;         // resolved levels
+constexpr double kJacobiWeightCoarse = 0.5;   // levels with omega*max(m)*max(h) >= kKhSmooth
+constexpr double kKhSmooth = 2.0;
 constexpr int kMaxRestart = 1024;
 constexpr int kLookahead = 2;          // Arnoldi steps enqueued ahead of the device
 constexpr double kStallSeconds = 120.0;
@@ -59,6 +61,7 @@ struct LevelData {
     int nz = 0, nx = 0;
     double hz = 0, hx = 0;
     int halve_z = 0, halve_x = 0;   // halving flags towards the next coarser level
+    double wj = kJacobiWeight;      // Jacobi weight of this level's smoother
     cplx* C = nullptr;              // 9-point Galerkin operator (levels >= 1)
     int64_t size() const { return (int64_t)nz * nx; }
 };
@@ -237,7 +240,7 @@ T* at(void* base, size_t off) {
 // ---------------------------------------------------------------------------
 // preconditioner
 // ---------------------------------------------------------------------------
-// One V(2,2) cycle on level l >= 1: ec_l = V(l, bc_l).
+// One V(2,2) cycle on level l >= 1: ec_l = V(l, bc_l), one kernel per leg.
 int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* active,
                   hipStream_t s) {
     const int nl = (int)p->levels.size();
@@ -252,14 +255,12 @@ int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* 
     const LevelData& lv = p->levels[l];
     const LevelData& nx = p->levels[l + 1];
     const CoarseOp A = coarse_op(lv);
-    cplx* t = at<cplx>(ws, L.t[l]);
-    HIPCHK(launch_vc_coarse_presmooth(A, kJacobiWeight, b, x, active, s));
-    HIPCHK(launch_vc_coarse_resid_restrict(A, lv.halve_z, lv.halve_x, b, x, nx.nz, nx.nx,
-                                           at<cplx>(ws, L.bc[l + 1]), active, s));
+    cplx* x2 = at<cplx>(ws, L.t[l]);
+    HIPCHK(launch_vc_coarse_down(A, lv.wj, b, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+                                 at<cplx>(ws, L.bc[l + 1]), active, s));
     CHK(vcycle_coarse(p, L, ws, l + 1, active, s));
-    HIPCHK(launch_vc_coarse_prolong_post1(A, kJacobiWeight, lv.halve_z, lv.halve_x, b, x,
-                                          at<cplx>(ws, L.ec[l + 1]), nx.nx, t, active, s));
-    HIPCHK(launch_vc_coarse_post2(A, kJacobiWeight, b, t, x, active, s));
+    HIPCHK(launch_vc_coarse_up(A, lv.wj, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[l + 1]),
+                               nx.nx, x, active, s));
     return HH_OK;
 }
 
@@ -290,17 +291,15 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const S
     }
     const LevelData& lv = p->levels[0];
     const LevelData& nx = p->levels[1];
-    cplx* t = at<cplx>(ws, L.t[0]);
-    TIMED(HH_KERNEL_PRESMOOTH, 56.0 * N,
-          launch_vc_fine_presmooth(M, kJacobiWeight, src, scale, vout, z, active, s));
+    cplx* x2 = at<cplx>(ws, L.t[0]);
+    TIMED(HH_KERNEL_VC_DOWN, 60.0 * N,
+          launch_vc_fine_down(M, lv.wj, src, scale, vout, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+                              at<cplx>(ws, L.bc[1]), active, s));
     const cplx* b = vout ? vout : src;
-    HIPCHK(launch_vc_fine_resid_restrict(M, lv.halve_z, lv.halve_x, b, z, nx.nz, nx.nx,
-                                         at<cplx>(ws, L.bc[1]), active, s));
     CHK(vcycle_coarse(p, L, ws, 1, active, s));
-    HIPCHK(launch_vc_fine_prolong_post1(M, kJacobiWeight, lv.halve_z, lv.halve_x, b, z,
-                                        at<cplx>(ws, L.ec[1]), nx.nx, t, active, s));
-    TIMED(HH_KERNEL_POSTSMOOTH, 56.0 * N,
-          launch_vc_fine_post2(M, kJacobiWeight, b, t, z, active, s));
+    TIMED(HH_KERNEL_VC_UP, 60.0 * N,
+          launch_vc_fine_up(M, lv.wj, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[1]), nx.nx,
+                            z, active, s));
     return HH_OK;
 }
 
@@ -330,8 +329,12 @@ int build_hierarchy(hh_problem_s* p) {
     const double kmax = p->omega * p->mmax;
     for (;;) {
         LevelData& cur = p->levels.back();
+        cur.wj = kmax * std::fmax(cur.hz, cur.hx) < kKhSmooth ? kJacobiWeight : kJacobiWeightCoarse;
+        // keep two nodes per shortest wavelength, unless the grid is still too
+        // large for the direct coarsest solve
+        const bool big = cur.size() > HH_MAX_COARSE;
         auto halves = [&](int n, double h) {
-            return (n - 1) % 2 == 0 && (n - 1) / 2 >= 2 && kmax * 2.0 * h <= M_PI;
+            return (n - 1) % 2 == 0 && (n - 1) / 2 >= 2 && (kmax * 2.0 * h <= M_PI || big);
         };
         const int hz = halves(cur.nz, cur.hz), hx = halves(cur.nx, cur.hx);
         if (!hz && !hx) break;

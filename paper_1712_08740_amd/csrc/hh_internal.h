@@ -219,30 +219,23 @@ hipError_t launch_normalize_pred(const cplx* w, const SolveState* st, cplx* v, i
 hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
                              double tol, HostRecord* rec, double* hist, hipStream_t s);
 
-// ---- fused V-cycle kernels (vcycle.hip) -------------------------------------
-hipError_t launch_vc_fine_presmooth(const FineOp& op, double wj, const cplx* src,
-                                    const double* scale, cplx* bout, cplx* xo, const int* active,
-                                    hipStream_t s);
-hipError_t launch_vc_fine_resid_restrict(const FineOp& op, int hz, int hx, const cplx* b,
-                                         const cplx* x, int nzc, int nxc, cplx* bc,
-                                         const int* active, hipStream_t s);
-hipError_t launch_vc_fine_prolong_post1(const FineOp& op, double wj, int hz, int hx,
-                                        const cplx* b, const cplx* x, const cplx* e, int nxc,
-                                        cplx* xo, const int* active, hipStream_t s);
-hipError_t launch_vc_fine_post2(const FineOp& op, double wj, const cplx* b, const cplx* x,
-                                cplx* xo, const int* active, hipStream_t s);
-hipError_t launch_vc_coarse_presmooth(const CoarseOp& op, double wj, const cplx* b, cplx* xo,
-                                      const int* active, hipStream_t s);
-hipError_t launch_vc_coarse_resid_restrict(const CoarseOp& op, int hz, int hx, const cplx* b,
-                                           const cplx* x, int nzc, int nxc, cplx* bc,
-                                           const int* active, hipStream_t s);
-hipError_t launch_vc_coarse_prolong_post1(const CoarseOp& op, double wj, int hz, int hx,
-                                          const cplx* b, const cplx* x, const cplx* e, int nxc,
-                                          cplx* xo, const int* active, hipStream_t s);
-hipError_t launch_vc_coarse_post2(const CoarseOp& op, double wj, const cplx* b, const cplx* x,
-                                  cplx* xo, const int* active, hipStream_t s);
+// ---- V-cycle kernels (vcycle_tiled.hip, coarsest.hip) ------------------------
 hipError_t launch_vc_gemv(int n, const cplx* A, const cplx* x, cplx* y, const int* active,
                           hipStream_t s);
+// temporally blocked legs (vcycle_tiled.hip): down = two pre-sweeps from zero,
+// residual and restriction; up = prolongation and two post-sweeps
+hipError_t launch_vc_fine_down(const FineOp& op, double wj, const cplx* src, const double* scale,
+                               cplx* bout, cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc,
+                               const int* active, hipStream_t s);
+hipError_t launch_vc_coarse_down(const CoarseOp& op, double wj, const cplx* b, cplx* x2, int hz,
+                                 int hx, int nzc, int nxc, cplx* bc, const int* active,
+                                 hipStream_t s);
+hipError_t launch_vc_fine_up(const FineOp& op, double wj, int hz, int hx, const cplx* b,
+                             const cplx* x2, const cplx* e, int nxc, cplx* out, const int* active,
+                             hipStream_t s);
+hipError_t launch_vc_coarse_up(const CoarseOp& op, double wj, int hz, int hx, const cplx* b,
+                               const cplx* x2, const cplx* e, int nxc, cplx* out,
+                               const int* active, hipStream_t s);
 // PCR with the normalisation of the Arnoldi vector folded in (vout = s*src, x = M^{-1} vout)
 hipError_t launch_pcr_norm(const FineOp& op, const cplx* src, const double* scale, cplx* vout,
                            cplx* x, const int* active, hipStream_t s);

@@ -105,8 +105,9 @@ __device__ __forceinline__ void block_dots(const cplx* V, int64_t n, int k, bool
 
 __device__ __forceinline__ bool off(const int* active) { return active && *active == 0; }
 
-// w = H z (fine operator) and the first projections V^H w
-template <int NDIM>
+// w = H z (fine operator) and the first projections V^H w; for k <= KMAX the
+// basis values are loaded up front (all in flight together)
+template <int NDIM, int KMAX>
 __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const cplx* __restrict__ z,
                                                    cplx* __restrict__ w,
                                                    const cplx* __restrict__ V, int k,
@@ -129,22 +130,41 @@ __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const cplx* __rest
     const bool valid = ix < op.nx && iz < op.nz;
     const int64_t n = (int64_t)op.nz * op.nx;
     const int64_t p = valid ? (int64_t)iz * op.nx + ix : 0;
+    cplx v[KMAX > 0 ? KMAX : 1];
+    if (KMAX > 0) {
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i)
+            v[i] = (valid && i < k) ? V[(int64_t)i * n + p] : mk(0.0, 0.0);
+    }
     cplx wp = mk(0.0, 0.0);
     if (valid) {
         const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
-        cplx sx = mk(0.0, 0.0);
-        if (ix > 0) sx = cadd(sx, z[p - 1]);
-        if (ix < op.nx - 1) sx = cadd(sx, z[p + 1]);
-        wp = csub(cmul(c.diag, z[p]), cscale(sx, c.cx));
+        const cplx zW = z[ix > 0 ? p - 1 : p], zE = z[ix < op.nx - 1 ? p + 1 : p];
+        const cplx zp = z[p];
+        cplx sx = cadd(ix > 0 ? zW : mk(0.0, 0.0), ix < op.nx - 1 ? zE : mk(0.0, 0.0));
+        wp = csub(cmul(c.diag, zp), cscale(sx, c.cx));
         if (NDIM == 2) {
-            cplx sz = mk(0.0, 0.0);
-            if (iz > 0) sz = cadd(sz, z[p - op.nx]);
-            if (iz < op.nz - 1) sz = cadd(sz, z[p + op.nx]);
+            const cplx zN = z[iz > 0 ? p - op.nx : p], zS = z[iz < op.nz - 1 ? p + op.nx : p];
+            cplx sz = cadd(iz > 0 ? zN : mk(0.0, 0.0), iz < op.nz - 1 ? zS : mk(0.0, 0.0));
             wp = csub(wp, cscale(sz, c.cz));
         }
         w[p] = wp;
     }
-    block_dots(V, n, k, valid, p, wp, partial, nb, blk, lds, tid);
+    if (KMAX > 0) {
+#pragma unroll
+        for (int c0 = 0; c0 < KMAX; c0 += KC) {
+            if (c0 >= k) break;
+            cplx d[KC];
+#pragma unroll
+            for (int c = 0; c < KC; ++c) d[c] = cmulc(v[c0 + c], wp);
+            cplx sum;
+            int idx;
+            block_multi_sum(d, lds, tid, &sum, &idx);
+            if (idx >= 0 && c0 + idx < k) partial[(int64_t)(c0 + idx) * nb + blk] = sum;
+        }
+    } else {
+        block_dots(V, n, k, valid, p, wp, partial, nb, blk, lds, tid);
+    }
 }
 
 // plain projections V^H w (for the stand-alone orthogonalisation entry point)
@@ -360,18 +380,27 @@ __global__ void __launch_bounds__(256) k_givens_step(SolveState* st, const cplx*
                                                      HostRecord* rec, double* hist) {
     if (st->active == 0) return;
     __shared__ double sh[4];
+    __shared__ cplx scol[1026];
+    __shared__ double scs[1024];
+    __shared__ cplx ssn[1024];
     const double hn2 = block_sum_partials(partial, nb, sh);
-    if (threadIdx.x != 0) return;
     const int j = st->j;
+    // stage the column and the previous rotations with parallel loads
+    for (int i = threadIdx.x; i <= j; i += 256) scol[i] = cadd(h1[i], h2[i]);
+    for (int i = threadIdx.x; i < j; i += 256) {
+        scs[i] = cs[i];
+        ssn[i] = sn[i];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
     const int ld = st->m + 1;
-    cplx* col = R + (int64_t)j * ld;
-    for (int i = 0; i <= j; ++i) col[i] = cadd(h1[i], h2[i]);
+    cplx* col = scol;
     const double hn = sqrt(hn2);
     col[j + 1] = mk(hn, 0.0);
     for (int i = 0; i < j; ++i) {
         const cplx p = col[i], q = col[i + 1];
-        col[i] = cadd(cscale(p, cs[i]), cmul(sn[i], q));
-        col[i + 1] = csub(cscale(q, cs[i]), cmulc(sn[i], p));
+        col[i] = cadd(cscale(p, scs[i]), cmul(ssn[i], q));
+        col[i + 1] = csub(cscale(q, scs[i]), cmulc(ssn[i], p));
     }
     const cplx a = col[j];
     double c;
@@ -390,6 +419,8 @@ __global__ void __launch_bounds__(256) k_givens_step(SolveState* st, const cplx*
     sn[j] = s;
     col[j] = cadd(cscale(a, c), cscale(s, hn));
     col[j + 1] = mk(0.0, 0.0);
+    cplx* Rcol = R + (int64_t)j * ld;
+    for (int i = 0; i <= j + 1; ++i) Rcol[i] = col[i];
     const cplx gj = g[j];
     g[j + 1] = csub(mk(0.0, 0.0), cmulc(s, gj));
     g[j] = cscale(gj, c);
@@ -528,14 +559,28 @@ hipError_t launch_check_slowness(const double* m, int64_t n, double* m2, int* fl
     return hipGetLastError();
 }
 
+template <int NDIM>
+static void apply_dot_dispatch(dim3 g, dim3 b, const FineOp& op, const cplx* z, cplx* w,
+                               const cplx* V, int k, cplx* partial, const int* active,
+                               hipStream_t s) {
+    if (k <= 8)
+        HH_LAUNCH((k_apply_dot<NDIM, 8>), g, b, 0, s, op, z, w, V, k, partial, active);
+    else if (k <= 16)
+        HH_LAUNCH((k_apply_dot<NDIM, 16>), g, b, 0, s, op, z, w, V, k, partial, active);
+    else if (k <= 32)
+        HH_LAUNCH((k_apply_dot<NDIM, 32>), g, b, 0, s, op, z, w, V, k, partial, active);
+    else
+        HH_LAUNCH((k_apply_dot<NDIM, 0>), g, b, 0, s, op, z, w, V, k, partial, active);
+}
+
 hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx* V, int k,
                             cplx* partial, const int* active, hipStream_t s) {
     if (op.ndim == 2)
-        HH_LAUNCH(k_apply_dot<2>, dim3((op.nx + 63) / 64, (op.nz + 3) / 4), dim3(64, 4), 0,
-                           s, op, z, w, V, k, partial, active);
+        apply_dot_dispatch<2>(dim3((op.nx + 63) / 64, (op.nz + 3) / 4), dim3(64, 4), op, z, w, V,
+                              k, partial, active, s);
     else
-        HH_LAUNCH(k_apply_dot<1>, dim3((op.nx + 255) / 256), dim3(256), 0, s, op, z, w, V,
-                           k, partial, active);
+        apply_dot_dispatch<1>(dim3((op.nx + 255) / 256), dim3(256), op, z, w, V, k, partial,
+                              active, s);
     return hipGetLastError();
 }
 int apply_blocks(const FineOp& op) {

@@ -1,0 +1,349 @@
+// Temporally blocked V-cycle legs: one kernel per level and direction.
+//
+//   down (level l -> l+1):  x1 = w D^{-1} b,  x2 = x1 + w D^{-1}(b - M x1),
+//                           r = b - M x2,     b_c = R r
+//   up   (level l+1 -> l):  x' = x2 + P e,    x3 = x' + w D^{-1}(b - M x'),
+//                           x4 = x3 + w D^{-1}(b - M x3)
+//
+// A block owns a tile and stages the data of the tile plus the halo the
+// sweeps need in LDS: each sweep shrinks the region by one node, so the
+// intermediate iterates never touch global memory. Nodes of the region that
+// lie outside the grid hold 0 and have no coupling to grid nodes.
+//
+// The operator of a level is a policy: Fine5 (level 0: the matrix-free
+// 5-point stencil of M with absorbing rows, coefficients from m^2) or Coarse9
+// (Galerkin levels: 9 complex coefficient planes).
+#include "hh_internal.h"
+
+namespace hh {
+
+namespace {
+
+constexpr int NT = 128;    // threads per block
+
+__device__ __forceinline__ bool inactive(const int* active) { return active && *active == 0; }
+
+// Row of the 5-point fine operator: a_p = diag, couplings -cx (x) and -cz (z).
+struct Row5 {
+    cplx diag;
+    double cx, cz;
+};
+
+struct Fine5 {
+    FineOp op;
+    __host__ __device__ int nz() const { return op.nz; }
+    __host__ __device__ int nx() const { return op.nx; }
+    typedef Row5 Row;
+    __device__ __forceinline__ Row row(int iz, int ix) const {
+        const Coef5 c = fine_coefs(op, iz, ix, op.m2[(int64_t)iz * op.nx + ix]);
+        Row r;
+        r.diag = c.diag;
+        r.cx = c.cx;
+        r.cz = c.cz;
+        return r;
+    }
+    __device__ __forceinline__ cplx diag(int iz, int ix) const {
+        return fine_coefs(op, iz, ix, op.m2[(int64_t)iz * op.nx + ix]).diag;
+    }
+    // (A x)_q from an LDS field s with row stride ld at local index i
+    __device__ __forceinline__ cplx apply(const Row& r, const cplx* s, int i, int ld) const {
+        const cplx sx = cadd(s[i - 1], s[i + 1]);
+        const cplx sz = cadd(s[i - ld], s[i + ld]);
+        return csub(csub(cmul(r.diag, s[i]), cscale(sx, r.cx)), cscale(sz, r.cz));
+    }
+};
+
+// Row of a 9-point Galerkin operator: coefficient t = (dz+1)*3 + (dx+1).
+struct Row9 {
+    cplx a[9];
+    cplx diag;
+};
+
+struct Coarse9 {
+    CoarseOp op;
+    __host__ __device__ int nz() const { return op.nz; }
+    __host__ __device__ int nx() const { return op.nx; }
+    typedef Row9 Row;
+    __device__ __forceinline__ Row row(int iz, int ix) const {
+        const int64_t N = (int64_t)op.nz * op.nx;
+        const int64_t p = (int64_t)iz * op.nx + ix;
+        Row r;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) r.a[t] = op.C[t * N + p];
+        r.diag = r.a[4];
+        return r;
+    }
+    __device__ __forceinline__ cplx diag(int iz, int ix) const {
+        return op.C[4 * (int64_t)op.nz * op.nx + (int64_t)iz * op.nx + ix];
+    }
+    __device__ __forceinline__ cplx apply(const Row& r, const cplx* s, int i, int ld) const {
+        cplx acc = mk(0.0, 0.0);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc = cadd(acc, cmul(r.a[t], s[i + (t / 3 - 1) * ld + (t % 3 - 1)]));
+        return acc;
+    }
+};
+
+__device__ __forceinline__ bool in_grid(int z, int x, int nz, int nx) {
+    return z >= 0 && z < nz && x >= 0 && x < nx;
+}
+
+// ---------------------------------------------------------------------------
+// down leg. A block owns a TCX x TCZ tile of coarse nodes. Along a halved
+// axis the fine region of the residual is [2c0 - 1, 2(c0 + TC) - 1], along
+// an unhalved axis [c0, c0 + TC - 1]; x2 needs one more node on each side,
+// x1 (and b, D) two more.
+// ---------------------------------------------------------------------------
+template <class OP, int TCX, int TCZ>
+__global__ void __launch_bounds__(NT) k_down(OP A, double wj, const cplx* __restrict__ src,
+                                             const double* __restrict__ scale,
+                                             cplx* __restrict__ bout, cplx* __restrict__ x2out,
+                                             int hz, int hx, int nzc, int nxc,
+                                             cplx* __restrict__ bc, double rscale,
+                                             const int* __restrict__ active) {
+    if (inactive(active)) return;
+    constexpr int W1X = 2 * TCX + 5, W1Z = 2 * TCZ + 5;   // largest x1 region
+    __shared__ cplx sb[W1X * W1Z];
+    __shared__ cplx sd[W1X * W1Z];
+    __shared__ cplx s1[W1X * W1Z];
+    __shared__ cplx s2[W1X * W1Z];
+    const int nz = A.nz(), nx = A.nx();
+    const int cx0 = blockIdx.x * TCX, cz0 = blockIdx.y * TCZ;
+    const int rlx = hx ? 2 * cx0 - 1 : cx0, rhx = hx ? 2 * (cx0 + TCX) - 1 : cx0 + TCX - 1;
+    const int rlz = hz ? 2 * cz0 - 1 : cz0, rhz = hz ? 2 * (cz0 + TCZ) - 1 : cz0 + TCZ - 1;
+    const int ox = rlx - 2, oz = rlz - 2;                  // origin of the x1 region
+    const int wx = rhx - rlx + 5, wz = rhz - rlz + 5;      // x1 region size (row stride wx)
+    const int olx = hx ? 2 * cx0 : cx0, ohx = hx ? 2 * (cx0 + TCX) - 1 : cx0 + TCX - 1;
+    const int olz = hz ? 2 * cz0 : cz0, ohz = hz ? 2 * (cz0 + TCZ) - 1 : cz0 + TCZ - 1;
+    const double s = scale ? scale[0] : 1.0;
+    const int n1 = wx * wz;
+    constexpr int SL1 = (W1X * W1Z + NT - 1) / NT;
+    // phase 1: b, D and x1 on the x1 region
+#pragma unroll
+    for (int k = 0; k < SL1; ++k) {
+        const int i = threadIdx.x + k * NT;
+        if (i >= n1) break;
+        const int qz = oz + i / wx, qx = ox + i % wx;
+        cplx bq = mk(0.0, 0.0), dq = mk(1.0, 0.0), x1 = mk(0.0, 0.0);
+        if (in_grid(qz, qx, nz, nx)) {
+            const int64_t q = (int64_t)qz * nx + qx;
+            bq = cscale(src[q], s);
+            dq = A.diag(qz, qx);
+            x1 = cscale(cdiv(bq, dq), wj);
+            if (bout && qz >= olz && qz <= ohz && qx >= olx && qx <= ohx) bout[q] = bq;
+        }
+        sb[i] = bq;
+        sd[i] = dq;
+        s1[i] = x1;
+    }
+    __syncthreads();
+    // phase 2: x2 on the x1 region shrunk by one node (stored at the same local index)
+    const int w2x = wx - 2, n2 = w2x * (wz - 2);
+#pragma unroll
+    for (int k = 0; k < SL1; ++k) {
+        const int j = threadIdx.x + k * NT;
+        if (j >= n2) break;
+        const int lz = 1 + j / w2x, lx = 1 + j % w2x;
+        const int i = lz * wx + lx;
+        const int qz = oz + lz, qx = ox + lx;
+        cplx x2 = mk(0.0, 0.0);
+        if (in_grid(qz, qx, nz, nx)) {
+            const typename OP::Row r = A.row(qz, qx);
+            const cplx ax = A.apply(r, s1, i, wx);
+            x2 = cadd(s1[i], cscale(cdiv(csub(sb[i], ax), sd[i]), wj));
+            if (qz >= olz && qz <= ohz && qx >= olx && qx <= ohx)
+                x2out[(int64_t)qz * nx + qx] = x2;
+        }
+        s2[i] = x2;
+    }
+    __syncthreads();
+    // phase 3: residual on the region shrunk by two nodes (into s1, no longer needed)
+    const int w3x = wx - 4, n3 = w3x * (wz - 4);
+#pragma unroll
+    for (int k = 0; k < SL1; ++k) {
+        const int j = threadIdx.x + k * NT;
+        if (j >= n3) break;
+        const int lz = 2 + j / w3x, lx = 2 + j % w3x;
+        const int i = lz * wx + lx;
+        const int qz = oz + lz, qx = ox + lx;
+        cplx r = mk(0.0, 0.0);
+        if (in_grid(qz, qx, nz, nx)) {
+            const typename OP::Row row = A.row(qz, qx);
+            r = csub(sb[i], A.apply(row, s2, i, wx));
+        }
+        s1[i] = r;
+    }
+    __syncthreads();
+    // phase 4: b_c = R r for the tile's coarse nodes
+    for (int t = threadIdx.x; t < TCX * TCZ; t += NT) {
+        const int Iz = cz0 + t / TCX, Ix = cx0 + t % TCX;
+        if (Iz >= nzc || Ix >= nxc) continue;
+        const int lz = (hz ? 2 * Iz : Iz) - oz, lx = (hx ? 2 * Ix : Ix) - ox;
+        cplx acc = mk(0.0, 0.0);
+#pragma unroll
+        for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                if ((dz != 0 && !hz) || (dx != 0 && !hx)) continue;
+                const double w = (dz == 0 ? 1.0 : 0.5) * (dx == 0 ? 1.0 : 0.5);
+                acc = cadd(acc, cscale(s1[(lz + dz) * wx + (lx + dx)], w));
+            }
+        }
+        bc[(int64_t)Iz * nxc + Ix] = cscale(acc, rscale);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// up leg. A block owns a TX x TZ tile of fine nodes: x' on the tile plus two
+// nodes, x3 on the tile plus one, x4 on the tile.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void interp2(int q, int halved, int& J0, int& J1, double& w0,
+                                        double& w1) {
+    if (!halved) { J0 = J1 = q; w0 = 1.0; w1 = 0.0; return; }
+    if ((q & 1) == 0) { J0 = J1 = q >> 1; w0 = 1.0; w1 = 0.0; return; }
+    J0 = (q - 1) >> 1; J1 = J0 + 1; w0 = w1 = 0.5;
+}
+
+template <class OP, int TX, int TZ>
+__global__ void __launch_bounds__(NT) k_up(OP A, double wj, int hz, int hx,
+                                           const cplx* __restrict__ b,
+                                           const cplx* __restrict__ x2,
+                                           const cplx* __restrict__ e, int nxc,
+                                           cplx* __restrict__ out,
+                                           const int* __restrict__ active) {
+    if (inactive(active)) return;
+    constexpr int WX = TX + 4, WZ = TZ + 4;
+    __shared__ cplx sp[WX * WZ];     // x' (tile + 2)
+    __shared__ cplx s3[WX * WZ];     // x3 (tile + 1)
+    const int nz = A.nz(), nx = A.nx();
+    const int fx0 = blockIdx.x * TX, fz0 = blockIdx.y * TZ;
+    const int ox = fx0 - 2, oz = fz0 - 2;
+    constexpr int SL = (WX * WZ + NT - 1) / NT;
+    // phase 1: x' = x2 + P e
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int i = threadIdx.x + k * NT;
+        if (i >= WX * WZ) break;
+        const int qz = oz + i / WX, qx = ox + i % WX;
+        cplx v = mk(0.0, 0.0);
+        if (in_grid(qz, qx, nz, nx)) {
+            int z0, z1, x0, x1;
+            double wz0, wz1, wx0, wx1;
+            interp2(qz, hz, z0, z1, wz0, wz1);
+            interp2(qx, hx, x0, x1, wx0, wx1);
+            const cplx e00 = e[(int64_t)z0 * nxc + x0], e01 = e[(int64_t)z0 * nxc + x1];
+            const cplx e10 = e[(int64_t)z1 * nxc + x0], e11 = e[(int64_t)z1 * nxc + x1];
+            const cplx pe = cadd(cadd(cscale(e00, wz0 * wx0), cscale(e01, wz0 * wx1)),
+                                 cadd(cscale(e10, wz1 * wx0), cscale(e11, wz1 * wx1)));
+            v = cadd(x2[(int64_t)qz * nx + qx], pe);
+        }
+        sp[i] = v;
+    }
+    __syncthreads();
+    // phase 2: x3 on the tile plus one node
+    constexpr int W3X = TX + 2, W3Z = TZ + 2;
+    constexpr int SL3 = (W3X * W3Z + NT - 1) / NT;
+#pragma unroll
+    for (int k = 0; k < SL3; ++k) {
+        const int j = threadIdx.x + k * NT;
+        if (j >= W3X * W3Z) break;
+        const int lz = 1 + j / W3X, lx = 1 + j % W3X;
+        const int i = lz * WX + lx;
+        const int qz = oz + lz, qx = ox + lx;
+        cplx v = mk(0.0, 0.0);
+        if (in_grid(qz, qx, nz, nx)) {
+            const typename OP::Row r = A.row(qz, qx);
+            const cplx ax = A.apply(r, sp, i, WX);
+            v = cadd(sp[i], cscale(cdiv(csub(b[(int64_t)qz * nx + qx], ax), r.diag), wj));
+        }
+        s3[i] = v;
+    }
+    __syncthreads();
+    // phase 3: x4 on the tile
+    constexpr int SL4 = (TX * TZ + NT - 1) / NT;
+#pragma unroll
+    for (int k = 0; k < SL4; ++k) {
+        const int j = threadIdx.x + k * NT;
+        if (j >= TX * TZ) break;
+        const int lz = 2 + j / TX, lx = 2 + j % TX;
+        const int i = lz * WX + lx;
+        const int qz = oz + lz, qx = ox + lx;
+        if (!in_grid(qz, qx, nz, nx)) continue;
+        const typename OP::Row r = A.row(qz, qx);
+        const cplx ax = A.apply(r, s3, i, WX);
+        const int64_t q = (int64_t)qz * nx + qx;
+        out[q] = cadd(s3[i], cscale(cdiv(csub(b[q], ax), r.diag), wj));
+    }
+}
+
+inline double inv2dc(int hz, int hx) { return 1.0 / (double)((hz ? 2 : 1) * (hx ? 2 : 1)); }
+
+// tiles: large grids use larger tiles (less halo work), small grids smaller
+// tiles (more blocks in flight)
+constexpr int64_t kBigLevel = 40000;
+
+template <class OP>
+hipError_t down_dispatch(const OP& A, double wj, const cplx* src, const double* scale, cplx* bout,
+                         cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc, const int* active,
+                         hipStream_t s) {
+    const double rs = inv2dc(hz, hx);
+    if ((int64_t)A.nz() * A.nx() >= kBigLevel) {
+        const dim3 g((nxc + 15) / 16, (nzc + 3) / 4);
+        HH_LAUNCH((k_down<OP, 16, 4>), g, dim3(NT), 0, s, A, wj, src, scale, bout, x2, hz, hx,
+                  nzc, nxc, bc, rs, active);
+    } else {
+        const dim3 g((nxc + 7) / 8, (nzc + 3) / 4);
+        HH_LAUNCH((k_down<OP, 8, 4>), g, dim3(NT), 0, s, A, wj, src, scale, bout, x2, hz, hx, nzc,
+                  nxc, bc, rs, active);
+    }
+    return hipGetLastError();
+}
+
+template <class OP>
+hipError_t up_dispatch(const OP& A, double wj, int hz, int hx, const cplx* b, const cplx* x2,
+                       const cplx* e, int nxc, cplx* out, const int* active, hipStream_t s) {
+    if ((int64_t)A.nz() * A.nx() >= kBigLevel) {
+        const dim3 g((A.nx() + 31) / 32, (A.nz() + 7) / 8);
+        HH_LAUNCH((k_up<OP, 32, 8>), g, dim3(NT), 0, s, A, wj, hz, hx, b, x2, e, nxc, out, active);
+    } else {
+        const dim3 g((A.nx() + 15) / 16, (A.nz() + 3) / 4);
+        HH_LAUNCH((k_up<OP, 16, 4>), g, dim3(NT), 0, s, A, wj, hz, hx, b, x2, e, nxc, out, active);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_vc_fine_down(const FineOp& op, double wj, const cplx* src, const double* scale,
+                               cplx* bout, cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc,
+                               const int* active, hipStream_t s) {
+    Fine5 A;
+    A.op = op;
+    return down_dispatch(A, wj, src, scale, bout, x2, hz, hx, nzc, nxc, bc, active, s);
+}
+
+hipError_t launch_vc_coarse_down(const CoarseOp& op, double wj, const cplx* b, cplx* x2, int hz,
+                                 int hx, int nzc, int nxc, cplx* bc, const int* active,
+                                 hipStream_t s) {
+    Coarse9 A;
+    A.op = op;
+    return down_dispatch(A, wj, b, nullptr, nullptr, x2, hz, hx, nzc, nxc, bc, active, s);
+}
+
+hipError_t launch_vc_fine_up(const FineOp& op, double wj, int hz, int hx, const cplx* b,
+                             const cplx* x2, const cplx* e, int nxc, cplx* out, const int* active,
+                             hipStream_t s) {
+    Fine5 A;
+    A.op = op;
+    return up_dispatch(A, wj, hz, hx, b, x2, e, nxc, out, active, s);
+}
+
+hipError_t launch_vc_coarse_up(const CoarseOp& op, double wj, int hz, int hx, const cplx* b,
+                               const cplx* x2, const cplx* e, int nxc, cplx* out,
+                               const int* active, hipStream_t s) {
+    Coarse9 A;
+    A.op = op;
+    return up_dispatch(A, wj, hz, hx, b, x2, e, nxc, out, active, s);
+}
+
+}  // namespace hh

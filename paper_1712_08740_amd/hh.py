@@ -33,8 +33,8 @@ HH_KERNEL_NONE = 0
 HH_KERNEL_APPLY_DOT = 1
 HH_KERNEL_AXPY_DOT = 2
 HH_KERNEL_AXPY_NORM = 3
-HH_KERNEL_PRESMOOTH = 4
-HH_KERNEL_POSTSMOOTH = 5
+HH_KERNEL_VC_DOWN = 4
+HH_KERNEL_VC_UP = 5
 HH_KERNEL_GEMV = 6
 HH_KERNEL_PCR = 7
 
@@ -48,7 +48,7 @@ EXPORTED = [
 
 KERNEL_IDS = {"none": HH_KERNEL_NONE, "apply_dot": HH_KERNEL_APPLY_DOT,
               "axpy_dot": HH_KERNEL_AXPY_DOT, "axpy_norm": HH_KERNEL_AXPY_NORM,
-              "presmooth": HH_KERNEL_PRESMOOTH, "postsmooth": HH_KERNEL_POSTSMOOTH,
+              "vc_down": HH_KERNEL_VC_DOWN, "vc_up": HH_KERNEL_VC_UP,
               "gemv": HH_KERNEL_GEMV, "pcr": HH_KERNEL_PCR}
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)

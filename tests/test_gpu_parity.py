@@ -43,8 +43,9 @@ def _problem(hh, m, omega, alpha, h, beta=(1.0, 0.5)):
 
 
 CASES_1D = [(1001, 5.0, 10.0), (37, 5.0, 10.0), (3, 5.0, 10.0), (1024, 5.0, 25.0)]
-CASES_2D = [((201, 401), 10.0, 10.0), ((13, 70), 10.0, 12.0), ((3, 3), 10.0, 10.0),
-            ((65, 33), 10.0, 4.0), ((17, 9), 10.0, 2.0)]
+CASES_2D = [((201, 401), 10.0, 10.0), ((201, 401), 10.0, 15.0), ((13, 70), 10.0, 12.0),
+            ((3, 3), 10.0, 10.0), ((65, 33), 10.0, 4.0), ((17, 9), 10.0, 2.0),
+            ((129, 129), 10.0, 30.0)]
 
 
 def _model(shape, h, seed=0):
@@ -268,6 +269,18 @@ def test_invalid_inputs(hh):
     with pytest.raises(hh.HHError) as e:
         P.solve(_t(fbad), tol=1e-6, restart=5)
     assert e.value.status == hh.HH_ENUMERIC
+
+
+def test_solve_grf_401x201_15hz_under_resolved_level(hh):
+    """15 Hz: the hierarchy continues past two nodes per wavelength (51 x 101 has
+    more than HH_MAX_COARSE nodes) and smooths that level with weight 0.5."""
+    w = wl.random_field_2d(401, 201, 10.0, seed=2, freq_hz=15.0, src=(200, 5))
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h, w.beta)
+    assert P.num_levels == 4 and P.level_info(3)[0] == (26, 51)
+    res = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    ref = solver.solve(w.slowness, w.omega, w.alpha, w.h, w.source, beta=w.beta, tol=w.tol,
+                       restart=w.restart)
+    _check_solve(res, ref, w.tol)
 
 
 def test_solve_is_bitwise_reproducible(hh):
