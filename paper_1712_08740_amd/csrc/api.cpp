@@ -63,6 +63,7 @@ struct LevelData {
     int halve_z = 0, halve_x = 0;   // halving flags towards the next coarser level
     double wj = kJacobiWeight;      // Jacobi weight of this level's smoother
     cplx* C = nullptr;              // 9-point Galerkin operator (levels >= 1)
+    cplx* wd = nullptr;             // wj / diag per node (smoothing levels)
     int64_t size() const { return (int64_t)nz * nx; }
 };
 
@@ -121,15 +122,21 @@ FineOp fine_op(const hh_problem_s* p, double sr, double si) {
     op.sr = sr;
     op.si = si;
     op.m2 = p->m2;
+    op.wdinv = nullptr;
     return op;
 }
 FineOp op_H(const hh_problem_s* p) { return fine_op(p, 1.0, -p->alpha); }
-FineOp op_M(const hh_problem_s* p) { return fine_op(p, p->beta1, -p->beta2); }
+FineOp op_M(const hh_problem_s* p) {
+    FineOp op = fine_op(p, p->beta1, -p->beta2);
+    op.wdinv = p->levels.empty() ? nullptr : p->levels[0].wd;
+    return op;
+}
 CoarseOp coarse_op(const LevelData& L) {
     CoarseOp op;
     op.nz = L.nz;
     op.nx = L.nx;
     op.C = L.C;
+    op.wdinv = L.wd;
     return op;
 }
 
@@ -256,10 +263,10 @@ int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* 
     const LevelData& nx = p->levels[l + 1];
     const CoarseOp A = coarse_op(lv);
     cplx* x2 = at<cplx>(ws, L.t[l]);
-    HIPCHK(launch_vc_coarse_down(A, lv.wj, b, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+    HIPCHK(launch_vc_coarse_down(A, b, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
                                  at<cplx>(ws, L.bc[l + 1]), active, s));
     CHK(vcycle_coarse(p, L, ws, l + 1, active, s));
-    HIPCHK(launch_vc_coarse_up(A, lv.wj, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[l + 1]),
+    HIPCHK(launch_vc_coarse_up(A, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[l + 1]),
                                nx.nx, x, active, s));
     return HH_OK;
 }
@@ -293,12 +300,12 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const S
     const LevelData& nx = p->levels[1];
     cplx* x2 = at<cplx>(ws, L.t[0]);
     TIMED(HH_KERNEL_VC_DOWN, 60.0 * N,
-          launch_vc_fine_down(M, lv.wj, src, scale, vout, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+          launch_vc_fine_down(M, src, scale, vout, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
                               at<cplx>(ws, L.bc[1]), active, s));
     const cplx* b = vout ? vout : src;
     CHK(vcycle_coarse(p, L, ws, 1, active, s));
     TIMED(HH_KERNEL_VC_UP, 60.0 * N,
-          launch_vc_fine_up(M, lv.wj, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[1]), nx.nx,
+          launch_vc_fine_up(M, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[1]), nx.nx,
                             z, active, s));
     return HH_OK;
 }
@@ -307,11 +314,12 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const S
 // set-up
 // ---------------------------------------------------------------------------
 void free_levels(hh_problem_s* p) {
-    for (auto& l : p->levels)
-        if (l.C) {
-            (void)hipFree(l.C);
-            l.C = nullptr;
-        }
+    for (auto& l : p->levels) {
+        if (l.C) (void)hipFree(l.C);
+        if (l.wd) (void)hipFree(l.wd);
+        l.C = nullptr;
+        l.wd = nullptr;
+    }
 }
 
 int build_hierarchy(hh_problem_s* p) {
@@ -356,6 +364,8 @@ int build_hierarchy(hh_problem_s* p) {
     p->nc = (int)nc;
     for (size_t l = 1; l < p->levels.size(); ++l)
         HIPCHK(hipMalloc(&p->levels[l].C, 9 * (size_t)p->levels[l].size() * sizeof(cplx)));
+    for (size_t l = 0; l + 1 < p->levels.size(); ++l)
+        HIPCHK(hipMalloc(&p->levels[l].wd, (size_t)p->levels[l].size() * sizeof(cplx)));
     HIPCHK(hipMalloc(&p->cinv, (size_t)nc * nc * sizeof(cplx)));
     HIPCHK(hipMalloc(&p->gj_scratch, 3 * (size_t)nc * sizeof(cplx)));
     HIPCHK(hipMalloc(&p->gj_perm, (size_t)nc * sizeof(int)));
@@ -376,6 +386,13 @@ int apply_shift(hh_problem_s* p) {
         else
             HIPCHK(launch_galerkin_from_coarse(coarse_op(f), f.halve_z, f.halve_x, c.nz, c.nx,
                                                c.C, s));
+    }
+    for (int l = 0; l + 1 < nl; ++l) {
+        const LevelData& lv = p->levels[l];
+        if (l == 0)
+            HIPCHK(launch_wdinv_fine(op_M(p), lv.wj, lv.wd, s));
+        else
+            HIPCHK(launch_wdinv_coarse(coarse_op(lv), lv.wj, lv.wd, s));
     }
     if (nl == 1)
         HIPCHK(launch_dense_from_fine(M, p->cinv, s));

@@ -74,6 +74,7 @@ struct FineOp {
     double omega2;       // omega^2
     double sr, si;       // sigma = sr + j si
     const double* m2;    // slowness squared, nz*nx
+    const cplx* wdinv;   // omega_J / diag per node (V-cycle smoother), or nullptr
 };
 
 struct Coef5 {
@@ -115,6 +116,7 @@ __device__ __forceinline__ Coef5 fine_coefs(const FineOp& op, int iz, int ix, do
 struct CoarseOp {
     int nz, nx;
     const cplx* C;
+    const cplx* wdinv;   // omega_J / diag per node (V-cycle smoother)
 };
 
 struct Level {
@@ -224,18 +226,22 @@ hipError_t launch_vc_gemv(int n, const cplx* A, const cplx* x, cplx* y, const in
                           hipStream_t s);
 // temporally blocked legs (vcycle_tiled.hip): down = two pre-sweeps from zero,
 // residual and restriction; up = prolongation and two post-sweeps
-hipError_t launch_vc_fine_down(const FineOp& op, double wj, const cplx* src, const double* scale,
+// (the smoother weight enters through op.wdinv = omega_J / diag)
+hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, const double* scale,
                                cplx* bout, cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc,
                                const int* active, hipStream_t s);
-hipError_t launch_vc_coarse_down(const CoarseOp& op, double wj, const cplx* b, cplx* x2, int hz,
+hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz,
                                  int hx, int nzc, int nxc, cplx* bc, const int* active,
                                  hipStream_t s);
-hipError_t launch_vc_fine_up(const FineOp& op, double wj, int hz, int hx, const cplx* b,
+hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b,
                              const cplx* x2, const cplx* e, int nxc, cplx* out, const int* active,
                              hipStream_t s);
-hipError_t launch_vc_coarse_up(const CoarseOp& op, double wj, int hz, int hx, const cplx* b,
+hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b,
                                const cplx* x2, const cplx* e, int nxc, cplx* out,
                                const int* active, hipStream_t s);
+// wdinv = wj / diag of a level operator (set-up)
+hipError_t launch_wdinv_fine(const FineOp& op, double wj, cplx* wdinv, hipStream_t s);
+hipError_t launch_wdinv_coarse(const CoarseOp& op, double wj, cplx* wdinv, hipStream_t s);
 // PCR with the normalisation of the Arnoldi vector folded in (vout = s*src, x = M^{-1} vout)
 hipError_t launch_pcr_norm(const FineOp& op, const cplx* src, const double* scale, cplx* vout,
                            cplx* x, const int* active, hipStream_t s);

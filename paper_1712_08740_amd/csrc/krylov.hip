@@ -440,13 +440,12 @@ __global__ void __launch_bounds__(256) k_givens_step(SolveState* st, const cplx*
     hist[it] = est;
     rec->it = it;
     rec->est = est;
-    __threadfence_system();
     rec->jstep = j + 1;
+    rec->status = st->status;
+    __threadfence_system();          // the fields above are visible before the flags
     if (stop) rec->stops += 1;
     rec->done = st->done;
-    rec->status = st->status;
     rec->seq += 1;
-    __threadfence_system();
 }
 
 // y = R^{-1} g (k = st->k columns), then u += Z y; one block of 256 threads

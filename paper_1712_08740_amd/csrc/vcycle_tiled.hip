@@ -27,6 +27,7 @@ __device__ __forceinline__ bool inactive(const int* active) { return active && *
 struct Row5 {
     cplx diag;
     double cx, cz;
+    __device__ __forceinline__ cplx d() const { return diag; }
 };
 
 struct Fine5 {
@@ -42,8 +43,14 @@ struct Fine5 {
         r.cz = c.cz;
         return r;
     }
-    __device__ __forceinline__ cplx diag(int iz, int ix) const {
-        return fine_coefs(op, iz, ix, op.m2[(int64_t)iz * op.nx + ix]).diag;
+    __device__ __forceinline__ cplx wd(int iz, int ix) const {
+        return op.wdinv[(int64_t)iz * op.nx + ix];
+    }
+    __device__ __forceinline__ static Row zero_row() {
+        Row r;
+        r.diag = mk(1.0, 0.0);
+        r.cx = r.cz = 0.0;
+        return r;
     }
     // (A x)_q from an LDS field s with row stride ld at local index i
     __device__ __forceinline__ cplx apply(const Row& r, const cplx* s, int i, int ld) const {
@@ -56,7 +63,7 @@ struct Fine5 {
 // Row of a 9-point Galerkin operator: coefficient t = (dz+1)*3 + (dx+1).
 struct Row9 {
     cplx a[9];
-    cplx diag;
+    __device__ __forceinline__ cplx d() const { return a[4]; }
 };
 
 struct Coarse9 {
@@ -70,11 +77,17 @@ struct Coarse9 {
         Row r;
 #pragma unroll
         for (int t = 0; t < 9; ++t) r.a[t] = op.C[t * N + p];
-        r.diag = r.a[4];
         return r;
     }
-    __device__ __forceinline__ cplx diag(int iz, int ix) const {
-        return op.C[4 * (int64_t)op.nz * op.nx + (int64_t)iz * op.nx + ix];
+    __device__ __forceinline__ cplx wd(int iz, int ix) const {
+        return op.wdinv[(int64_t)iz * op.nx + ix];
+    }
+    __device__ __forceinline__ static Row zero_row() {
+        Row r;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) r.a[t] = mk(0.0, 0.0);
+        r.a[4] = mk(1.0, 0.0);
+        return r;
     }
     __device__ __forceinline__ cplx apply(const Row& r, const cplx* s, int i, int ld) const {
         cplx acc = mk(0.0, 0.0);
@@ -95,7 +108,7 @@ __device__ __forceinline__ bool in_grid(int z, int x, int nz, int nx) {
 // x1 (and b, D) two more.
 // ---------------------------------------------------------------------------
 template <class OP, int TCX, int TCZ>
-__global__ void __launch_bounds__(NT) k_down(OP A, double wj, const cplx* __restrict__ src,
+__global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
                                              const double* __restrict__ scale,
                                              cplx* __restrict__ bout, cplx* __restrict__ x2out,
                                              int hz, int hx, int nzc, int nxc,
@@ -104,9 +117,10 @@ __global__ void __launch_bounds__(NT) k_down(OP A, double wj, const cplx* __rest
     if (inactive(active)) return;
     constexpr int W1X = 2 * TCX + 5, W1Z = 2 * TCZ + 5;   // largest x1 region
     __shared__ cplx sb[W1X * W1Z];
-    __shared__ cplx sd[W1X * W1Z];
+    __shared__ cplx sw[W1X * W1Z];                          // omega_J / diag
     __shared__ cplx s1[W1X * W1Z];
     __shared__ cplx s2[W1X * W1Z];
+    __shared__ typename OP::Row srow[W1X * W1Z];           // rows of the x1 region
     const int nz = A.nz(), nx = A.nx();
     const int cx0 = blockIdx.x * TCX, cz0 = blockIdx.y * TCZ;
     const int rlx = hx ? 2 * cx0 - 1 : cx0, rhx = hx ? 2 * (cx0 + TCX) - 1 : cx0 + TCX - 1;
@@ -118,23 +132,27 @@ __global__ void __launch_bounds__(NT) k_down(OP A, double wj, const cplx* __rest
     const double s = scale ? scale[0] : 1.0;
     const int n1 = wx * wz;
     constexpr int SL1 = (W1X * W1Z + NT - 1) / NT;
-    // phase 1: b, D and x1 on the x1 region
+    // phase 1: b, the operator rows and x1 on the x1 region (the only global reads)
 #pragma unroll
     for (int k = 0; k < SL1; ++k) {
         const int i = threadIdx.x + k * NT;
-        if (i >= n1) break;
-        const int qz = oz + i / wx, qx = ox + i % wx;
-        cplx bq = mk(0.0, 0.0), dq = mk(1.0, 0.0), x1 = mk(0.0, 0.0);
-        if (in_grid(qz, qx, nz, nx)) {
-            const int64_t q = (int64_t)qz * nx + qx;
-            bq = cscale(src[q], s);
-            dq = A.diag(qz, qx);
-            x1 = cscale(cdiv(bq, dq), wj);
-            if (bout && qz >= olz && qz <= ohz && qx >= olx && qx <= ohx) bout[q] = bq;
+        if (i < n1) {
+            const int qz = oz + i / wx, qx = ox + i % wx;
+            cplx bq = mk(0.0, 0.0), x1 = mk(0.0, 0.0), wq = mk(0.0, 0.0);
+            typename OP::Row r = OP::zero_row();
+            if (in_grid(qz, qx, nz, nx)) {
+                const int64_t q = (int64_t)qz * nx + qx;
+                bq = cscale(src[q], s);
+                r = A.row(qz, qx);
+                wq = A.wd(qz, qx);
+                x1 = cmul(bq, wq);
+                if (bout && qz >= olz && qz <= ohz && qx >= olx && qx <= ohx) bout[q] = bq;
+            }
+            sb[i] = bq;
+            sw[i] = wq;
+            srow[i] = r;
+            s1[i] = x1;
         }
-        sb[i] = bq;
-        sd[i] = dq;
-        s1[i] = x1;
     }
     __syncthreads();
     // phase 2: x2 on the x1 region shrunk by one node (stored at the same local index)
@@ -142,19 +160,20 @@ __global__ void __launch_bounds__(NT) k_down(OP A, double wj, const cplx* __rest
 #pragma unroll
     for (int k = 0; k < SL1; ++k) {
         const int j = threadIdx.x + k * NT;
-        if (j >= n2) break;
-        const int lz = 1 + j / w2x, lx = 1 + j % w2x;
-        const int i = lz * wx + lx;
-        const int qz = oz + lz, qx = ox + lx;
-        cplx x2 = mk(0.0, 0.0);
-        if (in_grid(qz, qx, nz, nx)) {
-            const typename OP::Row r = A.row(qz, qx);
-            const cplx ax = A.apply(r, s1, i, wx);
-            x2 = cadd(s1[i], cscale(cdiv(csub(sb[i], ax), sd[i]), wj));
-            if (qz >= olz && qz <= ohz && qx >= olx && qx <= ohx)
-                x2out[(int64_t)qz * nx + qx] = x2;
+        if (j < n2) {
+            const int lz = 1 + j / w2x, lx = 1 + j % w2x;
+            const int i = lz * wx + lx;
+            const int qz = oz + lz, qx = ox + lx;
+            cplx x2 = mk(0.0, 0.0);
+            if (in_grid(qz, qx, nz, nx)) {
+                const typename OP::Row& r = srow[i];
+                const cplx ax = A.apply(r, s1, i, wx);
+                x2 = cadd(s1[i], cmul(csub(sb[i], ax), sw[i]));
+                if (qz >= olz && qz <= ohz && qx >= olx && qx <= ohx)
+                    x2out[(int64_t)qz * nx + qx] = x2;
+            }
+            s2[i] = x2;
         }
-        s2[i] = x2;
     }
     __syncthreads();
     // phase 3: residual on the region shrunk by two nodes (into s1, no longer needed)
@@ -162,16 +181,14 @@ __global__ void __launch_bounds__(NT) k_down(OP A, double wj, const cplx* __rest
 #pragma unroll
     for (int k = 0; k < SL1; ++k) {
         const int j = threadIdx.x + k * NT;
-        if (j >= n3) break;
-        const int lz = 2 + j / w3x, lx = 2 + j % w3x;
-        const int i = lz * wx + lx;
-        const int qz = oz + lz, qx = ox + lx;
-        cplx r = mk(0.0, 0.0);
-        if (in_grid(qz, qx, nz, nx)) {
-            const typename OP::Row row = A.row(qz, qx);
-            r = csub(sb[i], A.apply(row, s2, i, wx));
+        if (j < n3) {
+            const int lz = 2 + j / w3x, lx = 2 + j % w3x;
+            const int i = lz * wx + lx;
+            const int qz = oz + lz, qx = ox + lx;
+            cplx r = mk(0.0, 0.0);
+            if (in_grid(qz, qx, nz, nx)) r = csub(sb[i], A.apply(srow[i], s2, i, wx));
+            s1[i] = r;
         }
-        s1[i] = r;
     }
     __syncthreads();
     // phase 4: b_c = R r for the tile's coarse nodes
@@ -205,7 +222,7 @@ __device__ __forceinline__ void interp2(int q, int halved, int& J0, int& J1, dou
 }
 
 template <class OP, int TX, int TZ>
-__global__ void __launch_bounds__(NT) k_up(OP A, double wj, int hz, int hx,
+__global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
                                            const cplx* __restrict__ b,
                                            const cplx* __restrict__ x2,
                                            const cplx* __restrict__ e, int nxc,
@@ -213,66 +230,90 @@ __global__ void __launch_bounds__(NT) k_up(OP A, double wj, int hz, int hx,
                                            const int* __restrict__ active) {
     if (inactive(active)) return;
     constexpr int WX = TX + 4, WZ = TZ + 4;
-    __shared__ cplx sp[WX * WZ];     // x' (tile + 2)
-    __shared__ cplx s3[WX * WZ];     // x3 (tile + 1)
+    constexpr int W3X = TX + 2, W3Z = TZ + 2;
+    __shared__ cplx sp[WX * WZ];                      // x' (tile + 2)
+    __shared__ cplx s3[WX * WZ];                      // x3 (tile + 1)
+    __shared__ cplx sbb[W3X * W3Z];                   // b on the tile + 1
+    __shared__ cplx sw[W3X * W3Z];                    // omega_J / diag on the tile + 1
+    __shared__ typename OP::Row srow[W3X * W3Z];      // rows on the tile + 1
     const int nz = A.nz(), nx = A.nx();
     const int fx0 = blockIdx.x * TX, fz0 = blockIdx.y * TZ;
     const int ox = fx0 - 2, oz = fz0 - 2;
     constexpr int SL = (WX * WZ + NT - 1) / NT;
-    // phase 1: x' = x2 + P e
+    constexpr int SL3 = (W3X * W3Z + NT - 1) / NT;
+    // phase 1: x' = x2 + P e on the tile + 2; b and rows on the tile + 1
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int i = threadIdx.x + k * NT;
-        if (i >= WX * WZ) break;
-        const int qz = oz + i / WX, qx = ox + i % WX;
-        cplx v = mk(0.0, 0.0);
-        if (in_grid(qz, qx, nz, nx)) {
-            int z0, z1, x0, x1;
-            double wz0, wz1, wx0, wx1;
-            interp2(qz, hz, z0, z1, wz0, wz1);
-            interp2(qx, hx, x0, x1, wx0, wx1);
-            const cplx e00 = e[(int64_t)z0 * nxc + x0], e01 = e[(int64_t)z0 * nxc + x1];
-            const cplx e10 = e[(int64_t)z1 * nxc + x0], e11 = e[(int64_t)z1 * nxc + x1];
-            const cplx pe = cadd(cadd(cscale(e00, wz0 * wx0), cscale(e01, wz0 * wx1)),
-                                 cadd(cscale(e10, wz1 * wx0), cscale(e11, wz1 * wx1)));
-            v = cadd(x2[(int64_t)qz * nx + qx], pe);
+        if (i < WX * WZ) {
+            const int qz = oz + i / WX, qx = ox + i % WX;
+            cplx v = mk(0.0, 0.0);
+            if (in_grid(qz, qx, nz, nx)) {
+                int z0, z1, x0, x1;
+                double wz0, wz1, wx0, wx1;
+                interp2(qz, hz, z0, z1, wz0, wz1);
+                interp2(qx, hx, x0, x1, wx0, wx1);
+                const cplx e00 = e[(int64_t)z0 * nxc + x0], e01 = e[(int64_t)z0 * nxc + x1];
+                const cplx e10 = e[(int64_t)z1 * nxc + x0], e11 = e[(int64_t)z1 * nxc + x1];
+                const cplx pe = cadd(cadd(cscale(e00, wz0 * wx0), cscale(e01, wz0 * wx1)),
+                                     cadd(cscale(e10, wz1 * wx0), cscale(e11, wz1 * wx1)));
+                v = cadd(x2[(int64_t)qz * nx + qx], pe);
+            }
+            sp[i] = v;
         }
-        sp[i] = v;
     }
-    __syncthreads();
-    // phase 2: x3 on the tile plus one node
-    constexpr int W3X = TX + 2, W3Z = TZ + 2;
-    constexpr int SL3 = (W3X * W3Z + NT - 1) / NT;
 #pragma unroll
     for (int k = 0; k < SL3; ++k) {
         const int j = threadIdx.x + k * NT;
-        if (j >= W3X * W3Z) break;
-        const int lz = 1 + j / W3X, lx = 1 + j % W3X;
-        const int i = lz * WX + lx;
-        const int qz = oz + lz, qx = ox + lx;
-        cplx v = mk(0.0, 0.0);
-        if (in_grid(qz, qx, nz, nx)) {
-            const typename OP::Row r = A.row(qz, qx);
-            const cplx ax = A.apply(r, sp, i, WX);
-            v = cadd(sp[i], cscale(cdiv(csub(b[(int64_t)qz * nx + qx], ax), r.diag), wj));
+        if (j < W3X * W3Z) {
+            const int qz = fz0 - 1 + j / W3X, qx = fx0 - 1 + j % W3X;
+            typename OP::Row r = OP::zero_row();
+            cplx bq = mk(0.0, 0.0), wq = mk(0.0, 0.0);
+            if (in_grid(qz, qx, nz, nx)) {
+                r = A.row(qz, qx);
+                bq = b[(int64_t)qz * nx + qx];
+                wq = A.wd(qz, qx);
+            }
+            srow[j] = r;
+            sbb[j] = bq;
+            sw[j] = wq;
         }
-        s3[i] = v;
+    }
+    __syncthreads();
+    // phase 2: x3 on the tile plus one node
+#pragma unroll
+    for (int k = 0; k < SL3; ++k) {
+        const int j = threadIdx.x + k * NT;
+        if (j < W3X * W3Z) {
+            const int lz = 1 + j / W3X, lx = 1 + j % W3X;
+            const int i = lz * WX + lx;
+            const int qz = oz + lz, qx = ox + lx;
+            cplx v = mk(0.0, 0.0);
+            if (in_grid(qz, qx, nz, nx)) {
+                const typename OP::Row& r = srow[j];
+                const cplx ax = A.apply(r, sp, i, WX);
+                v = cadd(sp[i], cmul(csub(sbb[j], ax), sw[j]));
+            }
+            s3[i] = v;
+        }
     }
     __syncthreads();
     // phase 3: x4 on the tile
     constexpr int SL4 = (TX * TZ + NT - 1) / NT;
 #pragma unroll
     for (int k = 0; k < SL4; ++k) {
-        const int j = threadIdx.x + k * NT;
-        if (j >= TX * TZ) break;
-        const int lz = 2 + j / TX, lx = 2 + j % TX;
-        const int i = lz * WX + lx;
-        const int qz = oz + lz, qx = ox + lx;
-        if (!in_grid(qz, qx, nz, nx)) continue;
-        const typename OP::Row r = A.row(qz, qx);
-        const cplx ax = A.apply(r, s3, i, WX);
-        const int64_t q = (int64_t)qz * nx + qx;
-        out[q] = cadd(s3[i], cscale(cdiv(csub(b[q], ax), r.diag), wj));
+        const int t = threadIdx.x + k * NT;
+        if (t < TX * TZ) {
+            const int lz = 2 + t / TX, lx = 2 + t % TX;
+            const int i = lz * WX + lx;
+            const int j = (lz - 1) * W3X + (lx - 1);
+            const int qz = oz + lz, qx = ox + lx;
+            if (in_grid(qz, qx, nz, nx)) {
+                const typename OP::Row& r = srow[j];
+                const cplx ax = A.apply(r, s3, i, WX);
+                out[(int64_t)qz * nx + qx] = cadd(s3[i], cmul(csub(sbb[j], ax), sw[j]));
+            }
+        }
     }
 }
 
@@ -282,68 +323,101 @@ inline double inv2dc(int hz, int hx) { return 1.0 / (double)((hz ? 2 : 1) * (hx 
 // tiles (more blocks in flight)
 constexpr int64_t kBigLevel = 40000;
 
+// Large tiles (less halo work) for the big 5-point grid; small tiles (more
+// blocks in flight, and room in LDS for the 9-coefficient rows) elsewhere.
 template <class OP>
-hipError_t down_dispatch(const OP& A, double wj, const cplx* src, const double* scale, cplx* bout,
+hipError_t down_dispatch(const OP& A, const cplx* src, const double* scale, cplx* bout,
                          cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc, const int* active,
                          hipStream_t s) {
     const double rs = inv2dc(hz, hx);
-    if ((int64_t)A.nz() * A.nx() >= kBigLevel) {
-        const dim3 g((nxc + 15) / 16, (nzc + 3) / 4);
-        HH_LAUNCH((k_down<OP, 16, 4>), g, dim3(NT), 0, s, A, wj, src, scale, bout, x2, hz, hx,
-                  nzc, nxc, bc, rs, active);
-    } else {
-        const dim3 g((nxc + 7) / 8, (nzc + 3) / 4);
-        HH_LAUNCH((k_down<OP, 8, 4>), g, dim3(NT), 0, s, A, wj, src, scale, bout, x2, hz, hx, nzc,
-                  nxc, bc, rs, active);
+    if constexpr (sizeof(typename OP::Row) <= 32) {
+        if ((int64_t)A.nz() * A.nx() >= kBigLevel) {
+            const dim3 g((nxc + 15) / 16, (nzc + 3) / 4);
+            HH_LAUNCH((k_down<OP, 16, 4>), g, dim3(NT), 0, s, A, src, scale, bout, x2, hz, hx,
+                      nzc, nxc, bc, rs, active);
+            return hipGetLastError();
+        }
     }
+    const dim3 g((nxc + 7) / 8, (nzc + 3) / 4);
+    HH_LAUNCH((k_down<OP, 8, 4>), g, dim3(NT), 0, s, A, src, scale, bout, x2, hz, hx, nzc, nxc,
+              bc, rs, active);
     return hipGetLastError();
 }
 
 template <class OP>
-hipError_t up_dispatch(const OP& A, double wj, int hz, int hx, const cplx* b, const cplx* x2,
+hipError_t up_dispatch(const OP& A, int hz, int hx, const cplx* b, const cplx* x2,
                        const cplx* e, int nxc, cplx* out, const int* active, hipStream_t s) {
-    if ((int64_t)A.nz() * A.nx() >= kBigLevel) {
-        const dim3 g((A.nx() + 31) / 32, (A.nz() + 7) / 8);
-        HH_LAUNCH((k_up<OP, 32, 8>), g, dim3(NT), 0, s, A, wj, hz, hx, b, x2, e, nxc, out, active);
-    } else {
-        const dim3 g((A.nx() + 15) / 16, (A.nz() + 3) / 4);
-        HH_LAUNCH((k_up<OP, 16, 4>), g, dim3(NT), 0, s, A, wj, hz, hx, b, x2, e, nxc, out, active);
+    if constexpr (sizeof(typename OP::Row) <= 32) {
+        if ((int64_t)A.nz() * A.nx() >= kBigLevel) {
+            const dim3 g((A.nx() + 31) / 32, (A.nz() + 7) / 8);
+            HH_LAUNCH((k_up<OP, 32, 8>), g, dim3(NT), 0, s, A, hz, hx, b, x2, e, nxc, out,
+                      active);
+            return hipGetLastError();
+        }
     }
+    const dim3 g((A.nx() + 15) / 16, (A.nz() + 3) / 4);
+    HH_LAUNCH((k_up<OP, 16, 4>), g, dim3(NT), 0, s, A, hz, hx, b, x2, e, nxc, out, active);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_vc_fine_down(const FineOp& op, double wj, const cplx* src, const double* scale,
+hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, const double* scale,
                                cplx* bout, cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc,
                                const int* active, hipStream_t s) {
     Fine5 A;
     A.op = op;
-    return down_dispatch(A, wj, src, scale, bout, x2, hz, hx, nzc, nxc, bc, active, s);
+    return down_dispatch(A, src, scale, bout, x2, hz, hx, nzc, nxc, bc, active, s);
 }
 
-hipError_t launch_vc_coarse_down(const CoarseOp& op, double wj, const cplx* b, cplx* x2, int hz,
-                                 int hx, int nzc, int nxc, cplx* bc, const int* active,
-                                 hipStream_t s) {
+hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz, int hx,
+                                 int nzc, int nxc, cplx* bc, const int* active, hipStream_t s) {
     Coarse9 A;
     A.op = op;
-    return down_dispatch(A, wj, b, nullptr, nullptr, x2, hz, hx, nzc, nxc, bc, active, s);
+    return down_dispatch(A, b, nullptr, nullptr, x2, hz, hx, nzc, nxc, bc, active, s);
 }
 
-hipError_t launch_vc_fine_up(const FineOp& op, double wj, int hz, int hx, const cplx* b,
-                             const cplx* x2, const cplx* e, int nxc, cplx* out, const int* active,
-                             hipStream_t s) {
+hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b, const cplx* x2,
+                             const cplx* e, int nxc, cplx* out, const int* active, hipStream_t s) {
     Fine5 A;
     A.op = op;
-    return up_dispatch(A, wj, hz, hx, b, x2, e, nxc, out, active, s);
+    return up_dispatch(A, hz, hx, b, x2, e, nxc, out, active, s);
 }
 
-hipError_t launch_vc_coarse_up(const CoarseOp& op, double wj, int hz, int hx, const cplx* b,
-                               const cplx* x2, const cplx* e, int nxc, cplx* out,
-                               const int* active, hipStream_t s) {
+hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b, const cplx* x2,
+                               const cplx* e, int nxc, cplx* out, const int* active,
+                               hipStream_t s) {
     Coarse9 A;
     A.op = op;
-    return up_dispatch(A, wj, hz, hx, b, x2, e, nxc, out, active, s);
+    return up_dispatch(A, hz, hx, b, x2, e, nxc, out, active, s);
+}
+
+namespace {
+__global__ void __launch_bounds__(256) k_wdinv_fine(FineOp op, double wj, cplx* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= (int64_t)op.nz * op.nx) return;
+    const int iz = (int)(p / op.nx), ix = (int)(p - (int64_t)iz * op.nx);
+    out[p] = cscale(crecip(fine_coefs(op, iz, ix, op.m2[p]).diag), wj);
+}
+__global__ void __launch_bounds__(256) k_wdinv_coarse(CoarseOp op, double wj,
+                                                      cplx* __restrict__ out) {
+    const int64_t N = (int64_t)op.nz * op.nx;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= N) return;
+    out[p] = cscale(crecip(op.C[4 * N + p]), wj);
+}
+}  // namespace
+
+hipError_t launch_wdinv_fine(const FineOp& op, double wj, cplx* wdinv, hipStream_t s) {
+    const int64_t n = (int64_t)op.nz * op.nx;
+    HH_LAUNCH(k_wdinv_fine, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, op, wj, wdinv);
+    return hipGetLastError();
+}
+
+hipError_t launch_wdinv_coarse(const CoarseOp& op, double wj, cplx* wdinv, hipStream_t s) {
+    const int64_t n = (int64_t)op.nz * op.nx;
+    HH_LAUNCH(k_wdinv_coarse, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, op, wj, wdinv);
+    return hipGetLastError();
 }
 
 }  // namespace hh
