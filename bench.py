@@ -38,9 +38,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grf_401x201",
                     choices=["grf_401x201", "layered_1d_well"])
-    ap.add_argument("--kernel", default="axpy_dot",
-                    help="kernel class for the roofline figure (apply_dot, axpy_dot, axpy_norm, "
-                         "vc_down, vc_up, gemv, pcr)")
+    ap.add_argument("--kernel", default="auto",
+                    help="kernel class for the roofline figure; 'auto' (default) times every "
+                         "class over one warm-up solve and takes the one with the most device time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample")
@@ -104,7 +104,19 @@ def main():
 
     for _ in range(a.warmup):
         one()
-    P.kernel_timer_start(a.kernel)
+    # device time per solve of every kernel class (one solve per class)
+    share = {}
+    for k in hh.KERNEL_IDS:
+        if k == "none":
+            continue
+        P.kernel_timer_start(k)
+        one()
+        n_k, ms_k, _ = P.kernel_timer_read()
+        if n_k:
+            share[k] = ms_k
+    P.kernel_timer_start("none")
+    kernel = max(share, key=share.get) if a.kernel == "auto" else a.kernel
+    P.kernel_timer_start(kernel)
     torch.cuda.synchronize()
     lat = []
     its = []
@@ -148,7 +160,8 @@ def main():
             "grid_nx_nz": [int(w.shape[-1]), int(w.shape[0]) if len(w.shape) == 2 else 1],
             "h_m": w.h, "freq_hz": w.freq_hz, "alpha": w.alpha, "beta": list(w.beta),
             "tol": w.tol, "restart": w.restart,
-            "precond": ("V(2,2) omega-Jacobi 0.8, Galerkin coarse operators, dense coarsest inverse"
+            "precond": ("V(2,2) omega-Jacobi (0.8 where omega*max(m)*h < 2, else 0.5), Galerkin "
+                        "coarse operators, dense coarsest inverse"
                         if len(w.shape) == 2 else "exact tridiagonal (PCR)"),
             "levels_nz_nx": levels,
             "iterations": int(np.median(its)),
@@ -160,7 +173,7 @@ def main():
                        "plain": "this is the plain FP64 one-request-at-a-time solver"},
         "roofline": {
             "bound": "hbm",
-            "kernel": a.kernel,
+            "kernel": kernel,
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -169,6 +182,8 @@ def main():
             "launches": int(launches),
             "avg_launch_us": avg_us,
             "algorithmic_bytes_per_launch": kbytes / max(launches, 1),
+            "device_ms_per_solve_by_kernel": {k: round(v, 4) for k, v in
+                                              sorted(share.items(), key=lambda kv: -kv[1])},
         },
     }
     if rank == 0 and not a.no_cpu_baseline:

@@ -188,11 +188,20 @@ enum hh_kernel_id {
     HH_KERNEL_AXPY_DOT   = 2,  /* w -= V h and the second projections: (k + 2) * 16 B/node   */
     HH_KERNEL_AXPY_NORM  = 3,  /* w -= V h and ||w||^2: (k + 2) * 16 B/node                  */
     HH_KERNEL_VC_DOWN    = 4,  /* fine-grid V-cycle down leg (2 sweeps, residual, restriction):
-                                  60 B/node (b, m^2 in; v, x2 out; restricted rhs 1/4)     */
+                                  72 B/node (w, m^2, omega/diag in; v, x2 out) + 16 B per
+                                  coarse node                                              */
     HH_KERNEL_VC_UP      = 5,  /* fine-grid V-cycle up leg (prolongation, 2 sweeps):
-                                  60 B/node (x2, b, m^2 in, correction 1/4; z out)         */
+                                  72 B/node (x2, v, m^2, omega/diag in; z out) + 16 B per
+                                  coarse node                                              */
     HH_KERNEL_GEMV       = 6,  /* coarsest dense inverse times vector: (n^2 + 2n) * 16 B     */
-    HH_KERNEL_PCR        = 7   /* 1D tridiagonal solve: 56 B/node                            */
+    HH_KERNEL_PCR        = 7,  /* 1D tridiagonal solve: 56 B/node                            */
+    HH_KERNEL_VC_DOWN_COARSE = 8,  /* coarse-level down legs: 192 B/node (b, 9 coefficients,
+                                      omega/diag in; x2 out) + 16 B per next-level node    */
+    HH_KERNEL_VC_UP_COARSE   = 9,  /* coarse-level up legs: 208 B/node (x2, b, 9 coefficients,
+                                      omega/diag in; x out) + 16 B per next-level node     */
+    HH_KERNEL_REDUCE     = 10, /* fixed-order sums of the projection partials:
+                                  16 B per partial + 16 B per result                       */
+    HH_KERNEL_GIVENS     = 11  /* Givens step (reads the norm partials; one block)         */
 };
 int hh_kernel_timer_start(hh_problem p, int kernel_id);
 int hh_kernel_timer_read(hh_problem p, int64_t* launches, double* total_ms,

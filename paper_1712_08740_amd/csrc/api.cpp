@@ -263,11 +263,14 @@ int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* 
     const LevelData& nx = p->levels[l + 1];
     const CoarseOp A = coarse_op(lv);
     cplx* x2 = at<cplx>(ws, L.t[l]);
-    HIPCHK(launch_vc_coarse_down(A, b, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
-                                 at<cplx>(ws, L.bc[l + 1]), active, s));
+    const double nl_ = (double)lv.size(), nn_ = (double)nx.size();
+    TIMED(HH_KERNEL_VC_DOWN_COARSE, 192.0 * nl_ + 16.0 * nn_,
+          launch_vc_coarse_down(A, b, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+                                at<cplx>(ws, L.bc[l + 1]), active, s));
     CHK(vcycle_coarse(p, L, ws, l + 1, active, s));
-    HIPCHK(launch_vc_coarse_up(A, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[l + 1]),
-                               nx.nx, x, active, s));
+    TIMED(HH_KERNEL_VC_UP_COARSE, 208.0 * nl_ + 16.0 * nn_,
+          launch_vc_coarse_up(A, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[l + 1]), nx.nx,
+                              x, active, s));
     return HH_OK;
 }
 
@@ -299,12 +302,13 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const S
     const LevelData& lv = p->levels[0];
     const LevelData& nx = p->levels[1];
     cplx* x2 = at<cplx>(ws, L.t[0]);
-    TIMED(HH_KERNEL_VC_DOWN, 60.0 * N,
+    const double N1 = (double)nx.size();
+    TIMED(HH_KERNEL_VC_DOWN, 72.0 * N + 16.0 * N1,
           launch_vc_fine_down(M, src, scale, vout, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
                               at<cplx>(ws, L.bc[1]), active, s));
     const cplx* b = vout ? vout : src;
     CHK(vcycle_coarse(p, L, ws, 1, active, s));
-    TIMED(HH_KERNEL_VC_UP, 60.0 * N,
+    TIMED(HH_KERNEL_VC_UP, 72.0 * N + 16.0 * N1,
           launch_vc_fine_up(M, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[1]), nx.nx,
                             z, active, s));
     return HH_OK;
@@ -802,13 +806,16 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
             }
             TIMED(HH_KERNEL_APPLY_DOT, (40.0 + 16.0 * kk) * (double)N,
                   launch_apply_dot(H, zj, w, V, kk, partial, active, s));
-            HIPCHK(launch_reduce_pred(partial, L.nbA, kk, h1, active, s));
+            TIMED(HH_KERNEL_REDUCE, 16.0 * kk * (L.nbA + 1),
+                  launch_reduce_pred(partial, L.nbA, kk, h1, active, s));
             TIMED(HH_KERNEL_AXPY_DOT, (kk + 2) * 16.0 * (double)N,
                   launch_axpy_dot(V, N, kk, h1, w, partial, active, s));
-            HIPCHK(launch_reduce_pred(partial, L.nbN, kk, h2, active, s));
+            TIMED(HH_KERNEL_REDUCE, 16.0 * kk * (L.nbN + 1),
+                  launch_reduce_pred(partial, L.nbN, kk, h2, active, s));
             TIMED(HH_KERNEL_AXPY_NORM, (kk + 2) * 16.0 * (double)N,
                   launch_axpy_norm(V, N, kk, h2, w, partial, active, s));
-            HIPCHK(launch_givens_step(st, h1, h2, partial, L.nbN, R, cs, sn, g, drec, dhist, s));
+            TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbN,
+                  launch_givens_step(st, h1, h2, partial, L.nbN, R, cs, sn, g, drec, dhist, s));
         }
         (void)closed;
         // the cycle closes on a step (or the solve ended at its start)
@@ -836,7 +843,7 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
 int hh_kernel_timer_start(hh_problem p, int kernel_id) {
     g_err.clear();
     if (!p) return fail(HH_EINVAL, "problem is NULL");
-    if (kernel_id < HH_KERNEL_NONE || kernel_id > HH_KERNEL_PCR)
+    if (kernel_id < HH_KERNEL_NONE || kernel_id > HH_KERNEL_GIVENS)
         return fail(HH_EINVAL, "unknown kernel id");
     p->kt.kid = kernel_id;
     p->kt.pending.clear();

@@ -37,6 +37,10 @@ HH_KERNEL_VC_DOWN = 4
 HH_KERNEL_VC_UP = 5
 HH_KERNEL_GEMV = 6
 HH_KERNEL_PCR = 7
+HH_KERNEL_VC_DOWN_COARSE = 8
+HH_KERNEL_VC_UP_COARSE = 9
+HH_KERNEL_REDUCE = 10
+HH_KERNEL_GIVENS = 11
 
 EXPORTED = [
     "hh_create_problem", "hh_set_shift", "hh_workspace_bytes", "hh_solve",
@@ -49,7 +53,9 @@ EXPORTED = [
 KERNEL_IDS = {"none": HH_KERNEL_NONE, "apply_dot": HH_KERNEL_APPLY_DOT,
               "axpy_dot": HH_KERNEL_AXPY_DOT, "axpy_norm": HH_KERNEL_AXPY_NORM,
               "vc_down": HH_KERNEL_VC_DOWN, "vc_up": HH_KERNEL_VC_UP,
-              "gemv": HH_KERNEL_GEMV, "pcr": HH_KERNEL_PCR}
+              "gemv": HH_KERNEL_GEMV, "pcr": HH_KERNEL_PCR,
+              "vc_down_coarse": HH_KERNEL_VC_DOWN_COARSE, "vc_up_coarse": HH_KERNEL_VC_UP_COARSE,
+              "reduce": HH_KERNEL_REDUCE, "givens": HH_KERNEL_GIVENS}
 
 _c_int_p = ctypes.POINTER(ctypes.c_int)
 _c_double_p = ctypes.POINTER(ctypes.c_double)

@@ -313,3 +313,34 @@ def test_kernel_timer_counts_working_launches(hh):
     assert nbytes == pytest.approx(sum((k + 2) * 16.0 * N for k in ks), rel=1e-12)
     assert 0 < ms < 1e3
     P.kernel_timer_start("none")
+
+
+@pytest.mark.gpu
+def test_kernel_timer_classes_cover_the_step(hh):
+    """Every kernel class of a 2D multigrid step is timed with one launch per
+    working step (per level for the coarse legs, two reductions per step), and
+    the byte model of the fine legs is 72 B per fine node + 16 B per coarse node."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    N = w.slowness.size
+    nl = P.num_levels
+    shapes = [P.level_shape(l) for l in range(nl)]
+    res = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    it = res.iterations
+    per_step = {"apply_dot": 1, "axpy_dot": 1, "axpy_norm": 1, "givens": 1, "reduce": 2,
+                "vc_down": 1, "vc_up": 1, "gemv": 1,
+                "vc_down_coarse": nl - 2, "vc_up_coarse": nl - 2}
+    for k, n in per_step.items():
+        P.kernel_timer_start(k)
+        r = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+        launches, ms, nbytes = P.kernel_timer_read()
+        assert r.iterations == it
+        assert launches == n * it, k
+        assert ms > 0, k
+        if k == "vc_down":
+            n1 = shapes[1][0] * shapes[1][1]
+            assert nbytes == pytest.approx(it * (72.0 * N + 16.0 * n1), rel=1e-12)
+    P.kernel_timer_start("pcr")
+    P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    assert P.kernel_timer_read()[0] == 0
+    P.kernel_timer_start("none")
