@@ -42,6 +42,9 @@ def parse():
                     help="kernel class for the roofline figure; 'auto' (default) times every "
                          "class over one warm-up solve and takes the one with the most device time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the solves, copy a buffer of this many MiB once on the device "
+                         "(a plain copy kernel of known size, to scale hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample")
     return ap.parse_args()
@@ -88,6 +91,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if a.copy_probe_mib > 0:
+        src = torch.ones(a.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = workload(a.workload)
     stream = torch.cuda.current_stream()
     m = torch.from_numpy(w.slowness).to(dev)

@@ -9,7 +9,7 @@
 // itself on a progress record that the device writes into pinned host memory;
 // it never waits on the stream inside the iteration.
 #include "helmholtz.h"
-#include "hh_internal.h"
+#include "givens.h"
 
 #include <immintrin.h>
 
@@ -276,9 +276,11 @@ int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* 
 
 // z = M^{-1} v. Inside a solve (st given) v = st->scale * src is also written
 // to vout (the normalised Krylov basis vector) and every kernel is predicated
-// on st->active; stand-alone (st == NULL) v = src.
+// on st->active; stand-alone (st == NULL) v = src. With giv (multigrid only)
+// the first leg normalises by 1/||src|| from the norm partials in
+// giv->partial and hosts the Givens step of the previous column.
 int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const SolveState* st,
-            cplx* vout, cplx* z, hipStream_t s) {
+            cplx* vout, cplx* z, hipStream_t s, const GivensArgs* giv = nullptr) {
     const double N = (double)p->N;
     const double* scale = st ? &st->scale : nullptr;
     const int* active = st ? &st->active : nullptr;
@@ -304,8 +306,9 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const S
     cplx* x2 = at<cplx>(ws, L.t[0]);
     const double N1 = (double)nx.size();
     TIMED(HH_KERNEL_VC_DOWN, 72.0 * N + 16.0 * N1,
-          launch_vc_fine_down(M, src, scale, vout, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
-                              at<cplx>(ws, L.bc[1]), active, s));
+          launch_vc_fine_down(M, src, scale, giv ? giv->partial : nullptr, giv ? giv->nb : 0,
+                              vout, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+                              at<cplx>(ws, L.bc[1]), active, giv, s));
     const cplx* b = vout ? vout : src;
     CHK(vcycle_coarse(p, L, ws, 1, active, s));
     TIMED(HH_KERNEL_VC_UP, 72.0 * N + 16.0 * N1,
@@ -781,6 +784,13 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
         // close to convergence: learn whether this cycle opens before enqueuing it
         if (last_est <= tol)
             CHK(wait_for(p, s, [&](const RecView& r) { return r.done || r.cycles >= cycle; }));
+        // The Givens step of column j runs inside the first V-cycle leg of step
+        // j + 1 when the multigrid path is taken; the last column's (or one
+        // whose next step is not enqueued) runs as a kernel of its own.
+        const bool fold = !no_prec && p->ndim == 2 && p->levels.size() >= 2 &&
+                          m <= vc_fine_down_givens_capacity(op_M(p));
+        const GivensArgs giv{st, h1, h2, partial, L.nbN, R, cs, sn, g, drec, dhist};
+        bool givens_pending = false;
         bool closed = false;
         for (int j = 0; j < m; ++j) {
             if (j >= kLookahead)
@@ -801,7 +811,8 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
                 HIPCHK(launch_normalize_pred(w, st, vj, N, s));
             } else {
                 cplx* zz = Z + (size_t)j * N;
-                CHK(precond(p, L, ws, w, st, vj, zz, s));
+                CHK(precond(p, L, ws, w, st, vj, zz, s, givens_pending ? &giv : nullptr));
+                givens_pending = false;
                 zj = zz;
             }
             TIMED(HH_KERNEL_APPLY_DOT, (40.0 + 16.0 * kk) * (double)N,
@@ -814,10 +825,15 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
                   launch_reduce_pred(partial, L.nbN, kk, h2, active, s));
             TIMED(HH_KERNEL_AXPY_NORM, (kk + 2) * 16.0 * (double)N,
                   launch_axpy_norm(V, N, kk, h2, w, partial, active, s));
-            TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbN,
-                  launch_givens_step(st, h1, h2, partial, L.nbN, R, cs, sn, g, drec, dhist, s));
+            if (fold) {
+                givens_pending = true;
+            } else {
+                TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbN, launch_givens_step(giv, s));
+            }
         }
-        (void)closed;
+        // a pending step after a break belongs to a cycle the device has closed
+        if (givens_pending && !closed)
+            TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbN, launch_givens_step(giv, s));
         // the cycle closes on a step (or the solve ended at its start)
         CHK(wait_for(p, s, [&](const RecView& r) { return r.done || r.stops >= cycle; }));
         const RecView r = read_rec(p->rec);

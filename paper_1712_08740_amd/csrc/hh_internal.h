@@ -119,6 +119,19 @@ struct CoarseOp {
     const cplx* wdinv;   // omega_J / diag per node (V-cycle smoother)
 };
 
+// Largest restart length (columns of the least-squares problem)
+constexpr int kMaxColumns = 1024;
+
+// Workgroups of a launch are handed to the 8 XCDs round-robin by linear id.
+// Map the linear id w (< n) to a logical tile index so that each XCD runs a
+// contiguous range of tiles: neighbouring tiles then share halo data in the
+// same L2.
+__device__ __forceinline__ int xcd_tile(int w, int n) {
+    const int x = w & 7, loc = w >> 3;
+    const int q = n >> 3, r = n & 7;
+    return x < r ? x * (q + 1) + loc : r * (q + 1) + (x - r) * q + loc;
+}
+
 struct Level {
     int nz, nx;
     double hz, hx;
@@ -210,9 +223,8 @@ hipError_t launch_residual_norm(const FineOp& op, const cplx* b, const cplx* u, 
                                 cplx* partial, const int* done, hipStream_t s);
 hipError_t launch_cycle_start(SolveState* st, const cplx* partial, int nb, cplx* g,
                               HostRecord* rec, hipStream_t s);
-hipError_t launch_givens_step(SolveState* st, const cplx* h1, const cplx* h2, const cplx* partial,
-                              int nb, cplx* R, double* cs, cplx* sn, cplx* g, HostRecord* rec,
-                              double* hist, hipStream_t s);
+struct GivensArgs;
+hipError_t launch_givens_step(const GivensArgs& a, hipStream_t s);
 // y = R^{-1} g, x += Z y for the st->k columns of the cycle, then st->k = 0
 hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
                                const cplx* Z, int64_t n, cplx* x, hipStream_t s);
@@ -227,9 +239,16 @@ hipError_t launch_vc_gemv(int n, const cplx* A, const cplx* x, cplx* y, const in
 // temporally blocked legs (vcycle_tiled.hip): down = two pre-sweeps from zero,
 // residual and restriction; up = prolongation and two post-sweeps
 // (the smoother weight enters through op.wdinv = omega_J / diag)
+// The fine down leg normalises its input: v = s * src is written to bout and
+// the outputs are those of v, with s = *scale, or s = 1/||src|| from the
+// per-block sums of |src|^2 in npart (nbn entries) when npart is given. With
+// giv non-null and giv->st set, one extra workgroup performs that Givens step
+// (restart length at most vc_fine_down_givens_capacity(op)).
 hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, const double* scale,
-                               cplx* bout, cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc,
-                               const int* active, hipStream_t s);
+                               const cplx* npart, int nbn, cplx* bout, cplx* x2, int hz, int hx,
+                               int nzc, int nxc, cplx* bc, const int* active,
+                               const GivensArgs* giv, hipStream_t s);
+int vc_fine_down_givens_capacity(const FineOp& op);
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz,
                                  int hx, int nzc, int nxc, cplx* bc, const int* active,
                                  hipStream_t s);

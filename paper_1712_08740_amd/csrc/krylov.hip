@@ -6,7 +6,7 @@
 // Reductions are two-stage with a fixed summation order (per-block partial
 // sums, then one pass over the partials), so results are bitwise
 // reproducible from run to run.
-#include "hh_internal.h"
+#include "givens.h"
 
 namespace hh {
 
@@ -369,83 +369,12 @@ __global__ void __launch_bounds__(256) k_cycle_start(SolveState* st, const cplx*
     __threadfence_system();
 }
 
-// Givens step on column j (single block): ||w|| from the per-block partials,
-// column = h1 + h2, previous rotations, new rotation, residual estimate,
-// stop decision, history entry for the host.
-__global__ void __launch_bounds__(256) k_givens_step(SolveState* st, const cplx* __restrict__ h1,
-                                                     const cplx* __restrict__ h2,
-                                                     const cplx* __restrict__ partial, int nb,
-                                                     cplx* __restrict__ R, double* __restrict__ cs,
-                                                     cplx* __restrict__ sn, cplx* __restrict__ g,
-                                                     HostRecord* rec, double* hist) {
-    if (st->active == 0) return;
-    __shared__ double sh[4];
-    __shared__ cplx scol[1026];
-    __shared__ double scs[1024];
-    __shared__ cplx ssn[1024];
-    const double hn2 = block_sum_partials(partial, nb, sh);
-    const int j = st->j;
-    // stage the column and the previous rotations with parallel loads
-    for (int i = threadIdx.x; i <= j; i += 256) scol[i] = cadd(h1[i], h2[i]);
-    for (int i = threadIdx.x; i < j; i += 256) {
-        scs[i] = cs[i];
-        ssn[i] = sn[i];
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    const int ld = st->m + 1;
-    cplx* col = scol;
-    const double hn = sqrt(hn2);
-    col[j + 1] = mk(hn, 0.0);
-    for (int i = 0; i < j; ++i) {
-        const cplx p = col[i], q = col[i + 1];
-        col[i] = cadd(cscale(p, scs[i]), cmul(ssn[i], q));
-        col[i + 1] = csub(cscale(q, scs[i]), cmulc(ssn[i], p));
-    }
-    const cplx a = col[j];
-    double c;
-    cplx s;
-    if (hn == 0.0) {
-        c = 1.0; s = mk(0.0, 0.0);
-    } else if (a.x == 0.0 && a.y == 0.0) {
-        c = 0.0; s = mk(1.0, 0.0);
-    } else {
-        const double aa = sqrt(cabs2(a));
-        const double t = sqrt(aa * aa + hn * hn);
-        c = aa / t;
-        s = cscale(mk(a.x / aa, a.y / aa), hn / t);
-    }
-    cs[j] = c;
-    sn[j] = s;
-    col[j] = cadd(cscale(a, c), cscale(s, hn));
-    col[j + 1] = mk(0.0, 0.0);
-    cplx* Rcol = R + (int64_t)j * ld;
-    for (int i = 0; i <= j + 1; ++i) Rcol[i] = col[i];
-    const cplx gj = g[j];
-    g[j + 1] = csub(mk(0.0, 0.0), cmulc(s, gj));
-    g[j] = cscale(gj, c);
-    const double est = sqrt(cabs2(g[j + 1])) / st->beta0;
-    const int it = st->it + 1;
-    const int bad = !(isfinite(est) && isfinite(hn));
-    const int stop = bad || hn == 0.0 || est <= st->tol || it >= st->max_iters || j + 1 >= st->m;
-    st->it = it;
-    st->j = j + 1;
-    st->k = j + 1;
-    st->scale = hn > 0.0 ? 1.0 / hn : 0.0;
-    if (stop) st->active = 0;
-    if (bad) {
-        st->done = 1;
-        st->status = -4;
-    }
-    hist[it] = est;
-    rec->it = it;
-    rec->est = est;
-    rec->jstep = j + 1;
-    rec->status = st->status;
-    __threadfence_system();          // the fields above are visible before the flags
-    if (stop) rec->stops += 1;
-    rec->done = st->done;
-    rec->seq += 1;
+// Givens step on column j as a kernel of its own (single block)
+__global__ void __launch_bounds__(256) k_givens_step(GivensArgs a) {
+    __shared__ cplx scol[kMaxColumns + 2];
+    __shared__ double scs[kMaxColumns];
+    __shared__ cplx ssn[kMaxColumns];
+    givens_body(a, scol, scs, ssn);
 }
 
 // y = R^{-1} g (k = st->k columns), then u += Z y; one block of 256 threads
@@ -630,11 +559,8 @@ hipError_t launch_cycle_start(SolveState* st, const cplx* partial, int nb, cplx*
     HH_LAUNCH(k_cycle_start, dim3(1), dim3(256), 0, s, st, partial, nb, g, rec);
     return hipGetLastError();
 }
-hipError_t launch_givens_step(SolveState* st, const cplx* h1, const cplx* h2, const cplx* partial,
-                              int nb, cplx* R, double* cs, cplx* sn, cplx* g, HostRecord* rec,
-                              double* hist, hipStream_t s) {
-    HH_LAUNCH(k_givens_step, dim3(1), dim3(256), 0, s, st, h1, h2, partial, nb, R, cs, sn,
-                       g, rec, hist);
+hipError_t launch_givens_step(const GivensArgs& a, hipStream_t s) {
+    HH_LAUNCH(k_givens_step, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,

@@ -13,7 +13,7 @@
 // The operator of a level is a policy: Fine5 (level 0: the matrix-free
 // 5-point stencil of M with absorbing rows, coefficients from m^2) or Coarse9
 // (Galerkin levels: 9 complex coefficient planes).
-#include "hh_internal.h"
+#include "givens.h"
 
 namespace hh {
 
@@ -21,7 +21,13 @@ namespace {
 
 constexpr int NT = 128;    // threads per block
 
-__device__ __forceinline__ bool inactive(const int* active) { return active && *active == 0; }
+// The flag may be cleared by a Givens step running as another workgroup of
+// the same launch (the fine down leg hosts it): read it atomically. Blocks
+// that still see it set do work the solver then ignores.
+__device__ __forceinline__ bool inactive(const int* active) {
+    return active && __hip_atomic_load(const_cast<int*>(active), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT) == 0;
+}
 
 // Row of the 5-point fine operator: a_p = diag, couplings -cx (x) and -cz (z).
 struct Row5 {
@@ -106,30 +112,47 @@ __device__ __forceinline__ bool in_grid(int z, int x, int nz, int nx) {
 // axis the fine region of the residual is [2c0 - 1, 2(c0 + TC) - 1], along
 // an unhalved axis [c0, c0 + TC - 1]; x2 needs one more node on each side,
 // x1 (and b, D) two more.
+//
+// The leg is linear in its input, so the normalisation of the Krylov vector
+// (v = s * src) is applied to the outputs only: s comes from *scale, or, when
+// npart is given, from the per-block sums of |src|^2 (s = 1/||src||), and the
+// sweeps run on src while that sum is still in flight. With giv.st set the
+// launch has one workgroup more, which performs the Givens step of the
+// previous Arnoldi column.
 // ---------------------------------------------------------------------------
+template <int W1>
+constexpr int givens_capacity() { return W1 - 2; }
+
 template <class OP, int TCX, int TCZ>
 __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
                                              const double* __restrict__ scale,
+                                             const cplx* __restrict__ npart, int nbn,
                                              cplx* __restrict__ bout, cplx* __restrict__ x2out,
                                              int hz, int hx, int nzc, int nxc,
                                              cplx* __restrict__ bc, double rscale,
-                                             const int* __restrict__ active) {
-    if (inactive(active)) return;
+                                             const int* __restrict__ active, int ntx, int ntiles,
+                                             GivensArgs giv) {
     constexpr int W1X = 2 * TCX + 5, W1Z = 2 * TCZ + 5;   // largest x1 region
     __shared__ cplx sb[W1X * W1Z];
     __shared__ cplx sw[W1X * W1Z];                          // omega_J / diag
     __shared__ cplx s1[W1X * W1Z];
     __shared__ cplx s2[W1X * W1Z];
     __shared__ typename OP::Row srow[W1X * W1Z];           // rows of the x1 region
+    __shared__ double s_scale;
+    if ((int)blockIdx.x == ntiles) {                       // the hosted Givens step
+        givens_body(giv, sb, reinterpret_cast<double*>(sw), s1);
+        return;
+    }
+    if (inactive(active)) return;
+    const int tile = xcd_tile(blockIdx.x, ntiles);
     const int nz = A.nz(), nx = A.nx();
-    const int cx0 = blockIdx.x * TCX, cz0 = blockIdx.y * TCZ;
+    const int cx0 = (tile % ntx) * TCX, cz0 = (tile / ntx) * TCZ;
     const int rlx = hx ? 2 * cx0 - 1 : cx0, rhx = hx ? 2 * (cx0 + TCX) - 1 : cx0 + TCX - 1;
     const int rlz = hz ? 2 * cz0 - 1 : cz0, rhz = hz ? 2 * (cz0 + TCZ) - 1 : cz0 + TCZ - 1;
     const int ox = rlx - 2, oz = rlz - 2;                  // origin of the x1 region
     const int wx = rhx - rlx + 5, wz = rhz - rlz + 5;      // x1 region size (row stride wx)
     const int olx = hx ? 2 * cx0 : cx0, ohx = hx ? 2 * (cx0 + TCX) - 1 : cx0 + TCX - 1;
     const int olz = hz ? 2 * cz0 : cz0, ohz = hz ? 2 * (cz0 + TCZ) - 1 : cz0 + TCZ - 1;
-    const double s = scale ? scale[0] : 1.0;
     const int n1 = wx * wz;
     constexpr int SL1 = (W1X * W1Z + NT - 1) / NT;
     // phase 1: b, the operator rows and x1 on the x1 region (the only global reads)
@@ -142,11 +165,10 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
             typename OP::Row r = OP::zero_row();
             if (in_grid(qz, qx, nz, nx)) {
                 const int64_t q = (int64_t)qz * nx + qx;
-                bq = cscale(src[q], s);
+                bq = src[q];
                 r = A.row(qz, qx);
                 wq = A.wd(qz, qx);
                 x1 = cmul(bq, wq);
-                if (bout && qz >= olz && qz <= ohz && qx >= olx && qx <= ohx) bout[q] = bq;
             }
             sb[i] = bq;
             sw[i] = wq;
@@ -154,7 +176,20 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
             s1[i] = x1;
         }
     }
+    if (npart && threadIdx.x < 64) {
+        const double t = wave_sum_re(npart, nbn, threadIdx.x);
+        if (threadIdx.x == 0) s_scale = inv_norm(t);
+    }
     __syncthreads();
+    const double s = npart ? s_scale : (scale ? scale[0] : 1.0);
+    if (bout) {
+        const int tox = ohx - olx + 1, ton = tox * (ohz - olz + 1);
+        for (int t = threadIdx.x; t < ton; t += NT) {
+            const int qz = olz + t / tox, qx = olx + t % tox;
+            if (qz < nz && qx < nx)
+                bout[(int64_t)qz * nx + qx] = cscale(sb[(qz - oz) * wx + (qx - ox)], s);
+        }
+    }
     // phase 2: x2 on the x1 region shrunk by one node (stored at the same local index)
     const int w2x = wx - 2, n2 = w2x * (wz - 2);
 #pragma unroll
@@ -170,7 +205,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
                 const cplx ax = A.apply(r, s1, i, wx);
                 x2 = cadd(s1[i], cmul(csub(sb[i], ax), sw[i]));
                 if (qz >= olz && qz <= ohz && qx >= olx && qx <= ohx)
-                    x2out[(int64_t)qz * nx + qx] = x2;
+                    x2out[(int64_t)qz * nx + qx] = cscale(x2, s);
             }
             s2[i] = x2;
         }
@@ -206,7 +241,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
                 acc = cadd(acc, cscale(s1[(lz + dz) * wx + (lx + dx)], w));
             }
         }
-        bc[(int64_t)Iz * nxc + Ix] = cscale(acc, rscale);
+        bc[(int64_t)Iz * nxc + Ix] = cscale(acc, rscale * s);
     }
 }
 
@@ -227,7 +262,7 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
                                            const cplx* __restrict__ x2,
                                            const cplx* __restrict__ e, int nxc,
                                            cplx* __restrict__ out,
-                                           const int* __restrict__ active) {
+                                           const int* __restrict__ active, int ntx, int ntiles) {
     if (inactive(active)) return;
     constexpr int WX = TX + 4, WZ = TZ + 4;
     constexpr int W3X = TX + 2, W3Z = TZ + 2;
@@ -237,7 +272,8 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
     __shared__ cplx sw[W3X * W3Z];                    // omega_J / diag on the tile + 1
     __shared__ typename OP::Row srow[W3X * W3Z];      // rows on the tile + 1
     const int nz = A.nz(), nx = A.nx();
-    const int fx0 = blockIdx.x * TX, fz0 = blockIdx.y * TZ;
+    const int tile = xcd_tile(blockIdx.x, ntiles);
+    const int fx0 = (tile % ntx) * TX, fz0 = (tile / ntx) * TZ;
     const int ox = fx0 - 2, oz = fz0 - 2;
     constexpr int SL = (WX * WZ + NT - 1) / NT;
     constexpr int SL3 = (W3X * W3Z + NT - 1) / NT;
@@ -326,55 +362,79 @@ constexpr int64_t kBigLevel = 40000;
 // Large tiles (less halo work) for the big 5-point grid; small tiles (more
 // blocks in flight, and room in LDS for the 9-coefficient rows) elsewhere.
 template <class OP>
-hipError_t down_dispatch(const OP& A, const cplx* src, const double* scale, cplx* bout,
-                         cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc, const int* active,
-                         hipStream_t s) {
-    const double rs = inv2dc(hz, hx);
-    if constexpr (sizeof(typename OP::Row) <= 32) {
-        if ((int64_t)A.nz() * A.nx() >= kBigLevel) {
-            const dim3 g((nxc + 15) / 16, (nzc + 3) / 4);
-            HH_LAUNCH((k_down<OP, 16, 4>), g, dim3(NT), 0, s, A, src, scale, bout, x2, hz, hx,
-                      nzc, nxc, bc, rs, active);
-            return hipGetLastError();
-        }
-    }
-    const dim3 g((nxc + 7) / 8, (nzc + 3) / 4);
-    HH_LAUNCH((k_down<OP, 8, 4>), g, dim3(NT), 0, s, A, src, scale, bout, x2, hz, hx, nzc, nxc,
-              bc, rs, active);
+bool big_tiles(const OP& A) {
+    if constexpr (sizeof(typename OP::Row) <= 32)
+        return (int64_t)A.nz() * A.nx() >= kBigLevel;
+    return false;
+}
+
+template <class OP, int TCX, int TCZ>
+hipError_t down_launch(const OP& A, const cplx* src, const double* scale, const cplx* npart,
+                       int nbn, cplx* bout, cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc,
+                       const int* active, const GivensArgs& giv, hipStream_t s) {
+    const int ntx = (nxc + TCX - 1) / TCX, ntz = (nzc + TCZ - 1) / TCZ;
+    const int ntiles = ntx * ntz;
+    const dim3 g(ntiles + (giv.st ? 1 : 0));
+    HH_LAUNCH((k_down<OP, TCX, TCZ>), g, dim3(NT), 0, s, A, src, scale, npart, nbn, bout, x2, hz,
+              hx, nzc, nxc, bc, inv2dc(hz, hx), active, ntx, ntiles, giv);
+    return hipGetLastError();
+}
+
+// Large tiles (less halo work) for the big 5-point grid; small tiles (more
+// blocks in flight, and room in LDS for the 9-coefficient rows) elsewhere.
+template <class OP>
+hipError_t down_dispatch(const OP& A, const cplx* src, const double* scale, const cplx* npart,
+                         int nbn, cplx* bout, cplx* x2, int hz, int hx, int nzc, int nxc,
+                         cplx* bc, const int* active, const GivensArgs& giv, hipStream_t s) {
+    if (big_tiles(A))
+        return down_launch<OP, 16, 4>(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
+                                      active, giv, s);
+    return down_launch<OP, 8, 4>(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
+                                 active, giv, s);
+}
+
+template <class OP, int TX, int TZ>
+hipError_t up_launch(const OP& A, int hz, int hx, const cplx* b, const cplx* x2, const cplx* e,
+                     int nxc, cplx* out, const int* active, hipStream_t s) {
+    const int ntx = (A.nx() + TX - 1) / TX, ntz = (A.nz() + TZ - 1) / TZ;
+    HH_LAUNCH((k_up<OP, TX, TZ>), dim3(ntx * ntz), dim3(NT), 0, s, A, hz, hx, b, x2, e, nxc, out,
+              active, ntx, ntx * ntz);
     return hipGetLastError();
 }
 
 template <class OP>
 hipError_t up_dispatch(const OP& A, int hz, int hx, const cplx* b, const cplx* x2,
                        const cplx* e, int nxc, cplx* out, const int* active, hipStream_t s) {
-    if constexpr (sizeof(typename OP::Row) <= 32) {
-        if ((int64_t)A.nz() * A.nx() >= kBigLevel) {
-            const dim3 g((A.nx() + 31) / 32, (A.nz() + 7) / 8);
-            HH_LAUNCH((k_up<OP, 32, 8>), g, dim3(NT), 0, s, A, hz, hx, b, x2, e, nxc, out,
-                      active);
-            return hipGetLastError();
-        }
-    }
-    const dim3 g((A.nx() + 15) / 16, (A.nz() + 3) / 4);
-    HH_LAUNCH((k_up<OP, 16, 4>), g, dim3(NT), 0, s, A, hz, hx, b, x2, e, nxc, out, active);
-    return hipGetLastError();
+    if (big_tiles(A)) return up_launch<OP, 32, 8>(A, hz, hx, b, x2, e, nxc, out, active, s);
+    return up_launch<OP, 16, 4>(A, hz, hx, b, x2, e, nxc, out, active, s);
 }
 
 }  // namespace
 
 hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, const double* scale,
-                               cplx* bout, cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc,
-                               const int* active, hipStream_t s) {
+                               const cplx* npart, int nbn, cplx* bout, cplx* x2, int hz, int hx,
+                               int nzc, int nxc, cplx* bc, const int* active,
+                               const GivensArgs* giv, hipStream_t s) {
     Fine5 A;
     A.op = op;
-    return down_dispatch(A, src, scale, bout, x2, hz, hx, nzc, nxc, bc, active, s);
+    const GivensArgs none{};
+    return down_dispatch(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc, active,
+                         giv ? *giv : none, s);
+}
+
+int vc_fine_down_givens_capacity(const FineOp& op) {
+    Fine5 A;
+    A.op = op;
+    return big_tiles(A) ? givens_capacity<(2 * 16 + 5) * (2 * 4 + 5)>()
+                        : givens_capacity<(2 * 8 + 5) * (2 * 4 + 5)>();
 }
 
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz, int hx,
                                  int nzc, int nxc, cplx* bc, const int* active, hipStream_t s) {
     Coarse9 A;
     A.op = op;
-    return down_dispatch(A, b, nullptr, nullptr, x2, hz, hx, nzc, nxc, bc, active, s);
+    return down_dispatch(A, b, nullptr, nullptr, 0, nullptr, x2, hz, hx, nzc, nxc, bc, active,
+                         GivensArgs{}, s);
 }
 
 hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b, const cplx* x2,

@@ -293,6 +293,19 @@ def test_solve_is_bitwise_reproducible(hh):
     assert np.array_equal(a.history, b.history)
 
 
+def test_hosted_and_separate_givens_steps_agree(hh):
+    """A restart length above what the first V-cycle leg can stage runs each
+    Givens step as a kernel of its own; the arithmetic is the same, so a solve
+    that finishes inside one cycle gives the same bits either way."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    a = P.solve(_t(w.source), tol=w.tol, restart=40)
+    b = P.solve(_t(w.source), tol=w.tol, restart=600)
+    assert a.iterations == b.iterations
+    assert np.array_equal(_np(a.u), _np(b.u))
+    assert np.array_equal(a.history, b.history)
+
+
 def test_kernel_timer_counts_working_launches(hh):
     """The dispatch-stamped timer counts one launch per Arnoldi step that did work
     (steps enqueued ahead and skipped on the device are not counted) and sums the
@@ -318,7 +331,8 @@ def test_kernel_timer_counts_working_launches(hh):
 @pytest.mark.gpu
 def test_kernel_timer_classes_cover_the_step(hh):
     """Every kernel class of a 2D multigrid step is timed with one launch per
-    working step (per level for the coarse legs, two reductions per step), and
+    working step (per level for the coarse legs, two reductions per step; the
+    Givens step only where it cannot ride on the next V-cycle leg), and
     the byte model of the fine legs is 72 B per fine node + 16 B per coarse node."""
     w = wl.grf_401x201()
     P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
@@ -327,7 +341,7 @@ def test_kernel_timer_classes_cover_the_step(hh):
     shapes = [P.level_shape(l) for l in range(nl)]
     res = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
     it = res.iterations
-    per_step = {"apply_dot": 1, "axpy_dot": 1, "axpy_norm": 1, "givens": 1, "reduce": 2,
+    per_step = {"apply_dot": 1, "axpy_dot": 1, "axpy_norm": 1, "reduce": 2,
                 "vc_down": 1, "vc_up": 1, "gemv": 1,
                 "vc_down_coarse": nl - 2, "vc_up_coarse": nl - 2}
     for k, n in per_step.items():
@@ -340,6 +354,12 @@ def test_kernel_timer_classes_cover_the_step(hh):
         if k == "vc_down":
             n1 = shapes[1][0] * shapes[1][1]
             assert nbytes == pytest.approx(it * (72.0 * N + 16.0 * n1), rel=1e-12)
+    # the Givens step of a column runs inside the next step's first V-cycle leg;
+    # only the column that closes a full cycle (30 + 6 steps here) has a launch
+    assert it == w.restart + 6
+    P.kernel_timer_start("givens")
+    P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    assert P.kernel_timer_read()[0] == 1
     P.kernel_timer_start("pcr")
     P.solve(_t(w.source), tol=w.tol, restart=w.restart)
     assert P.kernel_timer_read()[0] == 0
