@@ -60,6 +60,14 @@ enum hh_status {
 
 /* hh_solve flags */
 #define HH_NO_PRECOND 1u    /* plain GMRES on H (the paper's comparison, Fig. 3b/4) */
+#define HH_PRECOND_F32 2u   /* the preconditioner M^{-1} in complex64 arithmetic: m^2,
+                               smoother weights, Galerkin operators and coarsest inverse
+                               rounded to single precision (round to nearest even), the
+                               stored preconditioned vectors Z in complex64; the outer
+                               flexible GMRES (Arnoldi basis, Hessenberg least squares,
+                               residual recomputation, solution update) stays complex128.
+                               Flexible GMRES takes any fixed preconditioner, so the
+                               tolerance is met in full precision. Excludes HH_NO_PRECOND. */
 
 /* Largest coarsest-grid size (unknowns) inverted densely. */
 #define HH_MAX_COARSE 4096
@@ -102,7 +110,7 @@ int hh_workspace_bytes(hh_problem p, int restart, size_t* bytes);
  *   tol       : relative tolerance in (0, 1) on ||W f - H u||_2 / ||W f||_2.
  *   restart   : Krylov basis length per cycle, 1..1024.
  *   max_iters : budget of preconditioned operator applications, >= 1.
- *   flags     : 0 or HH_NO_PRECOND.
+ *   flags     : 0, HH_NO_PRECOND or HH_PRECOND_F32.
  *   workspace_dev / workspace_bytes : caller-owned device scratch of at least
  *               hh_workspace_bytes(p, restart) bytes; contents are overwritten.
  *   u_dev     : complex128 output wavefield, grid-shaped (caller-owned).
@@ -160,6 +168,14 @@ int hh_apply_level_operator(hh_problem p, int level, const void* x_dev, void* y_
  */
 int hh_apply_precond(hh_problem p, const void* v_dev, void* z_dev, void* workspace_dev,
                      size_t workspace_bytes, void* stream);
+
+/*
+ * hh_apply_precond_f32 -- the same preconditioner in complex64 (HH_PRECOND_F32):
+ * v_dev complex128 (read, rounded inside), z_dev complex64 (written),
+ * grid-shaped; workspace as for hh_solve.
+ */
+int hh_apply_precond_f32(hh_problem p, const void* v_dev, void* z_dev, void* workspace_dev,
+                         size_t workspace_bytes, void* stream);
 
 /*
  * hh_orthogonalize -- one classical Gram-Schmidt step with reorthogonalisation

@@ -64,6 +64,8 @@ struct LevelData {
     double wj = kJacobiWeight;      // Jacobi weight of this level's smoother
     cplx* C = nullptr;              // 9-point Galerkin operator (levels >= 1)
     cplx* wd = nullptr;             // wj / diag per node (smoothing levels)
+    cplxf* Cf = nullptr;            // the same, rounded to complex64
+    cplxf* wdf = nullptr;
     int64_t size() const { return (int64_t)nz * nx; }
 };
 
@@ -82,8 +84,10 @@ struct hh_problem_s {
     double beta1 = 1.0, beta2 = 0.5;
     double mmax = 0;
     double* m2 = nullptr;
+    float* m2f = nullptr;           // m^2 rounded to float (single-precision preconditioner)
     std::vector<LevelData> levels;
     cplx* cinv = nullptr;           // explicit inverse of the coarsest operator
+    cplxf* cinvf = nullptr;         // ... rounded to complex64
     int nc = 0;
     cplx* gj_scratch = nullptr;
     int* gj_perm = nullptr;
@@ -140,6 +144,49 @@ CoarseOp coarse_op(const LevelData& L) {
     return op;
 }
 
+// The preconditioner in complex64: the same operator with its parameters,
+// m^2, smoother weights, Galerkin planes and coarsest inverse rounded to
+// single precision (the double-precision set-up is done first).
+FineOpT<float> op_Mf(const hh_problem_s* p) {
+    const FineOp d = op_M(p);
+    FineOpT<float> op;
+    op.nz = d.nz;
+    op.nx = d.nx;
+    op.ndim = d.ndim;
+    op.ihx2 = (float)d.ihx2;
+    op.ihz2 = (float)d.ihz2;
+    op.ihx = (float)d.ihx;
+    op.ihz = (float)d.ihz;
+    op.omega = (float)d.omega;
+    op.omega2 = (float)d.omega2;
+    op.sr = (float)d.sr;
+    op.si = (float)d.si;
+    op.m2 = p->m2f;
+    op.wdinv = p->levels.empty() ? nullptr : p->levels[0].wdf;
+    return op;
+}
+CoarseOpT<float> coarse_opf(const LevelData& L) {
+    CoarseOpT<float> op;
+    op.nz = L.nz;
+    op.nx = L.nx;
+    op.C = L.Cf;
+    op.wdinv = L.wdf;
+    return op;
+}
+
+// precision-generic access to the preconditioner's data
+template <class T> struct Prec;
+template <> struct Prec<double> {
+    static FineOp fine(const hh_problem_s* p) { return op_M(p); }
+    static CoarseOp coarse(const LevelData& L) { return coarse_op(L); }
+    static const cplx* cinv(const hh_problem_s* p) { return p->cinv; }
+};
+template <> struct Prec<float> {
+    static FineOpT<float> fine(const hh_problem_s* p) { return op_Mf(p); }
+    static CoarseOpT<float> coarse(const LevelData& L) { return coarse_opf(L); }
+    static const cplxf* cinv(const hh_problem_s* p) { return p->cinvf; }
+};
+
 // ---------------------------------------------------------------------------
 // kernel timer
 // ---------------------------------------------------------------------------
@@ -195,7 +242,9 @@ struct Layout {
     int nbA, nbN, nbmax;
 };
 
-Layout layout(const hh_problem_s* p, int m) {
+// es: bytes per complex value of Z and the V-cycle vectors (16, or 8 when
+// the preconditioner runs in complex64; the 16-byte layout is the larger).
+Layout layout(const hh_problem_s* p, int m, size_t es = sizeof(cplx)) {
     Layout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -206,7 +255,7 @@ Layout layout(const hh_problem_s* p, int m) {
     const size_t c = sizeof(cplx);
     const size_t N = (size_t)p->N;
     L.V = take((size_t)(m + 1) * N * c);
-    L.Z = take((size_t)m * N * c);
+    L.Z = take((size_t)m * N * es);
     L.b = take(N * c);
     L.w = take(N * c);
     const int nl = (int)p->levels.size();
@@ -216,10 +265,10 @@ Layout layout(const hh_problem_s* p, int m) {
     if (p->ndim == 2) {
         for (int l = 0; l < nl; ++l) {
             const size_t n = (size_t)p->levels[l].size();
-            if (l < nl - 1) L.t[l] = take(n * c);
+            if (l < nl - 1) L.t[l] = take(n * es);
             if (l >= 1) {
-                L.bc[l] = take(n * c);
-                L.ec[l] = take(n * c);
+                L.bc[l] = take(n * es);
+                L.ec[l] = take(n * es);
             }
         }
     }
@@ -247,49 +296,63 @@ T* at(void* base, size_t off) {
 // ---------------------------------------------------------------------------
 // preconditioner
 // ---------------------------------------------------------------------------
-// One V(2,2) cycle on level l >= 1: ec_l = V(l, bc_l), one kernel per leg.
+// One V(2,2) cycle on level l >= 1: ec_l = V(l, bc_l), one kernel per leg,
+// in precision T.
+template <class T>
 int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* active,
                   hipStream_t s) {
+    typedef typename Cx<T>::type C;
+    const double es = (double)sizeof(C), rs = (double)sizeof(T);
     const int nl = (int)p->levels.size();
-    cplx* b = at<cplx>(ws, L.bc[l]);
-    cplx* x = at<cplx>(ws, L.ec[l]);
+    C* b = at<C>(ws, L.bc[l]);
+    C* x = at<C>(ws, L.ec[l]);
     if (l == nl - 1) {
         const double nc = p->nc;
-        TIMED(HH_KERNEL_GEMV, (nc * nc + 2 * nc) * sizeof(cplx),
-              launch_vc_gemv(p->nc, p->cinv, b, x, active, s));
+        TIMED(HH_KERNEL_GEMV, (nc * nc + 2 * nc) * es,
+              launch_vc_gemv(p->nc, Prec<T>::cinv(p), b, x, active, s));
         return HH_OK;
     }
+    (void)rs;
     const LevelData& lv = p->levels[l];
     const LevelData& nx = p->levels[l + 1];
-    const CoarseOp A = coarse_op(lv);
-    cplx* x2 = at<cplx>(ws, L.t[l]);
+    const auto A = Prec<T>::coarse(lv);
+    C* x2 = at<C>(ws, L.t[l]);
     const double nl_ = (double)lv.size(), nn_ = (double)nx.size();
-    TIMED(HH_KERNEL_VC_DOWN_COARSE, 192.0 * nl_ + 16.0 * nn_,
+    // down: b, 9 coefficients, omega/diag in, x2 out; up: x2, b, 9 coefficients,
+    // omega/diag in, x out (values of es bytes), plus the coarser vector
+    TIMED(HH_KERNEL_VC_DOWN_COARSE, 12.0 * es * nl_ + es * nn_,
           launch_vc_coarse_down(A, b, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
-                                at<cplx>(ws, L.bc[l + 1]), active, s));
-    CHK(vcycle_coarse(p, L, ws, l + 1, active, s));
-    TIMED(HH_KERNEL_VC_UP_COARSE, 208.0 * nl_ + 16.0 * nn_,
-          launch_vc_coarse_up(A, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[l + 1]), nx.nx,
-                              x, active, s));
+                                at<C>(ws, L.bc[l + 1]), active, s));
+    CHK(vcycle_coarse<T>(p, L, ws, l + 1, active, s));
+    TIMED(HH_KERNEL_VC_UP_COARSE, 13.0 * es * nl_ + es * nn_,
+          launch_vc_coarse_up(A, lv.halve_z, lv.halve_x, b, x2, at<C>(ws, L.ec[l + 1]), nx.nx, x,
+                              active, s));
     return HH_OK;
 }
 
-// z = M^{-1} v. Inside a solve (st given) v = st->scale * src is also written
-// to vout (the normalised Krylov basis vector) and every kernel is predicated
-// on st->active; stand-alone (st == NULL) v = src. With giv (multigrid only)
-// the first leg normalises by 1/||src|| from the norm partials in
-// giv->partial and hosts the Givens step of the previous column.
+// z = M^{-1} v in precision T (v and vout stay complex128). Inside a solve
+// (st given) v = st->scale * src is also written to vout (the normalised
+// Krylov basis vector) and every kernel is predicated on st->active;
+// stand-alone (st == NULL) v = src. With giv (multigrid only) the first leg
+// normalises by 1/||src|| from the norm partials in giv->partial and hosts the
+// Givens step of the previous column.
+template <class T>
 int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const SolveState* st,
-            cplx* vout, cplx* z, hipStream_t s, const GivensArgs* giv = nullptr) {
+            cplx* vout, typename Cx<T>::type* z, hipStream_t s,
+            const GivensArgs* giv = nullptr) {
+    typedef typename Cx<T>::type C;
+    const double es = (double)sizeof(C), rs = (double)sizeof(T);
     const double N = (double)p->N;
     const double* scale = st ? &st->scale : nullptr;
     const int* active = st ? &st->active : nullptr;
+    const auto M = Prec<T>::fine(p);
     if (p->ndim == 1) {
-        TIMED(HH_KERNEL_PCR, 56.0 * N, launch_pcr_norm(op_M(p), src, scale, vout, z, active, s));
+        // src, m^2 in; v, z out
+        TIMED(HH_KERNEL_PCR, (32.0 + rs + es) * N,
+              launch_pcr_norm(M, src, scale, vout, z, active, s));
         return HH_OK;
     }
     const int nl = (int)p->levels.size();
-    const FineOp M = op_M(p);
     if (nl == 1) {   // the fine grid is the coarsest: dense inverse only
         const cplx* b = src;
         if (st) {
@@ -297,23 +360,25 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const S
             b = vout;
         }
         const double nc = p->nc;
-        TIMED(HH_KERNEL_GEMV, (nc * nc + 2 * nc) * sizeof(cplx),
-              launch_vc_gemv(p->nc, p->cinv, b, z, active, s));
+        TIMED(HH_KERNEL_GEMV, (nc * nc + 2 * nc) * es,
+              launch_vc_gemv(p->nc, Prec<T>::cinv(p), b, z, active, s));
         return HH_OK;
     }
     const LevelData& lv = p->levels[0];
     const LevelData& nx = p->levels[1];
-    cplx* x2 = at<cplx>(ws, L.t[0]);
+    C* x2 = at<C>(ws, L.t[0]);
     const double N1 = (double)nx.size();
-    TIMED(HH_KERNEL_VC_DOWN, 72.0 * N + 16.0 * N1,
+    // down: w in, v out (complex128), m^2 and omega/diag in, x2 out; up: v in
+    // (complex128), x2, m^2, omega/diag in, z out; plus the coarse vector
+    TIMED(HH_KERNEL_VC_DOWN, (32.0 + rs + 2.0 * es) * N + es * N1,
           launch_vc_fine_down(M, src, scale, giv ? giv->partial : nullptr, giv ? giv->nb : 0,
                               vout, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
-                              at<cplx>(ws, L.bc[1]), active, giv, s));
+                              at<C>(ws, L.bc[1]), active, giv, s));
     const cplx* b = vout ? vout : src;
-    CHK(vcycle_coarse(p, L, ws, 1, active, s));
-    TIMED(HH_KERNEL_VC_UP, 72.0 * N + 16.0 * N1,
-          launch_vc_fine_up(M, lv.halve_z, lv.halve_x, b, x2, at<cplx>(ws, L.ec[1]), nx.nx,
-                            z, active, s));
+    CHK(vcycle_coarse<T>(p, L, ws, 1, active, s));
+    TIMED(HH_KERNEL_VC_UP, (16.0 + rs + 3.0 * es) * N + es * N1,
+          launch_vc_fine_up(M, lv.halve_z, lv.halve_x, b, x2, at<C>(ws, L.ec[1]), nx.nx, z,
+                            active, s));
     return HH_OK;
 }
 
@@ -324,8 +389,12 @@ void free_levels(hh_problem_s* p) {
     for (auto& l : p->levels) {
         if (l.C) (void)hipFree(l.C);
         if (l.wd) (void)hipFree(l.wd);
+        if (l.Cf) (void)hipFree(l.Cf);
+        if (l.wdf) (void)hipFree(l.wdf);
         l.C = nullptr;
         l.wd = nullptr;
+        l.Cf = nullptr;
+        l.wdf = nullptr;
     }
 }
 
@@ -369,11 +438,16 @@ int build_hierarchy(hh_problem_s* p) {
                         " unknowns (more than HH_MAX_COARSE = " +
                         std::to_string(HH_MAX_COARSE) + ")");
     p->nc = (int)nc;
-    for (size_t l = 1; l < p->levels.size(); ++l)
+    for (size_t l = 1; l < p->levels.size(); ++l) {
         HIPCHK(hipMalloc(&p->levels[l].C, 9 * (size_t)p->levels[l].size() * sizeof(cplx)));
-    for (size_t l = 0; l + 1 < p->levels.size(); ++l)
+        HIPCHK(hipMalloc(&p->levels[l].Cf, 9 * (size_t)p->levels[l].size() * sizeof(cplxf)));
+    }
+    for (size_t l = 0; l + 1 < p->levels.size(); ++l) {
         HIPCHK(hipMalloc(&p->levels[l].wd, (size_t)p->levels[l].size() * sizeof(cplx)));
+        HIPCHK(hipMalloc(&p->levels[l].wdf, (size_t)p->levels[l].size() * sizeof(cplxf)));
+    }
     HIPCHK(hipMalloc(&p->cinv, (size_t)nc * nc * sizeof(cplx)));
+    HIPCHK(hipMalloc(&p->cinvf, (size_t)nc * nc * sizeof(cplxf)));
     HIPCHK(hipMalloc(&p->gj_scratch, 3 * (size_t)nc * sizeof(cplx)));
     HIPCHK(hipMalloc(&p->gj_perm, (size_t)nc * sizeof(int)));
     HIPCHK(hipMalloc(&p->fin_partial, (size_t)node_blocks(nc * nc) * sizeof(cplx)));
@@ -417,6 +491,14 @@ int apply_shift(hh_problem_s* p) {
     HIPCHK(hipStreamSynchronize(s));
     if (!std::isfinite(p->nrm2_host->x))
         return fail(HH_ENUMERIC, "coarsest-level operator is singular for this shift");
+    // complex64 copies for the single-precision preconditioner
+    for (int l = 0; l < nl; ++l) {
+        const LevelData& lv = p->levels[l];
+        if (lv.C) HIPCHK(launch_to_c64(lv.C, lv.Cf, 9 * lv.size(), s));
+        if (lv.wd) HIPCHK(launch_to_c64(lv.wd, lv.wdf, lv.size(), s));
+    }
+    HIPCHK(launch_to_c64(p->cinv, p->cinvf, nn, s));
+    HIPCHK(hipStreamSynchronize(s));
     return HH_OK;
 }
 
@@ -424,7 +506,9 @@ void destroy(hh_problem_s* p) {
     if (!p) return;
     free_levels(p);
     if (p->m2) (void)hipFree(p->m2);
+    if (p->m2f) (void)hipFree(p->m2f);
     if (p->cinv) (void)hipFree(p->cinv);
+    if (p->cinvf) (void)hipFree(p->cinvf);
     if (p->gj_scratch) (void)hipFree(p->gj_scratch);
     if (p->gj_perm) (void)hipFree(p->gj_perm);
     if (p->fin_partial) (void)hipFree(p->fin_partial);
@@ -559,6 +643,7 @@ int hh_create_problem(const double* m_dev, int ndim, const int64_t* shape, doubl
     if (nb > 512) nb = 512;
     hipError_t e;
     if ((e = hipMalloc(&p->m2, p->N * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&p->m2f, p->N * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&p->dflag, sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&p->dpartial, 4096 * sizeof(cplx))) != hipSuccess ||
         (e = hipHostMalloc(reinterpret_cast<void**>(&p->nrm2_host), 64 * sizeof(cplx))) !=
@@ -571,6 +656,7 @@ int hh_create_problem(const double* m_dev, int ndim, const int64_t* shape, doubl
     int hflag = 0;
     if ((e = hipMemsetAsync(p->dflag, 0, sizeof(int), s)) != hipSuccess ||
         (e = launch_check_slowness(m_dev, p->N, p->m2, p->dflag, mpart, nb, s)) != hipSuccess ||
+        (e = launch_to_f32(p->m2, p->m2f, p->N, s)) != hipSuccess ||
         (e = hipMemcpyAsync(hpart.data(), mpart, nb * sizeof(double), hipMemcpyDeviceToHost,
                             s)) != hipSuccess ||
         (e = hipMemcpyAsync(&hflag, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s)) !=
@@ -673,8 +759,25 @@ int hh_apply_precond(hh_problem p, const void* v_dev, void* z_dev, void* workspa
     const Layout L = layout(p, 1);
     if (workspace_bytes < L.total) return fail(HH_EINVAL, "workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    CHK(precond(p, L, workspace_dev, static_cast<const cplx*>(v_dev), nullptr, nullptr,
-                static_cast<cplx*>(z_dev), s));
+    CHK(precond<double>(p, L, workspace_dev, static_cast<const cplx*>(v_dev), nullptr, nullptr,
+                        static_cast<cplx*>(z_dev), s));
+    HIPCHK(hipStreamSynchronize(s));
+    return HH_OK;
+}
+
+int hh_apply_precond_f32(hh_problem p, const void* v_dev, void* z_dev, void* workspace_dev,
+                         size_t workspace_bytes, void* stream) {
+    g_err.clear();
+    if (!p) return fail(HH_EINVAL, "problem is NULL");
+    CHK(check_ptr(v_dev, "v_dev"));
+    CHK(check_ptr(z_dev, "z_dev"));
+    CHK(check_ptr(workspace_dev, "workspace_dev"));
+    if (v_dev == z_dev) return fail(HH_EINVAL, "v_dev and z_dev must be distinct");
+    const Layout L = layout(p, 1, sizeof(cplxf));
+    if (workspace_bytes < L.total) return fail(HH_EINVAL, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    CHK(precond<float>(p, L, workspace_dev, static_cast<const cplx*>(v_dev), nullptr, nullptr,
+                       static_cast<cplxf*>(z_dev), s));
     HIPCHK(hipStreamSynchronize(s));
     return HH_OK;
 }
@@ -734,13 +837,16 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
     if (!(tol > 0.0 && tol < 1.0)) return fail(HH_EINVAL, "tol must be in (0, 1)");
     if (restart < 1 || restart > kMaxRestart) return fail(HH_EINVAL, "restart must be in [1, 1024]");
     if (max_iters < 1 || max_iters > (1 << 28)) return fail(HH_EINVAL, "max_iters must be in [1, 2^28]");
-    if (flags & ~HH_NO_PRECOND) return fail(HH_EINVAL, "unknown flag");
+    if (flags & ~(HH_NO_PRECOND | HH_PRECOND_F32)) return fail(HH_EINVAL, "unknown flag");
+    if ((flags & HH_NO_PRECOND) && (flags & HH_PRECOND_F32))
+        return fail(HH_EINVAL, "HH_NO_PRECOND and HH_PRECOND_F32 exclude each other");
     if (hist_cap < 0 || (hist_cap > 0 && !hist_host)) return fail(HH_EINVAL, "bad history buffer");
     if (f_dev == u_dev) return fail(HH_EINVAL, "f_dev and u_dev must be distinct");
     const int m = restart;
-    const Layout L = layout(p, m);
-    if (workspace_bytes < L.total) return fail(HH_EINVAL, "workspace too small");
     const bool no_prec = (flags & HH_NO_PRECOND) != 0;
+    const bool f32 = (flags & HH_PRECOND_F32) != 0;
+    const Layout L = layout(p, m, f32 ? sizeof(cplxf) : sizeof(cplx));
+    if (workspace_bytes < L.total) return fail(HH_EINVAL, "workspace too small");
     CHK(ensure_host_buffers(p, max_iters));
 
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -748,6 +854,7 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
     const int64_t N = p->N;
     cplx* V = at<cplx>(ws, L.V);
     cplx* Z = at<cplx>(ws, L.Z);
+    cplxf* Zf = at<cplxf>(ws, L.Z);
     cplx* b = at<cplx>(ws, L.b);
     cplx* w = at<cplx>(ws, L.w);
     cplx* partial = at<cplx>(ws, L.partial);
@@ -788,7 +895,8 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
         // j + 1 when the multigrid path is taken; the last column's (or one
         // whose next step is not enqueued) runs as a kernel of its own.
         const bool fold = !no_prec && p->ndim == 2 && p->levels.size() >= 2 &&
-                          m <= vc_fine_down_givens_capacity(op_M(p));
+                          m <= (f32 ? vc_fine_down_givens_capacity(op_Mf(p))
+                                    : vc_fine_down_givens_capacity(op_M(p)));
         const GivensArgs giv{st, h1, h2, partial, L.nbN, R, cs, sn, g, drec, dhist};
         bool givens_pending = false;
         bool closed = false;
@@ -806,17 +914,23 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
             p->kt.j = j;
             const int kk = j + 1;
             cplx* vj = V + (size_t)j * N;
-            const cplx* zj = vj;
+            const GivensArgs* gv = givens_pending ? &giv : nullptr;
             if (no_prec) {
                 HIPCHK(launch_normalize_pred(w, st, vj, N, s));
+                TIMED(HH_KERNEL_APPLY_DOT, (40.0 + 16.0 * kk) * (double)N,
+                      launch_apply_dot(H, vj, w, V, kk, partial, active, s));
+            } else if (f32) {
+                cplxf* zz = Zf + (size_t)j * N;
+                CHK(precond<float>(p, L, ws, w, st, vj, zz, s, gv));
+                TIMED(HH_KERNEL_APPLY_DOT, (32.0 + 16.0 * kk) * (double)N,
+                      launch_apply_dot(H, zz, w, V, kk, partial, active, s));
             } else {
                 cplx* zz = Z + (size_t)j * N;
-                CHK(precond(p, L, ws, w, st, vj, zz, s, givens_pending ? &giv : nullptr));
-                givens_pending = false;
-                zj = zz;
+                CHK(precond<double>(p, L, ws, w, st, vj, zz, s, gv));
+                TIMED(HH_KERNEL_APPLY_DOT, (40.0 + 16.0 * kk) * (double)N,
+                      launch_apply_dot(H, zz, w, V, kk, partial, active, s));
             }
-            TIMED(HH_KERNEL_APPLY_DOT, (40.0 + 16.0 * kk) * (double)N,
-                  launch_apply_dot(H, zj, w, V, kk, partial, active, s));
+            givens_pending = false;
             TIMED(HH_KERNEL_REDUCE, 16.0 * kk * (L.nbA + 1),
                   launch_reduce_pred(partial, L.nbA, kk, h1, active, s));
             TIMED(HH_KERNEL_AXPY_DOT, (kk + 2) * 16.0 * (double)N,
@@ -840,7 +954,10 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
         executed.push_back(r.stops >= cycle ? r.jstep : 0);
         last_est = ((const volatile HostRecord*)p->rec)->est;
         if (r.stops < cycle) break;                 // finished at the cycle start
-        HIPCHK(launch_cycle_finish(st, R, g, y, no_prec ? V : Z, N, u, s));
+        if (f32)
+            HIPCHK(launch_cycle_finish(st, R, g, y, Zf, N, u, s));
+        else
+            HIPCHK(launch_cycle_finish(st, R, g, y, no_prec ? V : Z, N, u, s));
         if (r.done) break;                          // non-finite value inside the cycle
     }
     HIPCHK(hipStreamSynchronize(s));

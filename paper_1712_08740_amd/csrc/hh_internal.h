@@ -59,65 +59,121 @@ __host__ __device__ inline cplx cdiv(cplx a, cplx b) {
 }
 __host__ __device__ inline cplx crecip(cplx b) { return cdiv(mk(1.0, 0.0), b); }
 
+// complex64 as float2, for the single-precision preconditioner
+typedef float2 cplxf;
+
+__host__ __device__ inline cplxf mkf(float re, float im) { cplxf c; c.x = re; c.y = im; return c; }
+__host__ __device__ inline cplxf cadd(cplxf a, cplxf b) { return mkf(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cplxf csub(cplxf a, cplxf b) { return mkf(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cplxf cmul(cplxf a, cplxf b) {
+    return mkf(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline cplxf cmulc(cplxf a, cplxf b) {
+    return mkf(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline cplxf cscale(cplxf a, float s) { return mkf(a.x * s, a.y * s); }
+__host__ __device__ inline float cabs2(cplxf a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline cplxf cdiv(cplxf a, cplxf b) {
+    if (fabsf(b.x) >= fabsf(b.y)) {
+        float r = b.y / b.x, d = b.x + b.y * r;
+        return mkf((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+    } else {
+        float r = b.x / b.y, d = b.y + b.x * r;
+        return mkf((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+    }
+}
+__host__ __device__ inline cplxf crecip(cplxf b) { return cdiv(mkf(1.0f, 0.0f), b); }
+
+// Complex type of a real type, and conversions between the two precisions
+// (double -> float rounds to nearest even).
+template <class T> struct Cx;
+template <> struct Cx<double> { typedef cplx type; };
+template <> struct Cx<float> { typedef cplxf type; };
+
+template <class C> __host__ __device__ inline C cconv(cplx a);
+template <class C> __host__ __device__ inline C cconv(cplxf a);
+template <> __host__ __device__ inline cplx cconv<cplx>(cplx a) { return a; }
+template <> __host__ __device__ inline cplxf cconv<cplxf>(cplx a) {
+    return mkf((float)a.x, (float)a.y);
+}
+template <> __host__ __device__ inline cplx cconv<cplx>(cplxf a) {
+    return mk((double)a.x, (double)a.y);
+}
+template <> __host__ __device__ inline cplxf cconv<cplxf>(cplxf a) { return a; }
+template <class C> __host__ __device__ inline C czero() { return cconv<C>(mk(0.0, 0.0)); }
+
 // ---------------------------------------------------------------------------
 // Fine-grid operator A_sigma (matrix-free 5-point / 3-point stencil):
 //   row p:  sum_a (prod_{b!=a} w_b)/h_a^2 sum_{q a-nbr}(u_p - u_q)
 //         + j k_p sum_a e_a (prod_{b!=a} w_b)/h_a u_p - sigma k_p^2 prod_a w_a u_p
 // w = 1/2 and e = 1 on the end nodes of an axis; 1D has no z axis.
 // ---------------------------------------------------------------------------
-struct FineOp {
+template <class T>
+struct FineOpT {
+    typedef T real;
+    typedef typename Cx<T>::type C;
     int nz, nx;          // nz = 1 in 1D
     int ndim;
-    double ihx2, ihz2;   // 1/hx^2, 1/hz^2
-    double ihx, ihz;     // 1/hx, 1/hz
-    double omega;        // rad/s
-    double omega2;       // omega^2
-    double sr, si;       // sigma = sr + j si
-    const double* m2;    // slowness squared, nz*nx
-    const cplx* wdinv;   // omega_J / diag per node (V-cycle smoother), or nullptr
+    T ihx2, ihz2;        // 1/hx^2, 1/hz^2
+    T ihx, ihz;          // 1/hx, 1/hz
+    T omega;             // rad/s
+    T omega2;            // omega^2
+    T sr, si;            // sigma = sr + j si
+    const T* m2;         // slowness squared, nz*nx
+    const C* wdinv;      // omega_J / diag per node (V-cycle smoother), or nullptr
 };
+typedef FineOpT<double> FineOp;
 
-struct Coef5 {
-    double cx;   // x-neighbour coupling (entry is -cx)
-    double cz;   // z-neighbour coupling (entry is -cz)
-    cplx diag;
+template <class T>
+struct Coef5T {
+    T cx;                        // x-neighbour coupling (entry is -cx)
+    T cz;                        // z-neighbour coupling (entry is -cz)
+    typename Cx<T>::type diag;
 };
+typedef Coef5T<double> Coef5;
 
-// Row p = (iz, ix) of the fine operator.
-__device__ __forceinline__ Coef5 fine_coefs(const FineOp& op, int iz, int ix, double m2p) {
-    Coef5 c;
+// Row p = (iz, ix) of the fine operator, in the operator's precision.
+template <class T>
+__device__ __forceinline__ Coef5T<T> fine_coefs(const FineOpT<T>& op, int iz, int ix, T m2p) {
+    Coef5T<T> c;
+    const T half = (T)0.5, one = (T)1;
     const bool bx = (ix == 0) || (ix == op.nx - 1);
-    const double wx = bx ? 0.5 : 1.0;
+    const T wx = bx ? half : one;
     bool bz = false;
-    double wz = 1.0;
+    T wz = one;
     if (op.ndim == 2) {
         bz = (iz == 0) || (iz == op.nz - 1);
-        wz = bz ? 0.5 : 1.0;
+        wz = bz ? half : one;
     }
     c.cx = wz * op.ihx2;
     c.cz = wx * op.ihz2;
-    double re = (double)((ix > 0) + (ix < op.nx - 1)) * c.cx;
-    if (op.ndim == 2) re += (double)((iz > 0) + (iz < op.nz - 1)) * c.cz;
-    const double k2 = op.omega2 * m2p;
-    const double ww = wx * wz;
-    double im = 0.0;
+    T re = (T)((ix > 0) + (ix < op.nx - 1)) * c.cx;
+    if (op.ndim == 2) re += (T)((iz > 0) + (iz < op.nz - 1)) * c.cz;
+    const T k2 = op.omega2 * m2p;
+    const T ww = wx * wz;
+    T im = 0;
     if (bx || bz) {
-        const double k = op.omega * sqrt(m2p);
-        im = k * ((bx ? wz * op.ihx : 0.0) + (bz ? wx * op.ihz : 0.0));
+        const T k = op.omega * sqrt(m2p);
+        im = k * ((bx ? wz * op.ihx : (T)0) + (bz ? wx * op.ihz : (T)0));
     }
     re -= op.sr * k2 * ww;
     im -= op.si * k2 * ww;
-    c.diag = mk(re, im);
+    c.diag.x = re;
+    c.diag.y = im;
     return c;
 }
 
 // Galerkin 9-point operator on a coarse level: coefficient t = (dz+1)*3+(dx+1)
 // of node p is C[t*N + p]; coefficients of neighbours outside the grid are 0.
-struct CoarseOp {
+template <class T>
+struct CoarseOpT {
+    typedef T real;
+    typedef typename Cx<T>::type Cv;
     int nz, nx;
-    const cplx* C;
-    const cplx* wdinv;   // omega_J / diag per node (V-cycle smoother)
+    const Cv* C;
+    const Cv* wdinv;     // omega_J / diag per node (V-cycle smoother)
 };
+typedef CoarseOpT<double> CoarseOp;
 
 // Largest restart length (columns of the least-squares problem)
 constexpr int kMaxColumns = 1024;
@@ -206,6 +262,8 @@ struct HostRecord {
 // w = H z and partial[i*nb + blk] = block sums of conj(V_i) w (nb = apply_blocks)
 hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx* V, int k,
                             cplx* partial, const int* active, hipStream_t s);
+hipError_t launch_apply_dot(const FineOp& op, const cplxf* z, cplx* w, const cplx* V, int k,
+                            cplx* partial, const int* active, hipStream_t s);
 int apply_blocks(const FineOp& op);
 int node_blocks(int64_t n);
 hipError_t launch_dot_blocks(const cplx* V, int64_t n, int k, const cplx* w, cplx* partial,
@@ -228,6 +286,8 @@ hipError_t launch_givens_step(const GivensArgs& a, hipStream_t s);
 // y = R^{-1} g, x += Z y for the st->k columns of the cycle, then st->k = 0
 hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
                                const cplx* Z, int64_t n, cplx* x, hipStream_t s);
+hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
+                               const cplxf* Z, int64_t n, cplx* x, hipStream_t s);
 hipError_t launch_normalize_pred(const cplx* w, const SolveState* st, cplx* v, int64_t n,
                                  hipStream_t s);
 hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
@@ -235,6 +295,10 @@ hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m,
 
 // ---- V-cycle kernels (vcycle_tiled.hip, coarsest.hip) ------------------------
 hipError_t launch_vc_gemv(int n, const cplx* A, const cplx* x, cplx* y, const int* active,
+                          hipStream_t s);
+hipError_t launch_vc_gemv(int n, const cplxf* A, const cplxf* x, cplxf* y, const int* active,
+                          hipStream_t s);
+hipError_t launch_vc_gemv(int n, const cplxf* A, const cplx* x, cplxf* y, const int* active,
                           hipStream_t s);
 // temporally blocked legs (vcycle_tiled.hip): down = two pre-sweeps from zero,
 // residual and restriction; up = prolongation and two post-sweeps
@@ -249,6 +313,21 @@ hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, const double* 
                                int nzc, int nxc, cplx* bc, const int* active,
                                const GivensArgs* giv, hipStream_t s);
 int vc_fine_down_givens_capacity(const FineOp& op);
+// single-precision cycle: the Krylov vector (src, bout) stays complex128
+hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, const double* scale,
+                               const cplx* npart, int nbn, cplx* bout, cplxf* x2, int hz, int hx,
+                               int nzc, int nxc, cplxf* bc, const int* active,
+                               const GivensArgs* giv, hipStream_t s);
+int vc_fine_down_givens_capacity(const FineOpT<float>& op);
+hipError_t launch_vc_coarse_down(const CoarseOpT<float>& op, const cplxf* b, cplxf* x2, int hz,
+                                 int hx, int nzc, int nxc, cplxf* bc, const int* active,
+                                 hipStream_t s);
+hipError_t launch_vc_fine_up(const FineOpT<float>& op, int hz, int hx, const cplx* b,
+                             const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
+                             const int* active, hipStream_t s);
+hipError_t launch_vc_coarse_up(const CoarseOpT<float>& op, int hz, int hx, const cplxf* b,
+                               const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
+                               const int* active, hipStream_t s);
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz,
                                  int hx, int nzc, int nxc, cplx* bc, const int* active,
                                  hipStream_t s);
@@ -264,5 +343,11 @@ hipError_t launch_wdinv_coarse(const CoarseOp& op, double wj, cplx* wdinv, hipSt
 // PCR with the normalisation of the Arnoldi vector folded in (vout = s*src, x = M^{-1} vout)
 hipError_t launch_pcr_norm(const FineOp& op, const cplx* src, const double* scale, cplx* vout,
                            cplx* x, const int* active, hipStream_t s);
+hipError_t launch_pcr_norm(const FineOpT<float>& op, const cplx* src, const double* scale,
+                           cplx* vout, cplxf* x, const int* active, hipStream_t s);
+
+// precision conversions (set-up of the single-precision preconditioner), RNE
+hipError_t launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s);
+hipError_t launch_to_c64(const cplx* a, cplxf* b, int64_t n, hipStream_t s);
 
 }  // namespace hh

@@ -107,8 +107,8 @@ __device__ __forceinline__ bool off(const int* active) { return active && *activ
 
 // w = H z (fine operator) and the first projections V^H w; for k <= KMAX the
 // basis values are loaded up front (all in flight together)
-template <int NDIM, int KMAX>
-__global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const cplx* __restrict__ z,
+template <int NDIM, int KMAX, class ZC>
+__global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const ZC* __restrict__ z,
                                                    cplx* __restrict__ w,
                                                    const cplx* __restrict__ V, int k,
                                                    cplx* __restrict__ partial,
@@ -139,12 +139,14 @@ __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const cplx* __rest
     cplx wp = mk(0.0, 0.0);
     if (valid) {
         const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
-        const cplx zW = z[ix > 0 ? p - 1 : p], zE = z[ix < op.nx - 1 ? p + 1 : p];
-        const cplx zp = z[p];
+        const cplx zW = cconv<cplx>(z[ix > 0 ? p - 1 : p]);
+        const cplx zE = cconv<cplx>(z[ix < op.nx - 1 ? p + 1 : p]);
+        const cplx zp = cconv<cplx>(z[p]);
         cplx sx = cadd(ix > 0 ? zW : mk(0.0, 0.0), ix < op.nx - 1 ? zE : mk(0.0, 0.0));
         wp = csub(cmul(c.diag, zp), cscale(sx, c.cx));
         if (NDIM == 2) {
-            const cplx zN = z[iz > 0 ? p - op.nx : p], zS = z[iz < op.nz - 1 ? p + op.nx : p];
+            const cplx zN = cconv<cplx>(z[iz > 0 ? p - op.nx : p]);
+            const cplx zS = cconv<cplx>(z[iz < op.nz - 1 ? p + op.nx : p]);
             cplx sz = cadd(iz > 0 ? zN : mk(0.0, 0.0), iz < op.nz - 1 ? zS : mk(0.0, 0.0));
             wp = csub(wp, cscale(sz, c.cz));
         }
@@ -399,8 +401,9 @@ __global__ void __launch_bounds__(256) k_backsub_pred(const SolveState* st,
     }
 }
 
+template <class ZC>
 __global__ void __launch_bounds__(256) k_update_pred(const SolveState* st,
-                                                     const cplx* __restrict__ Z, int64_t n,
+                                                     const ZC* __restrict__ Z, int64_t n,
                                                      const cplx* __restrict__ y,
                                                      cplx* __restrict__ x) {
     const int k = st->k;
@@ -411,7 +414,8 @@ __global__ void __launch_bounds__(256) k_update_pred(const SolveState* st,
     for (int c0 = 0; c0 < k; c0 += KC) {
         cplx v[KC];
 #pragma unroll
-        for (int c = 0; c < KC; ++c) v[c] = (c0 + c < k) ? Z[(int64_t)(c0 + c) * n + p] : mk(0.0, 0.0);
+        for (int c = 0; c < KC; ++c)
+            v[c] = (c0 + c < k) ? cconv<cplx>(Z[(int64_t)(c0 + c) * n + p]) : mk(0.0, 0.0);
 #pragma unroll
         for (int c = 0; c < KC; ++c)
             if (c0 + c < k) acc = cadd(acc, cmul(v[c], y[c0 + c]));
@@ -487,22 +491,23 @@ hipError_t launch_check_slowness(const double* m, int64_t n, double* m2, int* fl
     return hipGetLastError();
 }
 
-template <int NDIM>
-static void apply_dot_dispatch(dim3 g, dim3 b, const FineOp& op, const cplx* z, cplx* w,
+template <int NDIM, class ZC>
+static void apply_dot_dispatch(dim3 g, dim3 b, const FineOp& op, const ZC* z, cplx* w,
                                const cplx* V, int k, cplx* partial, const int* active,
                                hipStream_t s) {
     if (k <= 8)
-        HH_LAUNCH((k_apply_dot<NDIM, 8>), g, b, 0, s, op, z, w, V, k, partial, active);
+        HH_LAUNCH((k_apply_dot<NDIM, 8, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
     else if (k <= 16)
-        HH_LAUNCH((k_apply_dot<NDIM, 16>), g, b, 0, s, op, z, w, V, k, partial, active);
+        HH_LAUNCH((k_apply_dot<NDIM, 16, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
     else if (k <= 32)
-        HH_LAUNCH((k_apply_dot<NDIM, 32>), g, b, 0, s, op, z, w, V, k, partial, active);
+        HH_LAUNCH((k_apply_dot<NDIM, 32, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
     else
-        HH_LAUNCH((k_apply_dot<NDIM, 0>), g, b, 0, s, op, z, w, V, k, partial, active);
+        HH_LAUNCH((k_apply_dot<NDIM, 0, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
 }
 
-hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx* V, int k,
-                            cplx* partial, const int* active, hipStream_t s) {
+template <class ZC>
+hipError_t apply_dot(const FineOp& op, const ZC* z, cplx* w, const cplx* V, int k, cplx* partial,
+                     const int* active, hipStream_t s) {
     if (op.ndim == 2)
         apply_dot_dispatch<2>(dim3((op.nx + 63) / 64, (op.nz + 3) / 4), dim3(64, 4), op, z, w, V,
                               k, partial, active, s);
@@ -511,6 +516,16 @@ hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx
                               active, s);
     return hipGetLastError();
 }
+
+hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx* V, int k,
+                            cplx* partial, const int* active, hipStream_t s) {
+    return apply_dot(op, z, w, V, k, partial, active, s);
+}
+hipError_t launch_apply_dot(const FineOp& op, const cplxf* z, cplx* w, const cplx* V, int k,
+                            cplx* partial, const int* active, hipStream_t s) {
+    return apply_dot(op, z, w, V, k, partial, active, s);
+}
+
 int apply_blocks(const FineOp& op) {
     return op.ndim == 2 ? ((op.nx + 63) / 64) * ((op.nz + 3) / 4) : (op.nx + 255) / 256;
 }
@@ -563,11 +578,42 @@ hipError_t launch_givens_step(const GivensArgs& a, hipStream_t s) {
     HH_LAUNCH(k_givens_step, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
+template <class ZC>
+hipError_t cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y, const ZC* Z,
+                        int64_t n, cplx* x, hipStream_t s) {
+    HH_LAUNCH(k_backsub_pred, dim3(1), dim3(256), 0, s, st, R, g, y);
+    HH_LAUNCH(k_update_pred<ZC>, dim3(node_blocks(n)), dim3(256), 0, s, st, Z, n, y, x);
+    HH_LAUNCH(k_cycle_end, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
 hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
                                const cplx* Z, int64_t n, cplx* x, hipStream_t s) {
-    HH_LAUNCH(k_backsub_pred, dim3(1), dim3(256), 0, s, st, R, g, y);
-    HH_LAUNCH(k_update_pred, dim3(node_blocks(n)), dim3(256), 0, s, st, Z, n, y, x);
-    HH_LAUNCH(k_cycle_end, dim3(1), dim3(64), 0, s, st);
+    return cycle_finish(st, R, g, y, Z, n, x, s);
+}
+hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
+                               const cplxf* Z, int64_t n, cplx* x, hipStream_t s) {
+    return cycle_finish(st, R, g, y, Z, n, x, s);
+}
+
+namespace {
+__global__ void __launch_bounds__(256) k_to_f32(const double* __restrict__ a, float* __restrict__ b,
+                                                int64_t n) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < n) b[p] = (float)a[p];
+}
+__global__ void __launch_bounds__(256) k_to_c64(const cplx* __restrict__ a, cplxf* __restrict__ b,
+                                                int64_t n) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < n) b[p] = cconv<cplxf>(a[p]);
+}
+}  // namespace
+
+hipError_t launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s) {
+    HH_LAUNCH(k_to_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
+    return hipGetLastError();
+}
+hipError_t launch_to_c64(const cplx* a, cplxf* b, int64_t n, hipStream_t s) {
+    HH_LAUNCH(k_to_c64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
     return hipGetLastError();
 }
 hipError_t launch_normalize_pred(const cplx* w, const SolveState* st, cplx* v, int64_t n,

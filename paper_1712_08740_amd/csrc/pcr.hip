@@ -20,42 +20,49 @@ constexpr int PCR_THREADS = 1024;
 constexpr int PCR_MAXN = 1024;
 
 // d = s * src (s = *scale, or 1); vout = d when vout != nullptr (the normalised
-// Arnoldi vector); x = M^{-1} d. Returns at once when *active == 0.
-__global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOp op, const cplx* __restrict__ src,
+// Arnoldi vector, complex128); x = M^{-1} d in the operator's precision T.
+// Returns at once when *active == 0.
+template <class T>
+__global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOpT<T> op, const cplx* __restrict__ src,
                                                      const double* __restrict__ scale,
                                                      cplx* __restrict__ vout,
-                                                     cplx* __restrict__ x_out,
+                                                     typename Cx<T>::type* __restrict__ x_out,
                                                      const int* __restrict__ active) {
+    typedef typename Cx<T>::type C;
     if (active && *active == 0) return;
-    __shared__ cplx sa[PCR_MAXN], sb[PCR_MAXN], sc[PCR_MAXN], sd[PCR_MAXN];
+    __shared__ C sa[PCR_MAXN], sb[PCR_MAXN], sc[PCR_MAXN], sd[PCR_MAXN];
     const int n = op.nx;
     const int i = threadIdx.x;
     const double sv = scale ? scale[0] : 1.0;
+    const C zero = czero<C>();
     if (i < n) {
-        const Coef5 c = fine_coefs(op, 0, i, op.m2[i]);
-        sa[i] = mk(i > 0 ? -c.cx : 0.0, 0.0);
-        sc[i] = mk(i < n - 1 ? -c.cx : 0.0, 0.0);
+        const Coef5T<T> c = fine_coefs(op, 0, i, op.m2[i]);
+        C lo = zero, up = zero;
+        lo.x = i > 0 ? -c.cx : (T)0;
+        up.x = i < n - 1 ? -c.cx : (T)0;
+        sa[i] = lo;
+        sc[i] = up;
         sb[i] = c.diag;
         const cplx d = cscale(src[i], sv);
-        sd[i] = d;
+        sd[i] = cconv<C>(d);
         if (vout) vout[i] = d;
     }
     __syncthreads();
     for (int s = 1; s < n; s <<= 1) {
-        cplx na = mk(0.0, 0.0), nb = mk(0.0, 0.0), nc = mk(0.0, 0.0), nd = mk(0.0, 0.0);
+        C na = zero, nb = zero, nc = zero, nd = zero;
         if (i < n) {
-            const cplx ai = sa[i], ci = sc[i];
+            const C ai = sa[i], ci = sc[i];
             nb = sb[i];
             nd = sd[i];
             if (i - s >= 0) {
-                const cplx k1 = cdiv(ai, sb[i - s]);
-                na = csub(mk(0.0, 0.0), cmul(k1, sa[i - s]));
+                const C k1 = cdiv(ai, sb[i - s]);
+                na = csub(zero, cmul(k1, sa[i - s]));
                 nb = csub(nb, cmul(k1, sc[i - s]));
                 nd = csub(nd, cmul(k1, sd[i - s]));
             }
             if (i + s < n) {
-                const cplx k2 = cdiv(ci, sb[i + s]);
-                nc = csub(mk(0.0, 0.0), cmul(k2, sc[i + s]));
+                const C k2 = cdiv(ci, sb[i + s]);
+                nc = csub(zero, cmul(k2, sc[i + s]));
                 nb = csub(nb, cmul(k2, sa[i + s]));
                 nd = csub(nd, cmul(k2, sd[i + s]));
             }
@@ -72,6 +79,14 @@ __global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOp op, const cplx* __re
     if (i < n) x_out[i] = cdiv(sd[i], sb[i]);
 }
 
+template <class T>
+hipError_t pcr(const FineOpT<T>& op, const cplx* src, const double* scale, cplx* vout,
+               typename Cx<T>::type* x, const int* active, hipStream_t s) {
+    if (op.ndim != 1 || op.nx > PCR_MAXN) return hipErrorInvalidValue;
+    HH_LAUNCH((k_pcr<T>), dim3(1), dim3(PCR_THREADS), 0, s, op, src, scale, vout, x, active);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_pcr_solve(const FineOp& op, const cplx* d, cplx* x, hipStream_t s) {
@@ -80,9 +95,11 @@ hipError_t launch_pcr_solve(const FineOp& op, const cplx* d, cplx* x, hipStream_
 
 hipError_t launch_pcr_norm(const FineOp& op, const cplx* src, const double* scale, cplx* vout,
                            cplx* x, const int* active, hipStream_t s) {
-    if (op.ndim != 1 || op.nx > PCR_MAXN) return hipErrorInvalidValue;
-    HH_LAUNCH(k_pcr, dim3(1), dim3(PCR_THREADS), 0, s, op, src, scale, vout, x, active);
-    return hipGetLastError();
+    return pcr(op, src, scale, vout, x, active, s);
+}
+hipError_t launch_pcr_norm(const FineOpT<float>& op, const cplx* src, const double* scale,
+                           cplx* vout, cplxf* x, const int* active, hipStream_t s) {
+    return pcr(op, src, scale, vout, x, active, s);
 }
 
 }  // namespace hh

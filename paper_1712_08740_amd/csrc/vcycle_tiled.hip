@@ -30,53 +30,59 @@ __device__ __forceinline__ bool inactive(const int* active) {
 }
 
 // Row of the 5-point fine operator: a_p = diag, couplings -cx (x) and -cz (z).
+template <class T>
 struct Row5 {
-    cplx diag;
-    double cx, cz;
-    __device__ __forceinline__ cplx d() const { return diag; }
+    typename Cx<T>::type diag;
+    T cx, cz;
 };
 
+template <class T>
 struct Fine5 {
-    FineOp op;
+    typedef T real;
+    typedef typename Cx<T>::type C;
+    typedef Row5<T> Row;
+    FineOpT<T> op;
     __host__ __device__ int nz() const { return op.nz; }
     __host__ __device__ int nx() const { return op.nx; }
-    typedef Row5 Row;
     __device__ __forceinline__ Row row(int iz, int ix) const {
-        const Coef5 c = fine_coefs(op, iz, ix, op.m2[(int64_t)iz * op.nx + ix]);
+        const Coef5T<T> c = fine_coefs(op, iz, ix, op.m2[(int64_t)iz * op.nx + ix]);
         Row r;
         r.diag = c.diag;
         r.cx = c.cx;
         r.cz = c.cz;
         return r;
     }
-    __device__ __forceinline__ cplx wd(int iz, int ix) const {
+    __device__ __forceinline__ C wd(int iz, int ix) const {
         return op.wdinv[(int64_t)iz * op.nx + ix];
     }
     __device__ __forceinline__ static Row zero_row() {
         Row r;
-        r.diag = mk(1.0, 0.0);
-        r.cx = r.cz = 0.0;
+        r.diag = cconv<C>(mk(1.0, 0.0));
+        r.cx = r.cz = 0;
         return r;
     }
     // (A x)_q from an LDS field s with row stride ld at local index i
-    __device__ __forceinline__ cplx apply(const Row& r, const cplx* s, int i, int ld) const {
-        const cplx sx = cadd(s[i - 1], s[i + 1]);
-        const cplx sz = cadd(s[i - ld], s[i + ld]);
+    __device__ __forceinline__ C apply(const Row& r, const C* s, int i, int ld) const {
+        const C sx = cadd(s[i - 1], s[i + 1]);
+        const C sz = cadd(s[i - ld], s[i + ld]);
         return csub(csub(cmul(r.diag, s[i]), cscale(sx, r.cx)), cscale(sz, r.cz));
     }
 };
 
 // Row of a 9-point Galerkin operator: coefficient t = (dz+1)*3 + (dx+1).
+template <class T>
 struct Row9 {
-    cplx a[9];
-    __device__ __forceinline__ cplx d() const { return a[4]; }
+    typename Cx<T>::type a[9];
 };
 
+template <class T>
 struct Coarse9 {
-    CoarseOp op;
+    typedef T real;
+    typedef typename Cx<T>::type C;
+    typedef Row9<T> Row;
+    CoarseOpT<T> op;
     __host__ __device__ int nz() const { return op.nz; }
     __host__ __device__ int nx() const { return op.nx; }
-    typedef Row9 Row;
     __device__ __forceinline__ Row row(int iz, int ix) const {
         const int64_t N = (int64_t)op.nz * op.nx;
         const int64_t p = (int64_t)iz * op.nx + ix;
@@ -85,18 +91,18 @@ struct Coarse9 {
         for (int t = 0; t < 9; ++t) r.a[t] = op.C[t * N + p];
         return r;
     }
-    __device__ __forceinline__ cplx wd(int iz, int ix) const {
+    __device__ __forceinline__ C wd(int iz, int ix) const {
         return op.wdinv[(int64_t)iz * op.nx + ix];
     }
     __device__ __forceinline__ static Row zero_row() {
         Row r;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) r.a[t] = mk(0.0, 0.0);
-        r.a[4] = mk(1.0, 0.0);
+        for (int t = 0; t < 9; ++t) r.a[t] = czero<C>();
+        r.a[4] = cconv<C>(mk(1.0, 0.0));
         return r;
     }
-    __device__ __forceinline__ cplx apply(const Row& r, const cplx* s, int i, int ld) const {
-        cplx acc = mk(0.0, 0.0);
+    __device__ __forceinline__ C apply(const Row& r, const C* s, int i, int ld) const {
+        C acc = czero<C>();
 #pragma unroll
         for (int t = 0; t < 9; ++t) acc = cadd(acc, cmul(r.a[t], s[i + (t / 3 - 1) * ld + (t % 3 - 1)]));
         return acc;
@@ -120,27 +126,37 @@ __device__ __forceinline__ bool in_grid(int z, int x, int nz, int nx) {
 // launch has one workgroup more, which performs the Givens step of the
 // previous Arnoldi column.
 // ---------------------------------------------------------------------------
-template <int W1>
-constexpr int givens_capacity() { return W1 - 2; }
+// Columns of a Givens step the LDS of a down-leg block can stage: the fields
+// sb, sw and s1 (W1 values of type C each) hold the column (cap + 2 complex128),
+// the cosines and the sines.
+template <class C, int W1>
+constexpr int givens_capacity() { return (int)(W1 * sizeof(C) / sizeof(cplx)) - 2; }
 
-template <class OP, int TCX, int TCZ>
-__global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
+// SC is the type of src and bout: complex128 on the fine level (the Krylov
+// vectors) whatever the precision of the cycle, the level's own type below.
+template <class OP, class SC, int TCX, int TCZ>
+__global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
                                              const double* __restrict__ scale,
                                              const cplx* __restrict__ npart, int nbn,
-                                             cplx* __restrict__ bout, cplx* __restrict__ x2out,
+                                             SC* __restrict__ bout,
+                                             typename OP::C* __restrict__ x2out,
                                              int hz, int hx, int nzc, int nxc,
-                                             cplx* __restrict__ bc, double rscale,
+                                             typename OP::C* __restrict__ bc, double rscale,
                                              const int* __restrict__ active, int ntx, int ntiles,
                                              GivensArgs giv) {
+    typedef typename OP::C C;
+    typedef typename OP::real T;
     constexpr int W1X = 2 * TCX + 5, W1Z = 2 * TCZ + 5;   // largest x1 region
-    __shared__ cplx sb[W1X * W1Z];
-    __shared__ cplx sw[W1X * W1Z];                          // omega_J / diag
-    __shared__ cplx s1[W1X * W1Z];
-    __shared__ cplx s2[W1X * W1Z];
+    // 16-byte aligned: the hosted Givens step stages complex128 values here
+    __shared__ __align__(16) C sb[W1X * W1Z];
+    __shared__ __align__(16) C sw[W1X * W1Z];               // omega_J / diag
+    __shared__ __align__(16) C s1[W1X * W1Z];
+    __shared__ C s2[W1X * W1Z];
     __shared__ typename OP::Row srow[W1X * W1Z];           // rows of the x1 region
     __shared__ double s_scale;
     if ((int)blockIdx.x == ntiles) {                       // the hosted Givens step
-        givens_body(giv, sb, reinterpret_cast<double*>(sw), s1);
+        givens_body(giv, reinterpret_cast<cplx*>(sb), reinterpret_cast<double*>(sw),
+                    reinterpret_cast<cplx*>(s1));
         return;
     }
     if (inactive(active)) return;
@@ -161,11 +177,11 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
         const int i = threadIdx.x + k * NT;
         if (i < n1) {
             const int qz = oz + i / wx, qx = ox + i % wx;
-            cplx bq = mk(0.0, 0.0), x1 = mk(0.0, 0.0), wq = mk(0.0, 0.0);
+            C bq = czero<C>(), x1 = czero<C>(), wq = czero<C>();
             typename OP::Row r = OP::zero_row();
             if (in_grid(qz, qx, nz, nx)) {
                 const int64_t q = (int64_t)qz * nx + qx;
-                bq = src[q];
+                bq = cconv<C>(src[q]);
                 r = A.row(qz, qx);
                 wq = A.wd(qz, qx);
                 x1 = cmul(bq, wq);
@@ -186,8 +202,12 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
         const int tox = ohx - olx + 1, ton = tox * (ohz - olz + 1);
         for (int t = threadIdx.x; t < ton; t += NT) {
             const int qz = olz + t / tox, qx = olx + t % tox;
-            if (qz < nz && qx < nx)
-                bout[(int64_t)qz * nx + qx] = cscale(sb[(qz - oz) * wx + (qx - ox)], s);
+            if (qz >= nz || qx >= nx) continue;
+            const int64_t q = (int64_t)qz * nx + qx;
+            if constexpr (sizeof(SC) == sizeof(C))
+                bout[q] = cscale(sb[(qz - oz) * wx + (qx - ox)], s);
+            else
+                bout[q] = cscale(src[q], s);   // full precision of the Krylov vector
         }
     }
     // phase 2: x2 on the x1 region shrunk by one node (stored at the same local index)
@@ -199,13 +219,13 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
             const int lz = 1 + j / w2x, lx = 1 + j % w2x;
             const int i = lz * wx + lx;
             const int qz = oz + lz, qx = ox + lx;
-            cplx x2 = mk(0.0, 0.0);
+            C x2 = czero<C>();
             if (in_grid(qz, qx, nz, nx)) {
                 const typename OP::Row& r = srow[i];
-                const cplx ax = A.apply(r, s1, i, wx);
+                const C ax = A.apply(r, s1, i, wx);
                 x2 = cadd(s1[i], cmul(csub(sb[i], ax), sw[i]));
                 if (qz >= olz && qz <= ohz && qx >= olx && qx <= ohx)
-                    x2out[(int64_t)qz * nx + qx] = cscale(x2, s);
+                    x2out[(int64_t)qz * nx + qx] = cscale(x2, (T)s);
             }
             s2[i] = x2;
         }
@@ -220,7 +240,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
             const int lz = 2 + j / w3x, lx = 2 + j % w3x;
             const int i = lz * wx + lx;
             const int qz = oz + lz, qx = ox + lx;
-            cplx r = mk(0.0, 0.0);
+            C r = czero<C>();
             if (in_grid(qz, qx, nz, nx)) r = csub(sb[i], A.apply(srow[i], s2, i, wx));
             s1[i] = r;
         }
@@ -231,17 +251,17 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
         const int Iz = cz0 + t / TCX, Ix = cx0 + t % TCX;
         if (Iz >= nzc || Ix >= nxc) continue;
         const int lz = (hz ? 2 * Iz : Iz) - oz, lx = (hx ? 2 * Ix : Ix) - ox;
-        cplx acc = mk(0.0, 0.0);
+        C acc = czero<C>();
 #pragma unroll
         for (int dz = -1; dz <= 1; ++dz) {
 #pragma unroll
             for (int dx = -1; dx <= 1; ++dx) {
                 if ((dz != 0 && !hz) || (dx != 0 && !hx)) continue;
-                const double w = (dz == 0 ? 1.0 : 0.5) * (dx == 0 ? 1.0 : 0.5);
+                const T w = (dz == 0 ? (T)1 : (T)0.5) * (dx == 0 ? (T)1 : (T)0.5);
                 acc = cadd(acc, cscale(s1[(lz + dz) * wx + (lx + dx)], w));
             }
         }
-        bc[(int64_t)Iz * nxc + Ix] = cscale(acc, rscale * s);
+        bc[(int64_t)Iz * nxc + Ix] = cscale(acc, (T)(rscale * s));
     }
 }
 
@@ -249,27 +269,30 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const cplx* __restrict__ src,
 // up leg. A block owns a TX x TZ tile of fine nodes: x' on the tile plus two
 // nodes, x3 on the tile plus one, x4 on the tile.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void interp2(int q, int halved, int& J0, int& J1, double& w0,
-                                        double& w1) {
-    if (!halved) { J0 = J1 = q; w0 = 1.0; w1 = 0.0; return; }
-    if ((q & 1) == 0) { J0 = J1 = q >> 1; w0 = 1.0; w1 = 0.0; return; }
-    J0 = (q - 1) >> 1; J1 = J0 + 1; w0 = w1 = 0.5;
+template <class T>
+__device__ __forceinline__ void interp2(int q, int halved, int& J0, int& J1, T& w0, T& w1) {
+    if (!halved) { J0 = J1 = q; w0 = 1; w1 = 0; return; }
+    if ((q & 1) == 0) { J0 = J1 = q >> 1; w0 = 1; w1 = 0; return; }
+    J0 = (q - 1) >> 1; J1 = J0 + 1; w0 = w1 = (T)0.5;
 }
 
-template <class OP, int TX, int TZ>
+// SB is the type of b: complex128 on the fine level (the Krylov vector).
+template <class OP, class SB, int TX, int TZ>
 __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
-                                           const cplx* __restrict__ b,
-                                           const cplx* __restrict__ x2,
-                                           const cplx* __restrict__ e, int nxc,
-                                           cplx* __restrict__ out,
+                                           const SB* __restrict__ b,
+                                           const typename OP::C* __restrict__ x2,
+                                           const typename OP::C* __restrict__ e, int nxc,
+                                           typename OP::C* __restrict__ out,
                                            const int* __restrict__ active, int ntx, int ntiles) {
+    typedef typename OP::C C;
+    typedef typename OP::real T;
     if (inactive(active)) return;
     constexpr int WX = TX + 4, WZ = TZ + 4;
     constexpr int W3X = TX + 2, W3Z = TZ + 2;
-    __shared__ cplx sp[WX * WZ];                      // x' (tile + 2)
-    __shared__ cplx s3[WX * WZ];                      // x3 (tile + 1)
-    __shared__ cplx sbb[W3X * W3Z];                   // b on the tile + 1
-    __shared__ cplx sw[W3X * W3Z];                    // omega_J / diag on the tile + 1
+    __shared__ C sp[WX * WZ];                         // x' (tile + 2)
+    __shared__ C s3[WX * WZ];                         // x3 (tile + 1)
+    __shared__ C sbb[W3X * W3Z];                      // b on the tile + 1
+    __shared__ C sw[W3X * W3Z];                       // omega_J / diag on the tile + 1
     __shared__ typename OP::Row srow[W3X * W3Z];      // rows on the tile + 1
     const int nz = A.nz(), nx = A.nx();
     const int tile = xcd_tile(blockIdx.x, ntiles);
@@ -283,16 +306,16 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
         const int i = threadIdx.x + k * NT;
         if (i < WX * WZ) {
             const int qz = oz + i / WX, qx = ox + i % WX;
-            cplx v = mk(0.0, 0.0);
+            C v = czero<C>();
             if (in_grid(qz, qx, nz, nx)) {
                 int z0, z1, x0, x1;
-                double wz0, wz1, wx0, wx1;
+                T wz0, wz1, wx0, wx1;
                 interp2(qz, hz, z0, z1, wz0, wz1);
                 interp2(qx, hx, x0, x1, wx0, wx1);
-                const cplx e00 = e[(int64_t)z0 * nxc + x0], e01 = e[(int64_t)z0 * nxc + x1];
-                const cplx e10 = e[(int64_t)z1 * nxc + x0], e11 = e[(int64_t)z1 * nxc + x1];
-                const cplx pe = cadd(cadd(cscale(e00, wz0 * wx0), cscale(e01, wz0 * wx1)),
-                                     cadd(cscale(e10, wz1 * wx0), cscale(e11, wz1 * wx1)));
+                const C e00 = e[(int64_t)z0 * nxc + x0], e01 = e[(int64_t)z0 * nxc + x1];
+                const C e10 = e[(int64_t)z1 * nxc + x0], e11 = e[(int64_t)z1 * nxc + x1];
+                const C pe = cadd(cadd(cscale(e00, wz0 * wx0), cscale(e01, wz0 * wx1)),
+                                  cadd(cscale(e10, wz1 * wx0), cscale(e11, wz1 * wx1)));
                 v = cadd(x2[(int64_t)qz * nx + qx], pe);
             }
             sp[i] = v;
@@ -304,10 +327,10 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
         if (j < W3X * W3Z) {
             const int qz = fz0 - 1 + j / W3X, qx = fx0 - 1 + j % W3X;
             typename OP::Row r = OP::zero_row();
-            cplx bq = mk(0.0, 0.0), wq = mk(0.0, 0.0);
+            C bq = czero<C>(), wq = czero<C>();
             if (in_grid(qz, qx, nz, nx)) {
                 r = A.row(qz, qx);
-                bq = b[(int64_t)qz * nx + qx];
+                bq = cconv<C>(b[(int64_t)qz * nx + qx]);
                 wq = A.wd(qz, qx);
             }
             srow[j] = r;
@@ -324,10 +347,10 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
             const int lz = 1 + j / W3X, lx = 1 + j % W3X;
             const int i = lz * WX + lx;
             const int qz = oz + lz, qx = ox + lx;
-            cplx v = mk(0.0, 0.0);
+            C v = czero<C>();
             if (in_grid(qz, qx, nz, nx)) {
                 const typename OP::Row& r = srow[j];
-                const cplx ax = A.apply(r, sp, i, WX);
+                const C ax = A.apply(r, sp, i, WX);
                 v = cadd(sp[i], cmul(csub(sbb[j], ax), sw[j]));
             }
             s3[i] = v;
@@ -346,7 +369,7 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
             const int qz = oz + lz, qx = ox + lx;
             if (in_grid(qz, qx, nz, nx)) {
                 const typename OP::Row& r = srow[j];
-                const cplx ax = A.apply(r, s3, i, WX);
+                const C ax = A.apply(r, s3, i, WX);
                 out[(int64_t)qz * nx + qx] = cadd(s3[i], cmul(csub(sbb[j], ax), sw[j]));
             }
         }
@@ -368,45 +391,69 @@ bool big_tiles(const OP& A) {
     return false;
 }
 
-template <class OP, int TCX, int TCZ>
-hipError_t down_launch(const OP& A, const cplx* src, const double* scale, const cplx* npart,
-                       int nbn, cplx* bout, cplx* x2, int hz, int hx, int nzc, int nxc, cplx* bc,
-                       const int* active, const GivensArgs& giv, hipStream_t s) {
+template <class OP, class SC, int TCX, int TCZ>
+hipError_t down_launch(const OP& A, const SC* src, const double* scale, const cplx* npart,
+                       int nbn, SC* bout, typename OP::C* x2, int hz, int hx, int nzc, int nxc,
+                       typename OP::C* bc, const int* active, const GivensArgs& giv,
+                       hipStream_t s) {
     const int ntx = (nxc + TCX - 1) / TCX, ntz = (nzc + TCZ - 1) / TCZ;
     const int ntiles = ntx * ntz;
     const dim3 g(ntiles + (giv.st ? 1 : 0));
-    HH_LAUNCH((k_down<OP, TCX, TCZ>), g, dim3(NT), 0, s, A, src, scale, npart, nbn, bout, x2, hz,
-              hx, nzc, nxc, bc, inv2dc(hz, hx), active, ntx, ntiles, giv);
+    HH_LAUNCH((k_down<OP, SC, TCX, TCZ>), g, dim3(NT), 0, s, A, src, scale, npart, nbn, bout, x2,
+              hz, hx, nzc, nxc, bc, inv2dc(hz, hx), active, ntx, ntiles, giv);
     return hipGetLastError();
 }
 
 // Large tiles (less halo work) for the big 5-point grid; small tiles (more
 // blocks in flight, and room in LDS for the 9-coefficient rows) elsewhere.
-template <class OP>
-hipError_t down_dispatch(const OP& A, const cplx* src, const double* scale, const cplx* npart,
-                         int nbn, cplx* bout, cplx* x2, int hz, int hx, int nzc, int nxc,
-                         cplx* bc, const int* active, const GivensArgs& giv, hipStream_t s) {
+template <class OP, class SC>
+hipError_t down_dispatch(const OP& A, const SC* src, const double* scale, const cplx* npart,
+                         int nbn, SC* bout, typename OP::C* x2, int hz, int hx, int nzc, int nxc,
+                         typename OP::C* bc, const int* active, const GivensArgs& giv,
+                         hipStream_t s) {
     if (big_tiles(A))
-        return down_launch<OP, 16, 4>(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
-                                      active, giv, s);
-    return down_launch<OP, 8, 4>(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
-                                 active, giv, s);
+        return down_launch<OP, SC, 16, 4>(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc,
+                                          bc, active, giv, s);
+    return down_launch<OP, SC, 8, 4>(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
+                                     active, giv, s);
 }
 
-template <class OP, int TX, int TZ>
-hipError_t up_launch(const OP& A, int hz, int hx, const cplx* b, const cplx* x2, const cplx* e,
-                     int nxc, cplx* out, const int* active, hipStream_t s) {
+template <class OP>
+int down_givens_capacity(const OP& A) {
+    typedef typename OP::C C;
+    return big_tiles(A) ? givens_capacity<C, (2 * 16 + 5) * (2 * 4 + 5)>()
+                        : givens_capacity<C, (2 * 8 + 5) * (2 * 4 + 5)>();
+}
+
+template <class OP, class SB, int TX, int TZ>
+hipError_t up_launch(const OP& A, int hz, int hx, const SB* b, const typename OP::C* x2,
+                     const typename OP::C* e, int nxc, typename OP::C* out, const int* active,
+                     hipStream_t s) {
     const int ntx = (A.nx() + TX - 1) / TX, ntz = (A.nz() + TZ - 1) / TZ;
-    HH_LAUNCH((k_up<OP, TX, TZ>), dim3(ntx * ntz), dim3(NT), 0, s, A, hz, hx, b, x2, e, nxc, out,
-              active, ntx, ntx * ntz);
+    HH_LAUNCH((k_up<OP, SB, TX, TZ>), dim3(ntx * ntz), dim3(NT), 0, s, A, hz, hx, b, x2, e, nxc,
+              out, active, ntx, ntx * ntz);
     return hipGetLastError();
 }
 
-template <class OP>
-hipError_t up_dispatch(const OP& A, int hz, int hx, const cplx* b, const cplx* x2,
-                       const cplx* e, int nxc, cplx* out, const int* active, hipStream_t s) {
-    if (big_tiles(A)) return up_launch<OP, 32, 8>(A, hz, hx, b, x2, e, nxc, out, active, s);
-    return up_launch<OP, 16, 4>(A, hz, hx, b, x2, e, nxc, out, active, s);
+template <class OP, class SB>
+hipError_t up_dispatch(const OP& A, int hz, int hx, const SB* b, const typename OP::C* x2,
+                       const typename OP::C* e, int nxc, typename OP::C* out, const int* active,
+                       hipStream_t s) {
+    if (big_tiles(A)) return up_launch<OP, SB, 32, 8>(A, hz, hx, b, x2, e, nxc, out, active, s);
+    return up_launch<OP, SB, 16, 4>(A, hz, hx, b, x2, e, nxc, out, active, s);
+}
+
+template <class T>
+Fine5<T> fine5(const FineOpT<T>& op) {
+    Fine5<T> A;
+    A.op = op;
+    return A;
+}
+template <class T>
+Coarse9<T> coarse9(const CoarseOpT<T>& op) {
+    Coarse9<T> A;
+    A.op = op;
+    return A;
 }
 
 }  // namespace
@@ -415,41 +462,55 @@ hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, const double* 
                                const cplx* npart, int nbn, cplx* bout, cplx* x2, int hz, int hx,
                                int nzc, int nxc, cplx* bc, const int* active,
                                const GivensArgs* giv, hipStream_t s) {
-    Fine5 A;
-    A.op = op;
     const GivensArgs none{};
-    return down_dispatch(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc, active,
-                         giv ? *giv : none, s);
+    return down_dispatch(fine5(op), src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
+                         active, giv ? *giv : none, s);
+}
+hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, const double* scale,
+                               const cplx* npart, int nbn, cplx* bout, cplxf* x2, int hz, int hx,
+                               int nzc, int nxc, cplxf* bc, const int* active,
+                               const GivensArgs* giv, hipStream_t s) {
+    const GivensArgs none{};
+    return down_dispatch(fine5(op), src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
+                         active, giv ? *giv : none, s);
 }
 
-int vc_fine_down_givens_capacity(const FineOp& op) {
-    Fine5 A;
-    A.op = op;
-    return big_tiles(A) ? givens_capacity<(2 * 16 + 5) * (2 * 4 + 5)>()
-                        : givens_capacity<(2 * 8 + 5) * (2 * 4 + 5)>();
+int vc_fine_down_givens_capacity(const FineOp& op) { return down_givens_capacity(fine5(op)); }
+int vc_fine_down_givens_capacity(const FineOpT<float>& op) {
+    return down_givens_capacity(fine5(op));
 }
 
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz, int hx,
                                  int nzc, int nxc, cplx* bc, const int* active, hipStream_t s) {
-    Coarse9 A;
-    A.op = op;
-    return down_dispatch(A, b, nullptr, nullptr, 0, nullptr, x2, hz, hx, nzc, nxc, bc, active,
-                         GivensArgs{}, s);
+    return down_dispatch(coarse9(op), b, nullptr, nullptr, 0, (cplx*)nullptr, x2, hz, hx, nzc,
+                         nxc, bc, active, GivensArgs{}, s);
+}
+hipError_t launch_vc_coarse_down(const CoarseOpT<float>& op, const cplxf* b, cplxf* x2, int hz,
+                                 int hx, int nzc, int nxc, cplxf* bc, const int* active,
+                                 hipStream_t s) {
+    return down_dispatch(coarse9(op), b, nullptr, nullptr, 0, (cplxf*)nullptr, x2, hz, hx, nzc,
+                         nxc, bc, active, GivensArgs{}, s);
 }
 
 hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b, const cplx* x2,
                              const cplx* e, int nxc, cplx* out, const int* active, hipStream_t s) {
-    Fine5 A;
-    A.op = op;
-    return up_dispatch(A, hz, hx, b, x2, e, nxc, out, active, s);
+    return up_dispatch(fine5(op), hz, hx, b, x2, e, nxc, out, active, s);
+}
+hipError_t launch_vc_fine_up(const FineOpT<float>& op, int hz, int hx, const cplx* b,
+                             const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
+                             const int* active, hipStream_t s) {
+    return up_dispatch(fine5(op), hz, hx, b, x2, e, nxc, out, active, s);
 }
 
 hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b, const cplx* x2,
                                const cplx* e, int nxc, cplx* out, const int* active,
                                hipStream_t s) {
-    Coarse9 A;
-    A.op = op;
-    return up_dispatch(A, hz, hx, b, x2, e, nxc, out, active, s);
+    return up_dispatch(coarse9(op), hz, hx, b, x2, e, nxc, out, active, s);
+}
+hipError_t launch_vc_coarse_up(const CoarseOpT<float>& op, int hz, int hx, const cplxf* b,
+                               const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
+                               const int* active, hipStream_t s) {
+    return up_dispatch(coarse9(op), hz, hx, b, x2, e, nxc, out, active, s);
 }
 
 namespace {

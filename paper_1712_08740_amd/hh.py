@@ -27,6 +27,7 @@ HH_EDEVICE = -3
 HH_ENUMERIC = -4
 HH_EUNSUPPORTED = -5
 HH_NO_PRECOND = 1
+HH_PRECOND_F32 = 2
 HH_MAX_COARSE = 4096
 HH_MAX_1D = 1024
 HH_KERNEL_NONE = 0
@@ -46,6 +47,7 @@ EXPORTED = [
     "hh_create_problem", "hh_set_shift", "hh_workspace_bytes", "hh_solve",
     "hh_destroy_problem", "hh_status_string", "hh_last_error", "hh_num_levels",
     "hh_level_info", "hh_apply_operator", "hh_apply_level_operator", "hh_apply_precond",
+    "hh_apply_precond_f32",
     "hh_orthogonalize_scratch_bytes", "hh_orthogonalize", "hh_kernel_timer_start",
     "hh_kernel_timer_read",
 ]
@@ -86,6 +88,7 @@ def _load():
         "hh_apply_operator": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
         "hh_apply_level_operator": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
         "hh_apply_precond": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+        "hh_apply_precond_f32": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
         "hh_orthogonalize_scratch_bytes": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int,
                                                           _c_size_p]),
         "hh_orthogonalize": (ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int, _vp, _vp,
@@ -255,19 +258,25 @@ class Problem:
                "hh_apply_level_operator")
         return y
 
-    def apply_precond(self, v: torch.Tensor, stream=None):
+    def apply_precond(self, v: torch.Tensor, stream=None, f32: bool = False):
+        """z = M^{-1} v (complex128), or with ``f32`` the complex64 preconditioner
+        (z complex64)."""
         _dev_tensor(v, torch.complex128, self.shape, "v")
-        z = torch.empty_like(v)
+        z = torch.empty(v.shape, dtype=torch.complex64 if f32 else torch.complex128,
+                        device=v.device)
         ws = self.workspace(1)
-        _check(_lib.hh_apply_precond(self._handle, _vp(v.data_ptr()), _vp(z.data_ptr()),
-                                     _vp(ws.data_ptr()), ws.numel(), _vp(_stream_ptr(stream))),
-               "hh_apply_precond")
+        fn = _lib.hh_apply_precond_f32 if f32 else _lib.hh_apply_precond
+        _check(fn(self._handle, _vp(v.data_ptr()), _vp(z.data_ptr()), _vp(ws.data_ptr()),
+                  ws.numel(), _vp(_stream_ptr(stream))),
+               "hh_apply_precond_f32" if f32 else "hh_apply_precond")
         return z
 
     def solve(self, f: torch.Tensor, tol: float = 1e-6, restart: int = 30,
               max_iters: int = 2000, no_precond: bool = False, u: Optional[torch.Tensor] = None,
               workspace: Optional[torch.Tensor] = None, stream=None,
-              hist_cap: Optional[int] = None) -> SolveResult:
+              hist_cap: Optional[int] = None, precond_f32: bool = False) -> SolveResult:
+        """Right-preconditioned FGMRES(restart) to ``tol`` (``hh_solve``).
+        ``precond_f32`` runs the preconditioner in complex64 (HH_PRECOND_F32)."""
         _dev_tensor(f, torch.complex128, self.shape, "f")
         if u is None:
             u = torch.empty_like(f)
@@ -282,7 +291,7 @@ class Problem:
         its = ctypes.c_int()
         rel = ctypes.c_double()
         hlen = ctypes.c_int()
-        flags = HH_NO_PRECOND if no_precond else 0
+        flags = (HH_NO_PRECOND if no_precond else 0) | (HH_PRECOND_F32 if precond_f32 else 0)
         st = _check(_lib.hh_solve(self._handle, _vp(f.data_ptr()), float(tol), int(restart),
                                   int(max_iters), flags, _vp(ws.data_ptr()),
                                   ws.numel() * ws.element_size(), _vp(u.data_ptr()),

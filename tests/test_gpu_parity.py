@@ -364,3 +364,91 @@ def test_kernel_timer_classes_cover_the_step(hh):
     P.solve(_t(w.source), tol=w.tol, restart=w.restart)
     assert P.kernel_timer_read()[0] == 0
     P.kernel_timer_start("none")
+
+
+# ---------------------------------------------------------------------------
+# single-precision preconditioner inside the FP64 flexible GMRES
+# ---------------------------------------------------------------------------
+# The complex64 cycle rounds its data (m^2, omega_J/diag, Galerkin planes,
+# coarsest inverse) and its arithmetic to 24-bit mantissas: its output differs
+# from the FP64 cycle by about eps32 = 6e-8 times the cycle's amplification of
+# data perturbations. Measured on the grids below: 7.5e-8 (3 x 3) to 5.9e-7
+# (129 x 129 at 30 Hz), i.e. amplification <= 10; the bound allows 80.
+F32_CYCLE_TOL = 5e-6
+
+
+@pytest.mark.parametrize("case", CASES_2D, ids=str)
+def test_vcycle_f32_matches_oracle(hh, case):
+    shape, h, freq = case
+    m = _model(shape, h)
+    omega = 2 * np.pi * freq
+    P = _problem(hh, m, omega, 0.01, h)
+    V = mg.VCycle(m, omega, 1.0, 0.5, h)
+    for seed in (1, 2):
+        v = wl.random_complex(shape, seed)
+        z = _np(P.apply_precond(_t(v), f32=True))
+        assert z.dtype == np.complex64
+        ref = V(v.ravel()).reshape(shape)
+        err = np.linalg.norm(z.astype(np.complex128) - ref) / np.linalg.norm(ref)
+        print(f"f32 cycle {shape} {freq} Hz seed {seed}: rel err {err:.2e}")
+        assert err <= F32_CYCLE_TOL
+
+
+@pytest.mark.parametrize("n", [1001, 37])
+def test_pcr_f32_matches_direct_solve(hh, n):
+    h, freq = 5.0, 10.0
+    m = _model((n,), h)
+    omega = 2 * np.pi * freq
+    P = _problem(hh, m, omega, 0.01, h)
+    v = wl.random_complex((n,), 5)
+    z = _np(P.apply_precond(_t(v), f32=True)).astype(np.complex128)
+    ref = direct.solve_matrix(op.shifted_laplace(m, omega, 1.0, 0.5, h), v)
+    assert np.linalg.norm(z - ref) <= F32_CYCLE_TOL * np.linalg.norm(ref)
+
+
+def test_solve_f32_precond_401x201(hh):
+    """Mixed precision at the 401 x 201 workload: the tolerance is met in full
+    precision (recomputed residual), with about the FP64 iteration count; at a
+    tolerance scaled as for the FP64 path the wavefield matches LU to 1e-6."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    r64 = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    r32 = P.solve(_t(w.source), tol=w.tol, restart=w.restart, precond_f32=True)
+    assert r32.status == 0 and r32.true_rel_res <= w.tol
+    assert abs(r32.iterations - r64.iterations) <= 2
+    H = op.helmholtz(w.slowness, w.omega, w.alpha, w.h)
+    b = op.weighted_rhs(w.source).ravel()
+    u = _np(r32.u).ravel()
+    assert np.linalg.norm(b - H @ u) <= w.tol * np.linalg.norm(b)
+    lu = direct.solve_direct(w.slowness, w.omega, w.alpha, w.h, w.source).ravel()
+    tight = P.solve(_t(w.source), tol=1e-9, restart=w.restart, precond_f32=True)
+    ut = _np(tight.u).ravel()
+    assert np.linalg.norm(ut - lu) <= 1e-6 * np.linalg.norm(lu)
+
+
+def test_solve_f32_precond_1201x401_15hz(hh):
+    """The mixed-precision configuration: 1201 x 401, 15 Hz, FGMRES(40), tol 1e-8.
+    The recomputed FP64 residual (oracle operator on the CPU) meets 1e-8."""
+    w = wl.grf_1201x401()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    r32 = P.solve(_t(w.source), tol=w.tol, restart=w.restart, precond_f32=True)
+    print(f"1201x401 15 Hz mixed: {r32.iterations} iterations, rel res {r32.true_rel_res:.3e}")
+    assert r32.status == 0 and r32.true_rel_res <= w.tol
+    H = op.helmholtz(w.slowness, w.omega, w.alpha, w.h)
+    b = op.weighted_rhs(w.source).ravel()
+    u = _np(r32.u).ravel()
+    rel = np.linalg.norm(b - H @ u) / np.linalg.norm(b)
+    assert rel <= w.tol * (1 + 1e-6)
+    r64 = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    print(f"1201x401 15 Hz FP64: {r64.iterations} iterations")
+    assert abs(r32.iterations - r64.iterations) <= max(2, r64.iterations // 20)
+    assert np.linalg.norm(u - _np(r64.u).ravel()) <= 1e-6 * np.linalg.norm(u)
+
+
+def test_f32_flag_validation(hh):
+    w = wl.layered_1d_well()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    with pytest.raises(hh.HHError):
+        P.solve(_t(w.source), tol=1e-6, restart=5, no_precond=True, precond_f32=True)
+    r = P.solve(_t(w.source), tol=w.tol, restart=w.restart, precond_f32=True)
+    assert r.status == 0 and r.true_rel_res <= w.tol
