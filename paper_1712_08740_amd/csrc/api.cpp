@@ -239,7 +239,7 @@ int kt_harvest(hh_problem_s* p, const std::vector<int>& executed) {
 struct Layout {
     size_t V, Z, b, w, partial, h1, h2, R, cs, sn, g, y, st, total;
     std::vector<size_t> t, bc, ec;   // per level
-    int nbA, nbN, nbmax;
+    int nbA, nbN, nbS, nbmax;   // partials of apply_dot, node kernels, the norm
 };
 
 // es: bytes per complex value of Z and the V-cycle vectors (16, or 8 when
@@ -274,6 +274,7 @@ Layout layout(const hh_problem_s* p, int m, size_t es = sizeof(cplx)) {
     }
     L.nbA = apply_blocks(op_H(p));
     L.nbN = node_blocks(p->N);
+    L.nbS = norm_blocks(p->N);
     L.nbmax = L.nbA > L.nbN ? L.nbA : L.nbN;
     L.partial = take((size_t)L.nbmax * (m + 1) * c);
     L.h1 = take((size_t)(m + 1) * c);
@@ -810,7 +811,7 @@ int hh_orthogonalize(const void* V_dev, int64_t n, int k, void* w_dev, void* scr
     HIPCHK(launch_axpy_dot(V, n, k, h1, w, partial, nullptr, s));
     HIPCHK(launch_reduce_pred(partial, nb, k, h2, nullptr, s));
     HIPCHK(launch_axpy_norm(V, n, k, h2, w, partial, nullptr, s));
-    HIPCHK(launch_reduce_pred(partial, nb, 1, nr, nullptr, s));
+    HIPCHK(launch_reduce_pred(partial, norm_blocks(n), 1, nr, nullptr, s));
     std::vector<cplx> a(k), b(k);
     cplx nrm;
     HIPCHK(hipMemcpyAsync(a.data(), h1, k * sizeof(cplx), hipMemcpyDeviceToHost, s));
@@ -897,7 +898,7 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
         const bool fold = !no_prec && p->ndim == 2 && p->levels.size() >= 2 &&
                           m <= (f32 ? vc_fine_down_givens_capacity(op_Mf(p))
                                     : vc_fine_down_givens_capacity(op_M(p)));
-        const GivensArgs giv{st, h1, h2, partial, L.nbN, R, cs, sn, g, drec, dhist};
+        const GivensArgs giv{st, h1, h2, partial, L.nbS, R, cs, sn, g, drec, dhist};
         bool givens_pending = false;
         bool closed = false;
         for (int j = 0; j < m; ++j) {
@@ -942,12 +943,12 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
             if (fold) {
                 givens_pending = true;
             } else {
-                TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbN, launch_givens_step(giv, s));
+                TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbS, launch_givens_step(giv, s));
             }
         }
         // a pending step after a break belongs to a cycle the device has closed
         if (givens_pending && !closed)
-            TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbN, launch_givens_step(giv, s));
+            TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbS, launch_givens_step(giv, s));
         // the cycle closes on a step (or the solve ended at its start)
         CHK(wait_for(p, s, [&](const RecView& r) { return r.done || r.stops >= cycle; }));
         const RecView r = read_rec(p->rec);

@@ -266,12 +266,15 @@ hipError_t launch_apply_dot(const FineOp& op, const cplxf* z, cplx* w, const cpl
                             cplx* partial, const int* active, hipStream_t s);
 int apply_blocks(const FineOp& op);
 int node_blocks(int64_t n);
+// blocks of the norm kernel (its partial sums are re-read by each consumer)
+constexpr int kNormBlocks = 512;
+int norm_blocks(int64_t n);
 hipError_t launch_dot_blocks(const cplx* V, int64_t n, int k, const cplx* w, cplx* partial,
                              hipStream_t s);
 // w -= V h; partial = block sums of conj(V_i) w (nb = node_blocks(n))
 hipError_t launch_axpy_dot(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
                            const int* active, hipStream_t s);
-// w -= V h; partial[blk].x = block sums of |w|^2
+// w -= V h; partial[blk].x = block sums of |w|^2 (nb = norm_blocks(n))
 hipError_t launch_axpy_norm(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
                             const int* active, hipStream_t s);
 hipError_t launch_reduce_pred(const cplx* partial, int nb, int k, cplx* out, const int* active,

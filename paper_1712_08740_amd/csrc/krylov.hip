@@ -242,7 +242,9 @@ __global__ void __launch_bounds__(256) k_axpy_dot(const cplx* __restrict__ V, in
     }
 }
 
-// w -= V h, then ||w||^2 per block
+// w -= V h, then ||w||^2 per block. At most kNormBlocks blocks (grid-stride
+// over the nodes): the partials are summed again by every consumer of the
+// norm, so their number is kept small.
 __global__ void __launch_bounds__(256) k_axpy_norm(const cplx* __restrict__ V, int64_t n, int k,
                                                    const cplx* __restrict__ h,
                                                    cplx* __restrict__ w,
@@ -250,14 +252,14 @@ __global__ void __launch_bounds__(256) k_axpy_norm(const cplx* __restrict__ V, i
                                                    const int* __restrict__ active) {
     if (off(active)) return;
     __shared__ cplx sh[4];
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    cplx acc = mk(0.0, 0.0);
-    if (p < n) {
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * 256) {
         const cplx wp = axpy_chunked(V, n, k, h, p, w[p]);
         w[p] = wp;
-        acc = mk(cabs2(wp), 0.0);
+        acc += cabs2(wp);
     }
-    const cplx s = block_sum(acc, sh);
+    const cplx s = block_sum(mk(acc, 0.0), sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
@@ -501,6 +503,8 @@ static void apply_dot_dispatch(dim3 g, dim3 b, const FineOp& op, const ZC* z, cp
         HH_LAUNCH((k_apply_dot<NDIM, 16, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
     else if (k <= 32)
         HH_LAUNCH((k_apply_dot<NDIM, 32, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
+    else if (k <= 48)
+        HH_LAUNCH((k_apply_dot<NDIM, 48, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
     else
         HH_LAUNCH((k_apply_dot<NDIM, 0, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
 }
@@ -530,6 +534,7 @@ int apply_blocks(const FineOp& op) {
     return op.ndim == 2 ? ((op.nx + 63) / 64) * ((op.nz + 3) / 4) : (op.nx + 255) / 256;
 }
 int node_blocks(int64_t n) { return (int)((n + 255) / 256); }
+int norm_blocks(int64_t n) { return node_blocks(n) < kNormBlocks ? node_blocks(n) : kNormBlocks; }
 hipError_t launch_dot_blocks(const cplx* V, int64_t n, int k, const cplx* w, cplx* partial,
                              hipStream_t s) {
     HH_LAUNCH(k_dot_blocks, dim3(node_blocks(n)), dim3(256), 0, s, V, n, k, w, partial);
@@ -544,13 +549,15 @@ hipError_t launch_axpy_dot(const cplx* V, int64_t n, int k, const cplx* h, cplx*
         HH_LAUNCH(k_axpy_dot<16>, g, b, 0, s, V, n, k, h, w, partial, active);
     else if (k <= 32)
         HH_LAUNCH(k_axpy_dot<32>, g, b, 0, s, V, n, k, h, w, partial, active);
+    else if (k <= 48)
+        HH_LAUNCH(k_axpy_dot<48>, g, b, 0, s, V, n, k, h, w, partial, active);
     else
         HH_LAUNCH(k_axpy_dot<0>, g, b, 0, s, V, n, k, h, w, partial, active);
     return hipGetLastError();
 }
 hipError_t launch_axpy_norm(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
                             const int* active, hipStream_t s) {
-    HH_LAUNCH(k_axpy_norm, dim3(node_blocks(n)), dim3(256), 0, s, V, n, k, h, w, partial,
+    HH_LAUNCH(k_axpy_norm, dim3(norm_blocks(n)), dim3(256), 0, s, V, n, k, h, w, partial,
                        active);
     return hipGetLastError();
 }
