@@ -52,6 +52,24 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(workload_name: str, kernel: str):
+    """HBM bytes per launch of a kernel class from the committed --pmc summaries
+    (profiles/hbm_traffic_*.md), or None when there is none or the kernel's
+    sources changed since the counters were taken."""
+    import glob
+    sys.path.insert(0, ROOT)
+    from profile_summary import source_digest
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
+        text = open(path).read()
+        if "```json" not in text:
+            continue
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        entry = json.loads(block).get(workload_name, {}).get(kernel)
+        if entry and entry["digest"] == source_digest(kernel):
+            return entry["bytes_per_launch"]
+    return None
+
+
 def workload(name):
     import workloads as wl
     return {"grf_401x201": wl.grf_401x201, "layered_1d_well": wl.layered_1d_well,
@@ -215,7 +233,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(w.name + ("_mixed" if mixed else ""), kernel),
             "launches": int(launches),
             "avg_launch_us": avg_us,
             "algorithmic_bytes_per_launch": kbytes / max(launches, 1),

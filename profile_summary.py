@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 databases for ``profiles/`` (text only).
+
+    python profile_summary.py kernels DB TITLE COMMAND
+        per-kernel calls / total / average duration (``--kernel-trace --stats``)
+
+    python profile_summary.py traffic FETCH_DB WRITE_DB WORKLOAD COMMAND_FETCH COMMAND_WRITE
+        FETCH_SIZE and WRITE_SIZE per dispatch (two ``--pmc`` runs of
+        ``bench.py --copy-probe-mib 256``), scaled by what the counters read for
+        the 256 MiB device copy in the same run, per kernel class of the solve's
+        kernel timer; ends with a JSON block that ``bench.py`` reads for the
+        roofline ``traffic`` field (with a digest of the kernel sources: a
+        changed source makes the figure stale, and bench reports null).
+
+Only reads the databases; runs nothing.
+"""
+from __future__ import annotations
+
+import collections
+import hashlib
+import json
+import os
+import sqlite3
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(ROOT, "paper_1712_08740_amd", "csrc")
+
+# kernel class of the solve's kernel timer -> (kernel-name prefix, source files)
+CLASSES = {
+    "vc_down": ("k_down<Fine5", ["vcycle_tiled.hip", "hh_internal.h", "givens.h"]),
+    "vc_up": ("k_up<Fine5", ["vcycle_tiled.hip", "hh_internal.h"]),
+    "vc_down_coarse": ("k_down<Coarse9", ["vcycle_tiled.hip", "hh_internal.h", "givens.h"]),
+    "vc_up_coarse": ("k_up<Coarse9", ["vcycle_tiled.hip", "hh_internal.h"]),
+    "gemv": ("k_gemv_pred", ["coarsest.hip", "hh_internal.h"]),
+    "apply_dot": ("k_apply_dot", ["krylov.hip", "hh_internal.h", "givens.h"]),
+    "axpy_dot": ("k_axpy_dot", ["krylov.hip", "hh_internal.h", "givens.h"]),
+    "axpy_norm": ("k_axpy_norm", ["krylov.hip", "hh_internal.h", "givens.h"]),
+    "reduce": ("k_reduce_pred", ["krylov.hip", "hh_internal.h", "givens.h"]),
+    "pcr": ("k_pcr", ["pcr.hip", "hh_internal.h"]),
+}
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+COPY_KIB = 256 * 1024
+
+
+def source_digest(kernel_class: str) -> str:
+    h = hashlib.sha256()
+    for f in CLASSES[kernel_class][1]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _short(name: str) -> str:
+    return name.replace("hh::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+
+
+def kernels(db: str, title: str, cmd: str) -> str:
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, total_calls, total_duration, average, percentage "
+                       "from top_kernels").fetchall()
+    out = [f"# {title}", "", "Command (on the MI355X, from the repository root):", "",
+           f"    {cmd}", "",
+           "Kernel durations from `rocprofv3 --kernel-trace --stats` (top_kernels); "
+           "times in microseconds. Set-up kernels (Galerkin products, Gauss-Jordan "
+           "inversion) run once per problem.", "",
+           "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
+    for n, c, t, a, p in rows:
+        out.append(f"| {_short(n)} | {c} | {t:.1f} | {a:.3f} | {p:.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def _counter(db: str, ctr: str):
+    con = sqlite3.connect(db)
+    d = collections.defaultdict(list)
+    for name, v in con.execute("select kernel_name, value from counters_collection "
+                               "where counter_name=?", (ctr,)):
+        d[_short(name)].append(v)
+    return d
+
+
+def traffic(fetch_db: str, write_db: str, workload: str, cmd_f: str, cmd_w: str) -> str:
+    f = _counter(fetch_db, "FETCH_SIZE")
+    w = _counter(write_db, "WRITE_SIZE")
+    # the probe is the largest device copy of the run
+    fc, wc = max(f[COPY_KERNEL]), max(w[COPY_KERNEL])
+    ff, fw = COPY_KIB / fc, COPY_KIB / wc
+    out = [f"# HBM traffic per launch, {workload}", "",
+           "Commands (on the MI355X, from /tmp with TMPDIR=/tmp):", "",
+           f"    {cmd_f}", f"    {cmd_w}", "",
+           f"Scale: the 256 MiB device copy reads {fc:.0f} KiB "
+           f"(FETCH_SIZE) and writes {wc:.0f} KiB (WRITE_SIZE); "
+           f"factors {ff:.3f} and {fw:.3f} are applied below. FETCH_SIZE counts L2 misses "
+           "served by the fabric (Infinity Cache or HBM).", "",
+           "| kernel class | launches | fetch KiB/launch | write KiB/launch | scaled MB/launch |",
+           "|---|---:|---:|---:|---:|"]
+    table = {}
+    for cls, (prefix, _) in CLASSES.items():
+        fv = [v for k, vs in f.items() if k.startswith(prefix) for v in vs]
+        wv = [v for k, vs in w.items() if k.startswith(prefix) for v in vs]
+        if not fv or not wv:
+            continue
+        # launches of steps the device had already closed return at once: drop them
+        fv = [v for v in fv if v > 0.05 * max(fv)]
+        wv = [v for v in wv if v > 0.05 * max(wv)]
+        fk, wk = statistics.mean(fv), statistics.mean(wv)
+        b = (fk * ff + wk * fw) * 1024.0
+        table[cls] = {"bytes_per_launch": b, "digest": source_digest(cls)}
+        out.append(f"| {cls} | {len(fv)} | {fk:.1f} | {wk:.1f} | {b / 1e6:.3f} |")
+    out += ["", "```json", json.dumps({workload: table}, indent=1), "```", ""]
+    return "\n".join(out)
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "kernels":
+        sys.stdout.write(kernels(*sys.argv[2:5]))
+    elif sys.argv[1] == "traffic":
+        sys.stdout.write(traffic(*sys.argv[2:7]))
+    else:
+        raise SystemExit(__doc__)
