@@ -73,6 +73,8 @@ enum hh_status {
 #define HH_MAX_COARSE 4096
 /* Largest 1D grid handled by the single-workgroup tridiagonal solve. */
 #define HH_MAX_1D 1024
+/* Most right-hand sides in one hh_solve_batch call. */
+#define HH_MAX_BATCH 1024
 
 /*
  * hh_create_problem -- set up H for one model and frequency (Eq. 2-3).
@@ -128,6 +130,34 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
              unsigned flags, void* workspace_dev, size_t workspace_bytes, void* u_dev,
              int* iterations, double* true_rel_res, double* hist_host, int hist_cap,
              int* hist_len, void* stream);
+
+/* Bytes of device workspace hh_solve_batch needs: nrhs copies of the
+ * single-solve workspace (any flags). */
+int hh_workspace_bytes_batch(hh_problem p, int restart, int nrhs, size_t* bytes);
+
+/*
+ * hh_solve_batch -- hh_solve for nrhs sources of the same problem (same model,
+ * frequency and shift; several sources per frequency in the paper's modelling
+ * use), solved together: every kernel of an Arnoldi step covers all of them,
+ * the operators and multigrid hierarchy are shared, and each source keeps its
+ * own Krylov basis, least-squares problem and convergence test (a source whose
+ * cycle has stopped takes no further work in it; cycles close when every source
+ * has stopped). Each result is the one hh_solve gives for that source alone.
+ *   nrhs      : 1..HH_MAX_BATCH.
+ *   f_dev     : complex128 sources, nrhs grids back to back (not modified).
+ *   u_dev     : complex128 wavefields, nrhs grids back to back (caller-owned).
+ *   workspace : at least hh_workspace_bytes_batch(p, restart, nrhs) bytes.
+ *   iterations, true_rel_res, status : host arrays of nrhs entries (may be NULL);
+ *               status[i] is HH_OK, HH_NOT_CONVERGED or HH_ENUMERIC for source i.
+ *   hist_host : host array of nrhs * hist_cap entries (source i at i * hist_cap,
+ *               laid out as in hh_solve), or NULL with hist_cap = 0.
+ * Returns HH_OK when every source converged, HH_NOT_CONVERGED when any spent
+ * max_iters, HH_ENUMERIC when any met a non-finite value, or an error code.
+ */
+int hh_solve_batch(hh_problem p, int nrhs, const void* f_dev, double tol, int restart,
+                   int max_iters, unsigned flags, void* workspace_dev, size_t workspace_bytes,
+                   void* u_dev, int* iterations, double* true_rel_res, int* status,
+                   double* hist_host, int hist_cap, void* stream);
 
 /* Releases every device allocation of the handle. NULL is accepted. */
 int hh_destroy_problem(hh_problem p);

@@ -71,7 +71,8 @@ struct LevelData {
 
 struct PendingTime {
     int cycle, j;                   // Arnoldi step that made the launch
-    double bytes;
+    double bytes;                   // per working right-hand side
+    double shared;                  // once per launch (operator data read for all of them)
 };
 
 }  // namespace
@@ -95,9 +96,11 @@ struct hh_problem_s {
     int* dflag = nullptr;           // device scratch for checks
     double* dpartial = nullptr;
     cplx* nrm2_host = nullptr;      // pinned
-    HostRecord* rec = nullptr;      // pinned, written by the device
+    HostRecord* rec = nullptr;      // pinned, written by the device (one per right-hand side)
+    int rec_cap = 0;
     double* hist = nullptr;         // pinned, written by the device
-    int hist_cap = 0;
+    int64_t hist_cap = 0;           // entries
+    int64_t hist_stride = 0;        // entries per right-hand side
     hipStream_t stream = nullptr;
     // dispatch-stamped timing of one kernel class (hh_kernel_timer_*)
     struct {
@@ -203,35 +206,41 @@ bool kt_arm(hh_problem_s* p, int kid) {
     return true;
 }
 
-void kt_done(hh_problem_s* p, double bytes) {
-    p->kt.pending.push_back(PendingTime{p->kt.cycle, p->kt.j, bytes});
+void kt_done(hh_problem_s* p, double bytes, double shared) {
+    p->kt.pending.push_back(PendingTime{p->kt.cycle, p->kt.j, bytes, shared});
 }
 
-// After the stream is idle: keep the launches of steps that did work.
-int kt_harvest(hh_problem_s* p, const std::vector<int>& executed) {
+// After the stream is idle: keep the launches of steps that did work, with
+// the byte model times the number of right-hand sides that did the step
+// (executed[c][b] = steps right-hand side b took in cycle c + 1).
+int kt_harvest(hh_problem_s* p, const std::vector<std::vector<int>>& executed) {
     for (size_t i = 0; i < p->kt.pending.size(); ++i) {
         const PendingTime& t = p->kt.pending[i];
-        const bool did_work = t.cycle >= 1 && t.cycle <= (int)executed.size() &&
-                              t.j < executed[t.cycle - 1];
-        if (!did_work) continue;
+        int working = 0;
+        if (t.cycle >= 1 && t.cycle <= (int)executed.size())
+            for (int e : executed[t.cycle - 1]) working += t.j < e;
+        if (working == 0) continue;
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, p->kt.pool[2 * i], p->kt.pool[2 * i + 1]));
         p->kt.total_ms += ms;
-        p->kt.total_bytes += t.bytes;
+        p->kt.total_bytes += t.bytes * working + t.shared;
         p->kt.launches += 1;
     }
     p->kt.pending.clear();
     return HH_OK;
 }
 
-#define TIMED(KID, BYTES, EXPR)                      \
-    do {                                             \
-        const bool armed_ = kt_arm(p, (KID));        \
-        const hipError_t e2_ = (EXPR);               \
-        g_launch_events = LaunchEvents();            \
-        HIPCHK(e2_);                                 \
-        if (armed_) kt_done(p, (double)(BYTES));     \
+// Launch EXPR; when kernel class KID is being timed, stamp it and record its
+// algorithmic bytes: BYTES per right-hand side that did the step, SHARED once.
+#define TIMED2(KID, BYTES, SHARED, EXPR)                             \
+    do {                                                             \
+        const bool armed_ = kt_arm(p, (KID));                        \
+        const hipError_t e2_ = (EXPR);                               \
+        g_launch_events = LaunchEvents();                            \
+        HIPCHK(e2_);                                                 \
+        if (armed_) kt_done(p, (double)(BYTES), (double)(SHARED));   \
     } while (0)
+#define TIMED(KID, BYTES, EXPR) TIMED2(KID, BYTES, 0.0, EXPR)
 
 // ---------------------------------------------------------------------------
 // workspace layout
@@ -298,36 +307,35 @@ T* at(void* base, size_t off) {
 // preconditioner
 // ---------------------------------------------------------------------------
 // One V(2,2) cycle on level l >= 1: ec_l = V(l, bc_l), one kernel per leg,
-// in precision T.
+// in precision T, for every right-hand side of the batch.
 template <class T>
 int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* active,
-                  hipStream_t s) {
+                  hipStream_t s, const Batch& bt) {
     typedef typename Cx<T>::type C;
-    const double es = (double)sizeof(C), rs = (double)sizeof(T);
+    const double es = (double)sizeof(C);
     const int nl = (int)p->levels.size();
     C* b = at<C>(ws, L.bc[l]);
     C* x = at<C>(ws, L.ec[l]);
     if (l == nl - 1) {
         const double nc = p->nc;
-        TIMED(HH_KERNEL_GEMV, (nc * nc + 2 * nc) * es,
-              launch_vc_gemv(p->nc, Prec<T>::cinv(p), b, x, active, s));
+        TIMED2(HH_KERNEL_GEMV, 2 * nc * es, nc * nc * es,
+               launch_vc_gemv(p->nc, Prec<T>::cinv(p), b, x, active, s, bt));
         return HH_OK;
     }
-    (void)rs;
     const LevelData& lv = p->levels[l];
     const LevelData& nx = p->levels[l + 1];
     const auto A = Prec<T>::coarse(lv);
     C* x2 = at<C>(ws, L.t[l]);
     const double nl_ = (double)lv.size(), nn_ = (double)nx.size();
-    // down: b, 9 coefficients, omega/diag in, x2 out; up: x2, b, 9 coefficients,
-    // omega/diag in, x out (values of es bytes), plus the coarser vector
-    TIMED(HH_KERNEL_VC_DOWN_COARSE, 12.0 * es * nl_ + es * nn_,
-          launch_vc_coarse_down(A, b, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
-                                at<C>(ws, L.bc[l + 1]), active, s));
-    CHK(vcycle_coarse<T>(p, L, ws, l + 1, active, s));
-    TIMED(HH_KERNEL_VC_UP_COARSE, 13.0 * es * nl_ + es * nn_,
-          launch_vc_coarse_up(A, lv.halve_z, lv.halve_x, b, x2, at<C>(ws, L.ec[l + 1]), nx.nx, x,
-                              active, s));
+    // down: b in, x2 out, the coarser right-hand side out; up: x2, b in, x out,
+    // the coarser correction in; both read the 9 coefficients and omega/diag
+    TIMED2(HH_KERNEL_VC_DOWN_COARSE, 2.0 * es * nl_ + es * nn_, 10.0 * es * nl_,
+           launch_vc_coarse_down(A, b, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+                                 at<C>(ws, L.bc[l + 1]), active, s, bt));
+    CHK(vcycle_coarse<T>(p, L, ws, l + 1, active, s, bt));
+    TIMED2(HH_KERNEL_VC_UP_COARSE, 3.0 * es * nl_ + es * nn_, 10.0 * es * nl_,
+           launch_vc_coarse_up(A, lv.halve_z, lv.halve_x, b, x2, at<C>(ws, L.ec[l + 1]), nx.nx, x,
+                               active, s, bt));
     return HH_OK;
 }
 
@@ -336,11 +344,12 @@ int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* 
 // Krylov basis vector) and every kernel is predicated on st->active;
 // stand-alone (st == NULL) v = src. With giv (multigrid only) the first leg
 // normalises by 1/||src|| from the norm partials in giv->partial and hosts the
-// Givens step of the previous column.
+// Givens step of the previous column. All pointers are those of the first
+// right-hand side; the others follow at the batch stride.
 template <class T>
 int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const SolveState* st,
             cplx* vout, typename Cx<T>::type* z, hipStream_t s,
-            const GivensArgs* giv = nullptr) {
+            const GivensArgs* giv = nullptr, const Batch& bt = Batch()) {
     typedef typename Cx<T>::type C;
     const double es = (double)sizeof(C), rs = (double)sizeof(T);
     const double N = (double)p->N;
@@ -348,38 +357,39 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const S
     const int* active = st ? &st->active : nullptr;
     const auto M = Prec<T>::fine(p);
     if (p->ndim == 1) {
-        // src, m^2 in; v, z out
-        TIMED(HH_KERNEL_PCR, (32.0 + rs + es) * N,
-              launch_pcr_norm(M, src, scale, vout, z, active, s));
+        // src in, v and z out; m^2 shared
+        TIMED2(HH_KERNEL_PCR, (32.0 + es) * N, rs * N,
+               launch_pcr_norm(M, src, scale, vout, z, active, s, bt));
         return HH_OK;
     }
     const int nl = (int)p->levels.size();
     if (nl == 1) {   // the fine grid is the coarsest: dense inverse only
         const cplx* b = src;
         if (st) {
-            HIPCHK(launch_normalize_pred(src, st, vout, p->N, s));
+            HIPCHK(launch_normalize_pred(src, st, vout, p->N, s, bt));
             b = vout;
         }
         const double nc = p->nc;
-        TIMED(HH_KERNEL_GEMV, (nc * nc + 2 * nc) * es,
-              launch_vc_gemv(p->nc, Prec<T>::cinv(p), b, z, active, s));
+        TIMED2(HH_KERNEL_GEMV, 2 * nc * es, nc * nc * es,
+               launch_vc_gemv(p->nc, Prec<T>::cinv(p), b, z, active, s, bt));
         return HH_OK;
     }
     const LevelData& lv = p->levels[0];
     const LevelData& nx = p->levels[1];
     C* x2 = at<C>(ws, L.t[0]);
     const double N1 = (double)nx.size();
-    // down: w in, v out (complex128), m^2 and omega/diag in, x2 out; up: v in
-    // (complex128), x2, m^2, omega/diag in, z out; plus the coarse vector
-    TIMED(HH_KERNEL_VC_DOWN, (32.0 + rs + 2.0 * es) * N + es * N1,
-          launch_vc_fine_down(M, src, scale, giv ? giv->partial : nullptr, giv ? giv->nb : 0,
-                              vout, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
-                              at<C>(ws, L.bc[1]), active, giv, s));
+    // down: w in, v out (complex128), x2 out, the coarse right-hand side out;
+    // up: v in (complex128), x2 in, z out, the coarse correction in; both read
+    // m^2 and omega/diag (shared by the right-hand sides)
+    TIMED2(HH_KERNEL_VC_DOWN, (32.0 + es) * N + es * N1, (rs + es) * N,
+           launch_vc_fine_down(M, src, scale, giv ? giv->partial : nullptr, giv ? giv->nb : 0,
+                               vout, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+                               at<C>(ws, L.bc[1]), active, giv, s, bt));
     const cplx* b = vout ? vout : src;
-    CHK(vcycle_coarse<T>(p, L, ws, 1, active, s));
-    TIMED(HH_KERNEL_VC_UP, (16.0 + rs + 3.0 * es) * N + es * N1,
-          launch_vc_fine_up(M, lv.halve_z, lv.halve_x, b, x2, at<C>(ws, L.ec[1]), nx.nx, z,
-                            active, s));
+    CHK(vcycle_coarse<T>(p, L, ws, 1, active, s, bt));
+    TIMED2(HH_KERNEL_VC_UP, (16.0 + 2.0 * es) * N + es * N1, (rs + es) * N,
+           launch_vc_fine_up(M, lv.halve_z, lv.halve_x, b, x2, at<C>(ws, L.ec[1]), nx.nx, z,
+                             active, s, bt));
     return HH_OK;
 }
 
@@ -529,22 +539,28 @@ int check_ptr(const void* a, const char* name) {
     return HH_OK;
 }
 
-// pinned, device-visible memory written by kernels and polled by the host
-int ensure_host_buffers(hh_problem_s* p, int max_iters) {
-    if (!p->rec)
-        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->rec), sizeof(HostRecord),
+// pinned, device-visible memory written by kernels and polled by the host:
+// one progress record and one history of max_iters + 1 entries per right-hand side
+int ensure_host_buffers(hh_problem_s* p, int max_iters, int nrhs) {
+    if (p->rec_cap < nrhs) {
+        if (p->rec) HIPCHK(hipHostFree(p->rec));
+        p->rec = nullptr;
+        p->rec_cap = 0;
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->rec), (size_t)nrhs * sizeof(HostRecord),
                              hipHostMallocCoherent | hipHostMallocMapped));
-    if (p->hist_cap < max_iters + 1) {
-        if (p->hist) {
-            HIPCHK(hipHostFree(p->hist));
-            p->hist = nullptr;
-            p->hist_cap = 0;
-        }
-        const int cap = max_iters + 1 > 1024 ? max_iters + 1 : 1024;
-        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hist), (size_t)cap * sizeof(double),
-                             hipHostMallocCoherent | hipHostMallocMapped));
-        p->hist_cap = cap;
+        p->rec_cap = nrhs;
     }
+    const int64_t per = max_iters + 1 > 1024 ? max_iters + 1 : 1024;
+    if (p->hist_cap < per * nrhs) {
+        if (p->hist) HIPCHK(hipHostFree(p->hist));
+        p->hist = nullptr;
+        p->hist_cap = 0;
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&p->hist),
+                             (size_t)(per * nrhs) * sizeof(double),
+                             hipHostMallocCoherent | hipHostMallocMapped));
+        p->hist_cap = per * nrhs;
+    }
+    p->hist_stride = per;
     return HH_OK;
 }
 
@@ -566,17 +582,23 @@ RecView read_rec(const HostRecord* r) {
     return o;
 }
 
-// Spin until pred(record) holds; fails when the stream drained without it
-// (lost progress), on a stream error, or after kStallSeconds.
+// Spin until pred holds for the record of every right-hand side; fails when
+// the stream drained without it (lost progress), on a stream error, or after
+// kStallSeconds.
 template <class Pred>
-int wait_for(const hh_problem_s* p, hipStream_t s, Pred pred) {
+int wait_for(const hh_problem_s* p, int nrhs, hipStream_t s, Pred pred) {
+    auto all = [&]() {
+        for (int b = 0; b < nrhs; ++b)
+            if (!pred(read_rec(p->rec + b))) return false;
+        return true;
+    };
     auto t0 = std::chrono::steady_clock::now();
     for (unsigned spin = 0;; ++spin) {
-        if (pred(read_rec(p->rec))) return HH_OK;
+        if (all()) return HH_OK;
         if ((spin & 1023) == 1023) {
             const hipError_t q = hipStreamQuery(s);
             if (q == hipSuccess) {
-                if (pred(read_rec(p->rec))) return HH_OK;
+                if (all()) return HH_OK;
                 return fail(HH_EDEVICE, "device stopped without reaching the awaited state");
             }
             if (q != hipErrorNotReady)
@@ -826,33 +848,29 @@ int hh_orthogonalize(const void* V_dev, int64_t n, int k, void* w_dev, void* scr
     return HH_OK;
 }
 
-int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_iters,
-             unsigned flags, void* workspace_dev, size_t workspace_bytes, void* u_dev,
-             int* iterations, double* true_rel_res, double* hist_host, int hist_cap,
-             int* hist_len, void* stream) {
-    g_err.clear();
-    if (!p) return fail(HH_EINVAL, "problem is NULL");
-    CHK(check_ptr(f_dev, "f_dev"));
-    CHK(check_ptr(u_dev, "u_dev"));
-    CHK(check_ptr(workspace_dev, "workspace_dev"));
-    if (!(tol > 0.0 && tol < 1.0)) return fail(HH_EINVAL, "tol must be in (0, 1)");
-    if (restart < 1 || restart > kMaxRestart) return fail(HH_EINVAL, "restart must be in [1, 1024]");
-    if (max_iters < 1 || max_iters > (1 << 28)) return fail(HH_EINVAL, "max_iters must be in [1, 2^28]");
-    if (flags & ~(HH_NO_PRECOND | HH_PRECOND_F32)) return fail(HH_EINVAL, "unknown flag");
-    if ((flags & HH_NO_PRECOND) && (flags & HH_PRECOND_F32))
-        return fail(HH_EINVAL, "HH_NO_PRECOND and HH_PRECOND_F32 exclude each other");
-    if (hist_cap < 0 || (hist_cap > 0 && !hist_host)) return fail(HH_EINVAL, "bad history buffer");
-    if (f_dev == u_dev) return fail(HH_EINVAL, "f_dev and u_dev must be distinct");
+}  // extern "C"
+
+namespace {
+
+// Right-preconditioned FGMRES(restart) for nrhs right-hand sides of one
+// problem, each with its own Krylov basis, least-squares problem and
+// convergence (the kernels of a step cover all of them; a right-hand side
+// whose cycle has stopped returns at once). Steps advance together; a cycle
+// closes when every right-hand side has stopped it.
+int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart, int max_iters,
+               unsigned flags, void* workspace_dev, size_t workspace_bytes, cplx* u,
+               int* iterations, double* true_rel_res, int* status, double* hist_host,
+               int hist_cap, int* hist_len, hipStream_t s) {
     const int m = restart;
     const bool no_prec = (flags & HH_NO_PRECOND) != 0;
     const bool f32 = (flags & HH_PRECOND_F32) != 0;
     const Layout L = layout(p, m, f32 ? sizeof(cplxf) : sizeof(cplx));
-    if (workspace_bytes < L.total) return fail(HH_EINVAL, "workspace too small");
-    CHK(ensure_host_buffers(p, max_iters));
-
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    void* ws = workspace_dev;
+    if (workspace_bytes < (size_t)nrhs * L.total) return fail(HH_EINVAL, "workspace too small");
+    CHK(ensure_host_buffers(p, max_iters, nrhs));
     const int64_t N = p->N;
+    const Batch bt{nrhs, (int64_t)L.total, N};
+
+    void* ws = workspace_dev;
     cplx* V = at<cplx>(ws, L.V);
     cplx* Z = at<cplx>(ws, L.Z);
     cplxf* Zf = at<cplxf>(ws, L.Z);
@@ -868,47 +886,55 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
     cplx* y = at<cplx>(ws, L.y);
     SolveState* st = at<SolveState>(ws, L.st);
     const int* active = &st->active;
-    cplx* u = static_cast<cplx*>(u_dev);
     const FineOp H = op_H(p);
     double* dhist = nullptr;
     HostRecord* drec = nullptr;
     HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&dhist), p->hist, 0));
     HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&drec), p->rec, 0));
-    std::memset(p->rec, 0, sizeof(HostRecord));
+    std::memset(p->rec, 0, (size_t)nrhs * sizeof(HostRecord));
     p->kt.pending.clear();
 
     // prologue: b = W f, ||b||, u = 0
-    HIPCHK(launch_weight_rhs(H, static_cast<const cplx*>(f_dev), b, s));
-    HIPCHK(launch_dot_blocks(b, N, 1, b, partial, s));
-    HIPCHK(launch_solve_init(st, partial, L.nbN, m, max_iters, tol, drec, dhist, s));
-    HIPCHK(hipMemsetAsync(u, 0, (size_t)N * sizeof(cplx), s));
+    HIPCHK(launch_weight_rhs(H, f, b, s, bt));
+    HIPCHK(launch_dot_blocks(b, N, 1, b, partial, s, bt));
+    HIPCHK(launch_solve_init(st, partial, L.nbN, m, max_iters, tol, drec, dhist, p->hist_stride,
+                             s, bt));
+    HIPCHK(hipMemsetAsync(u, 0, (size_t)nrhs * N * sizeof(cplx), s));
 
-    std::vector<int> executed;   // Arnoldi steps that did work, per cycle
-    double last_est = 1.0;
+    // The Givens step of column j runs inside the first V-cycle leg of step
+    // j + 1 when the multigrid path is taken; the last column's (or one whose
+    // next step is not enqueued) runs as a kernel of its own.
+    const bool fold = !no_prec && p->ndim == 2 && p->levels.size() >= 2 &&
+                      m <= (f32 ? vc_fine_down_givens_capacity(op_Mf(p))
+                                : vc_fine_down_givens_capacity(op_M(p)));
+    const GivensArgs giv{st, h1, h2, partial, L.nbS, R, cs, sn, g, drec, dhist,
+                         (int64_t)L.total, p->hist_stride};
+
+    std::vector<std::vector<int>> executed;   // Arnoldi steps that did work, per cycle and RHS
+    double min_est = 1.0;
+    auto est_of = [&](int rb) { return ((const volatile HostRecord*)(p->rec + rb))->est; };
     for (int cycle = 1;; ++cycle) {
         p->kt.cycle = cycle;
-        HIPCHK(launch_residual_norm(H, b, u, w, partial, &st->done, s));
-        HIPCHK(launch_cycle_start(st, partial, L.nbA, g, drec, s));
+        HIPCHK(launch_residual_norm(H, b, u, w, partial, &st->done, s, bt));
+        HIPCHK(launch_cycle_start(st, partial, L.nbA, g, drec, s, bt));
         // close to convergence: learn whether this cycle opens before enqueuing it
-        if (last_est <= tol)
-            CHK(wait_for(p, s, [&](const RecView& r) { return r.done || r.cycles >= cycle; }));
-        // The Givens step of column j runs inside the first V-cycle leg of step
-        // j + 1 when the multigrid path is taken; the last column's (or one
-        // whose next step is not enqueued) runs as a kernel of its own.
-        const bool fold = !no_prec && p->ndim == 2 && p->levels.size() >= 2 &&
-                          m <= (f32 ? vc_fine_down_givens_capacity(op_Mf(p))
-                                    : vc_fine_down_givens_capacity(op_M(p)));
-        const GivensArgs giv{st, h1, h2, partial, L.nbS, R, cs, sn, g, drec, dhist};
+        if (min_est <= tol)
+            CHK(wait_for(p, nrhs, s,
+                         [&](const RecView& r) { return r.done || r.cycles >= cycle; }));
         bool givens_pending = false;
         bool closed = false;
         for (int j = 0; j < m; ++j) {
             if (j >= kLookahead)
-                CHK(wait_for(p, s, [&](const RecView& r) {
+                CHK(wait_for(p, nrhs, s, [&](const RecView& r) {
                     return r.done || r.stops >= cycle ||
                            (r.cycles >= cycle && r.jstep >= j - kLookahead + 1);
                 }));
-            const RecView r = read_rec(p->rec);
-            if (r.done || r.stops >= cycle) {
+            bool all_stopped = true;
+            for (int rb = 0; rb < nrhs && all_stopped; ++rb) {
+                const RecView r = read_rec(p->rec + rb);
+                all_stopped = r.done || r.stops >= cycle;
+            }
+            if (all_stopped) {
                 closed = true;
                 break;
             }
@@ -917,61 +943,135 @@ int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_i
             cplx* vj = V + (size_t)j * N;
             const GivensArgs* gv = givens_pending ? &giv : nullptr;
             if (no_prec) {
-                HIPCHK(launch_normalize_pred(w, st, vj, N, s));
+                HIPCHK(launch_normalize_pred(w, st, vj, N, s, bt));
                 TIMED(HH_KERNEL_APPLY_DOT, (40.0 + 16.0 * kk) * (double)N,
-                      launch_apply_dot(H, vj, w, V, kk, partial, active, s));
+                      launch_apply_dot(H, vj, w, V, kk, partial, active, s, bt));
             } else if (f32) {
                 cplxf* zz = Zf + (size_t)j * N;
-                CHK(precond<float>(p, L, ws, w, st, vj, zz, s, gv));
-                TIMED(HH_KERNEL_APPLY_DOT, (32.0 + 16.0 * kk) * (double)N,
-                      launch_apply_dot(H, zz, w, V, kk, partial, active, s));
+                CHK(precond<float>(p, L, ws, w, st, vj, zz, s, gv, bt));
+                TIMED2(HH_KERNEL_APPLY_DOT, (24.0 + 16.0 * kk) * (double)N, 8.0 * (double)N,
+                       launch_apply_dot(H, zz, w, V, kk, partial, active, s, bt));
             } else {
                 cplx* zz = Z + (size_t)j * N;
-                CHK(precond<double>(p, L, ws, w, st, vj, zz, s, gv));
-                TIMED(HH_KERNEL_APPLY_DOT, (40.0 + 16.0 * kk) * (double)N,
-                      launch_apply_dot(H, zz, w, V, kk, partial, active, s));
+                CHK(precond<double>(p, L, ws, w, st, vj, zz, s, gv, bt));
+                TIMED2(HH_KERNEL_APPLY_DOT, (32.0 + 16.0 * kk) * (double)N, 8.0 * (double)N,
+                       launch_apply_dot(H, zz, w, V, kk, partial, active, s, bt));
             }
             givens_pending = false;
             TIMED(HH_KERNEL_REDUCE, 16.0 * kk * (L.nbA + 1),
-                  launch_reduce_pred(partial, L.nbA, kk, h1, active, s));
+                  launch_reduce_pred(partial, L.nbA, kk, h1, active, s, bt));
             TIMED(HH_KERNEL_AXPY_DOT, (kk + 2) * 16.0 * (double)N,
-                  launch_axpy_dot(V, N, kk, h1, w, partial, active, s));
+                  launch_axpy_dot(V, N, kk, h1, w, partial, active, s, bt));
             TIMED(HH_KERNEL_REDUCE, 16.0 * kk * (L.nbN + 1),
-                  launch_reduce_pred(partial, L.nbN, kk, h2, active, s));
+                  launch_reduce_pred(partial, L.nbN, kk, h2, active, s, bt));
             TIMED(HH_KERNEL_AXPY_NORM, (kk + 2) * 16.0 * (double)N,
-                  launch_axpy_norm(V, N, kk, h2, w, partial, active, s));
+                  launch_axpy_norm(V, N, kk, h2, w, partial, active, s, bt));
             if (fold) {
                 givens_pending = true;
             } else {
-                TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbS, launch_givens_step(giv, s));
+                TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbS, launch_givens_step(giv, s, bt));
             }
         }
         // a pending step after a break belongs to a cycle the device has closed
         if (givens_pending && !closed)
-            TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbS, launch_givens_step(giv, s));
-        // the cycle closes on a step (or the solve ended at its start)
-        CHK(wait_for(p, s, [&](const RecView& r) { return r.done || r.stops >= cycle; }));
-        const RecView r = read_rec(p->rec);
-        executed.push_back(r.stops >= cycle ? r.jstep : 0);
-        last_est = ((const volatile HostRecord*)p->rec)->est;
-        if (r.stops < cycle) break;                 // finished at the cycle start
+            TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbS, launch_givens_step(giv, s, bt));
+        // the cycle closes on a step for every right-hand side (or they ended at its start)
+        CHK(wait_for(p, nrhs, s, [&](const RecView& r) { return r.done || r.stops >= cycle; }));
+        std::vector<int> ex(nrhs, 0);
+        bool any_stopped = false, all_done = true;
+        min_est = 1.0;
+        for (int rb = 0; rb < nrhs; ++rb) {
+            const RecView r = read_rec(p->rec + rb);
+            ex[rb] = r.stops >= cycle ? r.jstep : 0;
+            any_stopped = any_stopped || r.stops >= cycle;
+            all_done = all_done && r.done;
+            if (!r.done) min_est = std::fmin(min_est, est_of(rb));
+        }
+        executed.push_back(ex);
+        if (!any_stopped) break;                    // every right-hand side finished at the start
         if (f32)
-            HIPCHK(launch_cycle_finish(st, R, g, y, Zf, N, u, s));
+            HIPCHK(launch_cycle_finish(st, R, g, y, Zf, N, u, s, bt));
         else
-            HIPCHK(launch_cycle_finish(st, R, g, y, no_prec ? V : Z, N, u, s));
-        if (r.done) break;                          // non-finite value inside the cycle
+            HIPCHK(launch_cycle_finish(st, R, g, y, no_prec ? V : Z, N, u, s, bt));
+        if (all_done) break;                        // non-finite values inside the cycle
     }
     HIPCHK(hipStreamSynchronize(s));
-    SolveState fin;
-    HIPCHK(hipMemcpy(&fin, st, sizeof(SolveState), hipMemcpyDeviceToHost));
+    std::vector<SolveState> fin(nrhs);
+    HIPCHK(hipMemcpy2D(fin.data(), sizeof(SolveState), st, L.total, sizeof(SolveState), nrhs,
+                       hipMemcpyDeviceToHost));
     CHK(kt_harvest(p, executed));
-    const int it = fin.it;
-    if (iterations) *iterations = it;
-    if (true_rel_res) *true_rel_res = fin.rel;
-    if (hist_len) *hist_len = it + 1;
-    for (int i = 0; i <= it && i < hist_cap; ++i) hist_host[i] = p->hist[i];
-    if (fin.status == -4) return fail(HH_ENUMERIC, "non-finite value in the iteration");
-    return fin.status == 1 ? HH_NOT_CONVERGED : HH_OK;
+    bool any_bad = false, any_nc = false;
+    for (int rb = 0; rb < nrhs; ++rb) {
+        const SolveState& q = fin[rb];
+        if (iterations) iterations[rb] = q.it;
+        if (true_rel_res) true_rel_res[rb] = q.rel;
+        const int code = q.status == -4 ? HH_ENUMERIC : q.status == 1 ? HH_NOT_CONVERGED : HH_OK;
+        if (status) status[rb] = code;
+        any_bad = any_bad || code == HH_ENUMERIC;
+        any_nc = any_nc || code == HH_NOT_CONVERGED;
+        if (hist_host)
+            for (int i = 0; i <= q.it && i < hist_cap; ++i)
+                hist_host[(int64_t)rb * hist_cap + i] = p->hist[rb * p->hist_stride + i];
+    }
+    if (hist_len) *hist_len = fin[0].it + 1;
+    if (any_bad) return fail(HH_ENUMERIC, "non-finite value in the iteration");
+    return any_nc ? HH_NOT_CONVERGED : HH_OK;
+}
+
+int check_solve_args(hh_problem p, const void* f_dev, const void* u_dev, const void* ws,
+                     double tol, int restart, int max_iters, unsigned flags) {
+    if (!p) return fail(HH_EINVAL, "problem is NULL");
+    CHK(check_ptr(f_dev, "f_dev"));
+    CHK(check_ptr(u_dev, "u_dev"));
+    CHK(check_ptr(ws, "workspace_dev"));
+    if (!(tol > 0.0 && tol < 1.0)) return fail(HH_EINVAL, "tol must be in (0, 1)");
+    if (restart < 1 || restart > kMaxRestart) return fail(HH_EINVAL, "restart must be in [1, 1024]");
+    if (max_iters < 1 || max_iters > (1 << 28)) return fail(HH_EINVAL, "max_iters must be in [1, 2^28]");
+    if (flags & ~(HH_NO_PRECOND | HH_PRECOND_F32)) return fail(HH_EINVAL, "unknown flag");
+    if ((flags & HH_NO_PRECOND) && (flags & HH_PRECOND_F32))
+        return fail(HH_EINVAL, "HH_NO_PRECOND and HH_PRECOND_F32 exclude each other");
+    if (f_dev == u_dev) return fail(HH_EINVAL, "f_dev and u_dev must be distinct");
+    return HH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hh_solve(hh_problem p, const void* f_dev, double tol, int restart, int max_iters,
+             unsigned flags, void* workspace_dev, size_t workspace_bytes, void* u_dev,
+             int* iterations, double* true_rel_res, double* hist_host, int hist_cap,
+             int* hist_len, void* stream) {
+    g_err.clear();
+    CHK(check_solve_args(p, f_dev, u_dev, workspace_dev, tol, restart, max_iters, flags));
+    if (hist_cap < 0 || (hist_cap > 0 && !hist_host)) return fail(HH_EINVAL, "bad history buffer");
+    return solve_impl(p, 1, static_cast<const cplx*>(f_dev), tol, restart, max_iters, flags,
+                      workspace_dev, workspace_bytes, static_cast<cplx*>(u_dev), iterations,
+                      true_rel_res, nullptr, hist_host, hist_cap, hist_len,
+                      static_cast<hipStream_t>(stream));
+}
+
+int hh_workspace_bytes_batch(hh_problem p, int restart, int nrhs, size_t* bytes) {
+    g_err.clear();
+    if (!p || !bytes) return fail(HH_EINVAL, "NULL argument");
+    if (restart < 1 || restart > kMaxRestart) return fail(HH_EINVAL, "restart must be in [1, 1024]");
+    if (nrhs < 1 || nrhs > HH_MAX_BATCH) return fail(HH_EINVAL, "nrhs must be in [1, HH_MAX_BATCH]");
+    *bytes = (size_t)nrhs * layout(p, restart).total;
+    return HH_OK;
+}
+
+int hh_solve_batch(hh_problem p, int nrhs, const void* f_dev, double tol, int restart,
+                   int max_iters, unsigned flags, void* workspace_dev, size_t workspace_bytes,
+                   void* u_dev, int* iterations, double* true_rel_res, int* status,
+                   double* hist_host, int hist_cap, void* stream) {
+    g_err.clear();
+    CHK(check_solve_args(p, f_dev, u_dev, workspace_dev, tol, restart, max_iters, flags));
+    if (nrhs < 1 || nrhs > HH_MAX_BATCH) return fail(HH_EINVAL, "nrhs must be in [1, HH_MAX_BATCH]");
+    if (hist_cap < 0 || (hist_cap > 0 && !hist_host)) return fail(HH_EINVAL, "bad history buffer");
+    return solve_impl(p, nrhs, static_cast<const cplx*>(f_dev), tol, restart, max_iters, flags,
+                      workspace_dev, workspace_bytes, static_cast<cplx*>(u_dev), iterations,
+                      true_rel_res, status, hist_host, hist_cap, nullptr,
+                      static_cast<hipStream_t>(stream));
 }
 
 int hh_kernel_timer_start(hh_problem p, int kernel_id) {

@@ -34,8 +34,10 @@ struct GivensArgs {
     double* cs;               // rotations
     cplx* sn;
     cplx* g;                  // rotated right-hand side
-    HostRecord* rec;          // progress record in pinned host memory
+    HostRecord* rec;          // progress records in pinned host memory (one per right-hand side)
     double* hist;             // residual estimates, pinned host memory
+    int64_t bs;               // bytes between the workspaces of consecutive right-hand sides
+    int64_t hist_stride;      // entries between the histories of consecutive right-hand sides
 };
 
 // Capacity (in columns) of LDS staging a caller provides: scol holds
@@ -45,8 +47,21 @@ struct GivensArgs {
 // GMRES, Eq. 7's outer solver): column = h1 + h2 with h_{j+1,j} = ||w||, the
 // previous rotations applied, a new rotation that zeroes h_{j+1,j}, the rotated
 // right-hand side, the residual estimate |g_{j+1}| / beta0 and the decision to
-// stop the cycle. Called by every thread of one workgroup (blockDim >= 64).
-__device__ inline void givens_body(const GivensArgs& a, cplx* scol, double* scs, cplx* ssn) {
+// stop the cycle. Called by every thread of one workgroup (blockDim >= 64)
+// for right-hand side rb.
+__device__ inline void givens_body(const GivensArgs& ga, int rb, cplx* scol, double* scs,
+                                   cplx* ssn) {
+    GivensArgs a = ga;                 // this right-hand side's state
+    a.st = rhs_nn(ga.st, rb, ga.bs);
+    a.h1 = rhs_nn(ga.h1, rb, ga.bs);
+    a.h2 = rhs_nn(ga.h2, rb, ga.bs);
+    a.partial = rhs_nn(ga.partial, rb, ga.bs);
+    a.R = rhs_nn(ga.R, rb, ga.bs);
+    a.cs = rhs_nn(ga.cs, rb, ga.bs);
+    a.sn = rhs_nn(ga.sn, rb, ga.bs);
+    a.g = rhs_nn(ga.g, rb, ga.bs);
+    a.rec = ga.rec + rb;
+    a.hist = ga.hist + (int64_t)rb * ga.hist_stride;
     SolveState* st = a.st;
     if (__hip_atomic_load(&st->active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) return;
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;

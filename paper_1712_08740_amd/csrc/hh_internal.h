@@ -6,6 +6,7 @@
 #include <hip/hip_ext.h>
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 namespace hh {
 
@@ -178,6 +179,33 @@ typedef CoarseOpT<double> CoarseOp;
 // Largest restart length (columns of the least-squares problem)
 constexpr int kMaxColumns = 1024;
 
+// Several right-hand sides solved together share the operators; each has its
+// own copy of the solver workspace (same layout), `bs` bytes apart, and its
+// source / wavefield `fs` elements apart in the caller's arrays. Kernels take
+// the right-hand side from a grid dimension. One right-hand side: n = 1.
+struct Batch {
+    int n = 1;
+    int64_t bs = 0;       // bytes between the workspaces of consecutive right-hand sides
+    int64_t fs = 0;       // elements between consecutive sources / wavefields
+};
+
+// p advanced by `rb` strides of `bytes` (null stays null). Pointer arithmetic
+// (not an integer round trip) keeps the pointer's provenance, so the compiler
+// still knows it addresses global memory and emits global, not flat, accesses.
+template <class T>
+__host__ __device__ __forceinline__ T* rhs_at(T* p, int rb, int64_t bytes) {
+    typedef typename std::conditional<std::is_const<T>::value, const char, char>::type B;
+    return p ? reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (int64_t)rb * bytes) : p;
+}
+// the same for a pointer that is never null (no select: keeps the compiler's
+// proof that read-only arguments are not clobbered, so uniform values are
+// fetched with scalar loads)
+template <class T>
+__host__ __device__ __forceinline__ T* rhs_nn(T* p, int rb, int64_t bytes) {
+    typedef typename std::conditional<std::is_const<T>::value, const char, char>::type B;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(p) + (int64_t)rb * bytes);
+}
+
 // Workgroups of a launch are handed to the 8 XCDs round-robin by linear id.
 // Map the linear id w (< n) to a logical tile index so that each XCD runs a
 // contiguous range of tiles: neighbouring tiles then share halo data in the
@@ -220,7 +248,8 @@ hipError_t dense_invert(int n, cplx* A, cplx* scratch, int* perm, hipStream_t s)
 hipError_t launch_pcr_solve(const FineOp& op, const cplx* d, cplx* x, hipStream_t s);
 
 // b = W f
-hipError_t launch_weight_rhs(const FineOp& op, const cplx* f, cplx* b, hipStream_t s);
+hipError_t launch_weight_rhs(const FineOp& op, const cplx* f, cplx* b, hipStream_t s,
+                             const Batch& bt = Batch());
 // validation of the slowness: flags[0] |= any non-finite or <= 0, mmax[0] = max
 hipError_t launch_check_slowness(const double* m, int64_t n, double* m2, int* flag,
                                  double* mmax_partial, int nb, hipStream_t s);
@@ -261,93 +290,103 @@ struct HostRecord {
 // ---- fused, predicated Arnoldi kernels (krylov.hip) -----------------------
 // w = H z and partial[i*nb + blk] = block sums of conj(V_i) w (nb = apply_blocks)
 hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx* V, int k,
-                            cplx* partial, const int* active, hipStream_t s);
+                            cplx* partial, const int* active, hipStream_t s,
+                            const Batch& bt = Batch());
 hipError_t launch_apply_dot(const FineOp& op, const cplxf* z, cplx* w, const cplx* V, int k,
-                            cplx* partial, const int* active, hipStream_t s);
+                            cplx* partial, const int* active, hipStream_t s,
+                            const Batch& bt = Batch());
 int apply_blocks(const FineOp& op);
 int node_blocks(int64_t n);
 // blocks of the norm kernel (its partial sums are re-read by each consumer)
 constexpr int kNormBlocks = 512;
 int norm_blocks(int64_t n);
 hipError_t launch_dot_blocks(const cplx* V, int64_t n, int k, const cplx* w, cplx* partial,
-                             hipStream_t s);
+                             hipStream_t s, const Batch& bt = Batch());
 // w -= V h; partial = block sums of conj(V_i) w (nb = node_blocks(n))
 hipError_t launch_axpy_dot(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
-                           const int* active, hipStream_t s);
+                           const int* active, hipStream_t s, const Batch& bt = Batch());
 // w -= V h; partial[blk].x = block sums of |w|^2 (nb = norm_blocks(n))
 hipError_t launch_axpy_norm(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
-                            const int* active, hipStream_t s);
+                            const int* active, hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_reduce_pred(const cplx* partial, int nb, int k, cplx* out, const int* active,
-                              hipStream_t s);
+                              hipStream_t s, const Batch& bt = Batch());
 // r = b - H u; partial[blk].x = block sums of |r|^2 (skipped when *done)
 hipError_t launch_residual_norm(const FineOp& op, const cplx* b, const cplx* u, cplx* r,
-                                cplx* partial, const int* done, hipStream_t s);
+                                cplx* partial, const int* done, hipStream_t s,
+                                const Batch& bt = Batch());
 hipError_t launch_cycle_start(SolveState* st, const cplx* partial, int nb, cplx* g,
-                              HostRecord* rec, hipStream_t s);
+                              HostRecord* rec, hipStream_t s, const Batch& bt = Batch());
 struct GivensArgs;
-hipError_t launch_givens_step(const GivensArgs& a, hipStream_t s);
+hipError_t launch_givens_step(const GivensArgs& a, hipStream_t s, const Batch& bt = Batch());
 // y = R^{-1} g, x += Z y for the st->k columns of the cycle, then st->k = 0
 hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
-                               const cplx* Z, int64_t n, cplx* x, hipStream_t s);
+                               const cplx* Z, int64_t n, cplx* x, hipStream_t s,
+                               const Batch& bt = Batch());
 hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
-                               const cplxf* Z, int64_t n, cplx* x, hipStream_t s);
+                               const cplxf* Z, int64_t n, cplx* x, hipStream_t s,
+                               const Batch& bt = Batch());
 hipError_t launch_normalize_pred(const cplx* w, const SolveState* st, cplx* v, int64_t n,
-                                 hipStream_t s);
+                                 hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
-                             double tol, HostRecord* rec, double* hist, hipStream_t s);
+                             double tol, HostRecord* rec, double* hist, int64_t hist_stride,
+                             hipStream_t s, const Batch& bt = Batch());
 
 // ---- V-cycle kernels (vcycle_tiled.hip, coarsest.hip) ------------------------
+// coarsest level: y = A x (one right-hand side), or for every right-hand side
+// of a batch (x, y and the predicate in each right-hand side's workspace)
 hipError_t launch_vc_gemv(int n, const cplx* A, const cplx* x, cplx* y, const int* active,
-                          hipStream_t s);
+                          hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_gemv(int n, const cplxf* A, const cplxf* x, cplxf* y, const int* active,
-                          hipStream_t s);
+                          hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_gemv(int n, const cplxf* A, const cplx* x, cplxf* y, const int* active,
-                          hipStream_t s);
+                          hipStream_t s, const Batch& bt = Batch());
 // temporally blocked legs (vcycle_tiled.hip): down = two pre-sweeps from zero,
 // residual and restriction; up = prolongation and two post-sweeps
-// (the smoother weight enters through op.wdinv = omega_J / diag)
+// (the smoother weight enters through op.wdinv = omega_J / diag).
 // The fine down leg normalises its input: v = s * src is written to bout and
 // the outputs are those of v, with s = *scale, or s = 1/||src|| from the
 // per-block sums of |src|^2 in npart (nbn entries) when npart is given. With
-// giv non-null and giv->st set, one extra workgroup performs that Givens step
-// (restart length at most vc_fine_down_givens_capacity(op)).
+// giv non-null and giv->st set, one extra workgroup per right-hand side
+// performs that Givens step (restart length at most
+// vc_fine_down_givens_capacity(op)).
 hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, const double* scale,
                                const cplx* npart, int nbn, cplx* bout, cplx* x2, int hz, int hx,
                                int nzc, int nxc, cplx* bc, const int* active,
-                               const GivensArgs* giv, hipStream_t s);
+                               const GivensArgs* giv, hipStream_t s, const Batch& bt = Batch());
 int vc_fine_down_givens_capacity(const FineOp& op);
 // single-precision cycle: the Krylov vector (src, bout) stays complex128
 hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, const double* scale,
                                const cplx* npart, int nbn, cplx* bout, cplxf* x2, int hz, int hx,
                                int nzc, int nxc, cplxf* bc, const int* active,
-                               const GivensArgs* giv, hipStream_t s);
+                               const GivensArgs* giv, hipStream_t s, const Batch& bt = Batch());
 int vc_fine_down_givens_capacity(const FineOpT<float>& op);
 hipError_t launch_vc_coarse_down(const CoarseOpT<float>& op, const cplxf* b, cplxf* x2, int hz,
                                  int hx, int nzc, int nxc, cplxf* bc, const int* active,
-                                 hipStream_t s);
+                                 hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_fine_up(const FineOpT<float>& op, int hz, int hx, const cplx* b,
                              const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
-                             const int* active, hipStream_t s);
+                             const int* active, hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_coarse_up(const CoarseOpT<float>& op, int hz, int hx, const cplxf* b,
                                const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
-                               const int* active, hipStream_t s);
+                               const int* active, hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz,
                                  int hx, int nzc, int nxc, cplx* bc, const int* active,
-                                 hipStream_t s);
+                                 hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b,
                              const cplx* x2, const cplx* e, int nxc, cplx* out, const int* active,
-                             hipStream_t s);
+                             hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b,
                                const cplx* x2, const cplx* e, int nxc, cplx* out,
-                               const int* active, hipStream_t s);
+                               const int* active, hipStream_t s, const Batch& bt = Batch());
 // wdinv = wj / diag of a level operator (set-up)
 hipError_t launch_wdinv_fine(const FineOp& op, double wj, cplx* wdinv, hipStream_t s);
 hipError_t launch_wdinv_coarse(const CoarseOp& op, double wj, cplx* wdinv, hipStream_t s);
 // PCR with the normalisation of the Arnoldi vector folded in (vout = s*src, x = M^{-1} vout)
 hipError_t launch_pcr_norm(const FineOp& op, const cplx* src, const double* scale, cplx* vout,
-                           cplx* x, const int* active, hipStream_t s);
+                           cplx* x, const int* active, hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_pcr_norm(const FineOpT<float>& op, const cplx* src, const double* scale,
-                           cplx* vout, cplxf* x, const int* active, hipStream_t s);
+                           cplx* vout, cplxf* x, const int* active, hipStream_t s,
+                           const Batch& bt = Batch());
 
 // precision conversions (set-up of the single-precision preconditioner), RNE
 hipError_t launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s);

@@ -30,7 +30,10 @@ __device__ __forceinline__ cplx block_sum(cplx v, cplx* sh) {
 }
 
 __global__ void __launch_bounds__(EB) k_weight_rhs(FineOp op, const cplx* __restrict__ f,
-                                                   cplx* __restrict__ b) {
+                                                   cplx* __restrict__ b, int64_t bs, int64_t fs) {
+    const int rb = blockIdx.y;
+    f += rb * fs;
+    b = rhs_nn(b, rb, bs);
     const int64_t p = (int64_t)blockIdx.x * EB + threadIdx.x;
     const int64_t n = (int64_t)op.nz * op.nx;
     if (p >= n) return;
@@ -112,8 +115,14 @@ __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const ZC* __restri
                                                    cplx* __restrict__ w,
                                                    const cplx* __restrict__ V, int k,
                                                    cplx* __restrict__ partial,
-                                                   const int* __restrict__ active) {
+                                                   const int* __restrict__ active, int64_t bs) {
+    const int rb = blockIdx.z;
+    active = rhs_at(active, rb, bs);
     if (off(active)) return;
+    z = rhs_nn(z, rb, bs);
+    w = rhs_nn(w, rb, bs);
+    V = rhs_nn(V, rb, bs);
+    partial = rhs_nn(partial, rb, bs);
     __shared__ cplx lds[KC * 256];
     int ix, iz, tid;
     if (NDIM == 2) {
@@ -172,8 +181,12 @@ __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const ZC* __restri
 // plain projections V^H w (for the stand-alone orthogonalisation entry point)
 __global__ void __launch_bounds__(256) k_dot_blocks(const cplx* __restrict__ V, int64_t n, int k,
                                                     const cplx* __restrict__ w,
-                                                    cplx* __restrict__ partial) {
+                                                    cplx* __restrict__ partial, int64_t bs) {
     __shared__ cplx lds[KC * 256];
+    const int rb = blockIdx.y;
+    V = rhs_nn(V, rb, bs);
+    w = rhs_nn(w, rb, bs);
+    partial = rhs_nn(partial, rb, bs);
     const int tid = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * 256 + tid;
     const bool valid = p < n;
@@ -203,8 +216,14 @@ __global__ void __launch_bounds__(256) k_axpy_dot(const cplx* __restrict__ V, in
                                                   const cplx* __restrict__ h,
                                                   cplx* __restrict__ w,
                                                   cplx* __restrict__ partial,
-                                                  const int* __restrict__ active) {
+                                                  const int* __restrict__ active, int64_t bs) {
+    const int rb = blockIdx.y;
+    active = rhs_at(active, rb, bs);
     if (off(active)) return;
+    V = rhs_nn(V, rb, bs);
+    h = rhs_nn(h, rb, bs);
+    w = rhs_nn(w, rb, bs);
+    partial = rhs_nn(partial, rb, bs);
     __shared__ cplx lds[KC * 256];
     const int tid = threadIdx.x;
     const int64_t p = (int64_t)blockIdx.x * 256 + tid;
@@ -249,8 +268,14 @@ __global__ void __launch_bounds__(256) k_axpy_norm(const cplx* __restrict__ V, i
                                                    const cplx* __restrict__ h,
                                                    cplx* __restrict__ w,
                                                    cplx* __restrict__ partial,
-                                                   const int* __restrict__ active) {
+                                                   const int* __restrict__ active, int64_t bs) {
+    const int rb = blockIdx.y;
+    active = rhs_at(active, rb, bs);
     if (off(active)) return;
+    V = rhs_nn(V, rb, bs);
+    h = rhs_nn(h, rb, bs);
+    w = rhs_nn(w, rb, bs);
+    partial = rhs_nn(partial, rb, bs);
     __shared__ cplx sh[4];
     double acc = 0.0;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n;
@@ -266,8 +291,12 @@ __global__ void __launch_bounds__(256) k_axpy_norm(const cplx* __restrict__ V, i
 // predicated fixed-order reduction of partial sums (k blocks of 64 threads)
 __global__ void __launch_bounds__(64) k_reduce_pred(const cplx* __restrict__ partial, int nb,
                                                     cplx* __restrict__ out,
-                                                    const int* __restrict__ active) {
+                                                    const int* __restrict__ active, int64_t bs) {
+    const int rb = blockIdx.y;
+    active = rhs_at(active, rb, bs);
     if (off(active)) return;
+    partial = rhs_nn(partial, rb, bs);
+    out = rhs_nn(out, rb, bs);
     const int i = blockIdx.x;
     const cplx* pi = partial + (int64_t)i * nb;
     cplx acc = mk(0.0, 0.0);
@@ -285,8 +314,15 @@ __global__ void __launch_bounds__(256) k_residual_norm(FineOp op, const cplx* __
                                                        const cplx* __restrict__ u,
                                                        cplx* __restrict__ r,
                                                        cplx* __restrict__ partial,
-                                                       const int* __restrict__ done) {
+                                                       const int* __restrict__ done, int64_t bs,
+                                                       int64_t fs) {
+    const int rb = blockIdx.z;
+    done = rhs_at(done, rb, bs);
     if (*done) return;
+    b = rhs_nn(b, rb, bs);
+    u += rb * fs;
+    r = rhs_nn(r, rb, bs);
+    partial = rhs_nn(partial, rb, bs);
     __shared__ cplx sh[4];
     int ix, iz;
     if (NDIM == 2) {
@@ -339,7 +375,12 @@ __device__ __forceinline__ double block_sum_partials(const cplx* partial, int nb
 // finished; otherwise reset the least-squares state and open the cycle.
 __global__ void __launch_bounds__(256) k_cycle_start(SolveState* st, const cplx* __restrict__ partial,
                                                      int nb, cplx* __restrict__ g,
-                                                     HostRecord* rec) {
+                                                     HostRecord* rec, int64_t bs) {
+    const int rb = blockIdx.x;
+    st = rhs_nn(st, rb, bs);
+    partial = rhs_nn(partial, rb, bs);
+    g = rhs_nn(g, rb, bs);
+    rec += rb;
     if (st->done) return;
     __shared__ double sh[4];
     const double beta = sqrt(block_sum_partials(partial, nb, sh));
@@ -378,7 +419,7 @@ __global__ void __launch_bounds__(256) k_givens_step(GivensArgs a) {
     __shared__ cplx scol[kMaxColumns + 2];
     __shared__ double scs[kMaxColumns];
     __shared__ cplx ssn[kMaxColumns];
-    givens_body(a, scol, scs, ssn);
+    givens_body(a, blockIdx.x, scol, scs, ssn);
 }
 
 // y = R^{-1} g (k = st->k columns), then u += Z y; one block of 256 threads
@@ -386,7 +427,12 @@ __global__ void __launch_bounds__(256) k_givens_step(GivensArgs a) {
 __global__ void __launch_bounds__(256) k_backsub_pred(const SolveState* st,
                                                       const cplx* __restrict__ R,
                                                       const cplx* __restrict__ g,
-                                                      cplx* __restrict__ y) {
+                                                      cplx* __restrict__ y, int64_t bs) {
+    const int rb = blockIdx.x;
+    st = rhs_nn(st, rb, bs);
+    R = rhs_nn(R, rb, bs);
+    g = rhs_nn(g, rb, bs);
+    y = rhs_nn(y, rb, bs);
     const int k = st->k;
     if (k == 0) return;
     const int ld = st->m + 1;
@@ -407,7 +453,13 @@ template <class ZC>
 __global__ void __launch_bounds__(256) k_update_pred(const SolveState* st,
                                                      const ZC* __restrict__ Z, int64_t n,
                                                      const cplx* __restrict__ y,
-                                                     cplx* __restrict__ x) {
+                                                     cplx* __restrict__ x, int64_t bs,
+                                                     int64_t fs) {
+    const int rb = blockIdx.y;
+    st = rhs_nn(st, rb, bs);
+    Z = rhs_nn(Z, rb, bs);
+    y = rhs_nn(y, rb, bs);
+    x += rb * fs;
     const int k = st->k;
     if (k == 0) return;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -426,15 +478,20 @@ __global__ void __launch_bounds__(256) k_update_pred(const SolveState* st,
 }
 
 // after the update of a cycle: mark k = 0 so a repeated end-of-cycle is a no-op
-__global__ void k_cycle_end(SolveState* st) {
-    if (threadIdx.x == 0) st->k = 0;
+__global__ void k_cycle_end(SolveState* st, int64_t bs) {
+    if (threadIdx.x == 0) rhs_at(st, (int)blockIdx.x, bs)->k = 0;
 }
 
 // v_j = s * w (normalisation, used when no preconditioner reads w first)
 __global__ void __launch_bounds__(256) k_normalize_pred(const cplx* __restrict__ w,
                                                         const SolveState* st,
-                                                        cplx* __restrict__ v, int64_t n) {
+                                                        cplx* __restrict__ v, int64_t n,
+                                                        int64_t bs) {
+    const int rb = blockIdx.y;
+    st = rhs_nn(st, rb, bs);
     if (st->active == 0) return;
+    w = rhs_nn(w, rb, bs);
+    v = rhs_nn(v, rb, bs);
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     v[p] = cscale(w[p], st->scale);
@@ -443,7 +500,13 @@ __global__ void __launch_bounds__(256) k_normalize_pred(const cplx* __restrict__
 // solve prologue: beta0 = ||b|| from partials; sets done when b == 0 or not finite
 __global__ void __launch_bounds__(256) k_solve_init(SolveState* st, const cplx* __restrict__ partial,
                                                     int nb, int m, int max_iters, double tol,
-                                                    HostRecord* rec, double* hist) {
+                                                    HostRecord* rec, double* hist, int64_t bs,
+                                                    int64_t hist_stride) {
+    const int rb = blockIdx.x;
+    st = rhs_nn(st, rb, bs);
+    partial = rhs_nn(partial, rb, bs);
+    rec += rb;
+    hist += (int64_t)rb * hist_stride;
     __shared__ double sh[4];
     const double b2 = block_sum_partials(partial, nb, sh);
     if (threadIdx.x != 0) return;
@@ -480,9 +543,10 @@ inline unsigned eblocks(int64_t n) { return (unsigned)((n + EB - 1) / EB); }
 
 }  // namespace
 
-hipError_t launch_weight_rhs(const FineOp& op, const cplx* f, cplx* b, hipStream_t s) {
+hipError_t launch_weight_rhs(const FineOp& op, const cplx* f, cplx* b, hipStream_t s,
+                             const Batch& bt) {
     const int64_t n = (int64_t)op.nz * op.nx;
-    HH_LAUNCH(k_weight_rhs, dim3(eblocks(n)), dim3(EB), 0, s, op, f, b);
+    HH_LAUNCH(k_weight_rhs, dim3(eblocks(n), bt.n), dim3(EB), 0, s, op, f, b, bt.bs, bt.fs);
     return hipGetLastError();
 }
 
@@ -496,38 +560,38 @@ hipError_t launch_check_slowness(const double* m, int64_t n, double* m2, int* fl
 template <int NDIM, class ZC>
 static void apply_dot_dispatch(dim3 g, dim3 b, const FineOp& op, const ZC* z, cplx* w,
                                const cplx* V, int k, cplx* partial, const int* active,
-                               hipStream_t s) {
+                               int64_t bs, hipStream_t s) {
     if (k <= 8)
-        HH_LAUNCH((k_apply_dot<NDIM, 8, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
+        HH_LAUNCH((k_apply_dot<NDIM, 8, ZC>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
     else if (k <= 16)
-        HH_LAUNCH((k_apply_dot<NDIM, 16, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
+        HH_LAUNCH((k_apply_dot<NDIM, 16, ZC>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
     else if (k <= 32)
-        HH_LAUNCH((k_apply_dot<NDIM, 32, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
+        HH_LAUNCH((k_apply_dot<NDIM, 32, ZC>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
     else if (k <= 48)
-        HH_LAUNCH((k_apply_dot<NDIM, 48, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
+        HH_LAUNCH((k_apply_dot<NDIM, 48, ZC>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
     else
-        HH_LAUNCH((k_apply_dot<NDIM, 0, ZC>), g, b, 0, s, op, z, w, V, k, partial, active);
+        HH_LAUNCH((k_apply_dot<NDIM, 0, ZC>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
 }
 
 template <class ZC>
 hipError_t apply_dot(const FineOp& op, const ZC* z, cplx* w, const cplx* V, int k, cplx* partial,
-                     const int* active, hipStream_t s) {
+                     const int* active, hipStream_t s, const Batch& bt) {
     if (op.ndim == 2)
-        apply_dot_dispatch<2>(dim3((op.nx + 63) / 64, (op.nz + 3) / 4), dim3(64, 4), op, z, w, V,
-                              k, partial, active, s);
+        apply_dot_dispatch<2>(dim3((op.nx + 63) / 64, (op.nz + 3) / 4, bt.n), dim3(64, 4), op, z,
+                              w, V, k, partial, active, bt.bs, s);
     else
-        apply_dot_dispatch<1>(dim3((op.nx + 255) / 256), dim3(256), op, z, w, V, k, partial,
-                              active, s);
+        apply_dot_dispatch<1>(dim3((op.nx + 255) / 256, 1, bt.n), dim3(256), op, z, w, V, k,
+                              partial, active, bt.bs, s);
     return hipGetLastError();
 }
 
 hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx* V, int k,
-                            cplx* partial, const int* active, hipStream_t s) {
-    return apply_dot(op, z, w, V, k, partial, active, s);
+                            cplx* partial, const int* active, hipStream_t s, const Batch& bt) {
+    return apply_dot(op, z, w, V, k, partial, active, s, bt);
 }
 hipError_t launch_apply_dot(const FineOp& op, const cplxf* z, cplx* w, const cplx* V, int k,
-                            cplx* partial, const int* active, hipStream_t s) {
-    return apply_dot(op, z, w, V, k, partial, active, s);
+                            cplx* partial, const int* active, hipStream_t s, const Batch& bt) {
+    return apply_dot(op, z, w, V, k, partial, active, s, bt);
 }
 
 int apply_blocks(const FineOp& op) {
@@ -536,70 +600,87 @@ int apply_blocks(const FineOp& op) {
 int node_blocks(int64_t n) { return (int)((n + 255) / 256); }
 int norm_blocks(int64_t n) { return node_blocks(n) < kNormBlocks ? node_blocks(n) : kNormBlocks; }
 hipError_t launch_dot_blocks(const cplx* V, int64_t n, int k, const cplx* w, cplx* partial,
-                             hipStream_t s) {
-    HH_LAUNCH(k_dot_blocks, dim3(node_blocks(n)), dim3(256), 0, s, V, n, k, w, partial);
+                             hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_dot_blocks, dim3(node_blocks(n), bt.n), dim3(256), 0, s, V, n, k, w, partial,
+              bt.bs);
     return hipGetLastError();
 }
 hipError_t launch_axpy_dot(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
-                           const int* active, hipStream_t s) {
-    const dim3 g(node_blocks(n)), b(256);
+                           const int* active, hipStream_t s, const Batch& bt) {
+    const dim3 g(node_blocks(n), bt.n), b(256);
+    const int64_t bs = bt.bs;
     if (k <= 8)
-        HH_LAUNCH(k_axpy_dot<8>, g, b, 0, s, V, n, k, h, w, partial, active);
+        HH_LAUNCH(k_axpy_dot<8>, g, b, 0, s, V, n, k, h, w, partial, active, bs);
     else if (k <= 16)
-        HH_LAUNCH(k_axpy_dot<16>, g, b, 0, s, V, n, k, h, w, partial, active);
+        HH_LAUNCH(k_axpy_dot<16>, g, b, 0, s, V, n, k, h, w, partial, active, bs);
     else if (k <= 32)
-        HH_LAUNCH(k_axpy_dot<32>, g, b, 0, s, V, n, k, h, w, partial, active);
+        HH_LAUNCH(k_axpy_dot<32>, g, b, 0, s, V, n, k, h, w, partial, active, bs);
     else if (k <= 48)
-        HH_LAUNCH(k_axpy_dot<48>, g, b, 0, s, V, n, k, h, w, partial, active);
+        HH_LAUNCH(k_axpy_dot<48>, g, b, 0, s, V, n, k, h, w, partial, active, bs);
     else
-        HH_LAUNCH(k_axpy_dot<0>, g, b, 0, s, V, n, k, h, w, partial, active);
+        HH_LAUNCH(k_axpy_dot<0>, g, b, 0, s, V, n, k, h, w, partial, active, bs);
     return hipGetLastError();
 }
 hipError_t launch_axpy_norm(const cplx* V, int64_t n, int k, const cplx* h, cplx* w, cplx* partial,
-                            const int* active, hipStream_t s) {
-    HH_LAUNCH(k_axpy_norm, dim3(norm_blocks(n)), dim3(256), 0, s, V, n, k, h, w, partial,
-                       active);
+                            const int* active, hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_axpy_norm, dim3(norm_blocks(n), bt.n), dim3(256), 0, s, V, n, k, h, w, partial,
+              active, bt.bs);
     return hipGetLastError();
 }
 hipError_t launch_reduce_pred(const cplx* partial, int nb, int k, cplx* out, const int* active,
-                              hipStream_t s) {
-    HH_LAUNCH(k_reduce_pred, dim3(k), dim3(64), 0, s, partial, nb, out, active);
+                              hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_reduce_pred, dim3(k, bt.n), dim3(64), 0, s, partial, nb, out, active, bt.bs);
     return hipGetLastError();
 }
 hipError_t launch_residual_norm(const FineOp& op, const cplx* b, const cplx* u, cplx* r,
-                                cplx* partial, const int* done, hipStream_t s) {
+                                cplx* partial, const int* done, hipStream_t s, const Batch& bt) {
     if (op.ndim == 2)
-        HH_LAUNCH(k_residual_norm<2>, dim3((op.nx + 63) / 64, (op.nz + 3) / 4), dim3(64, 4),
-                           0, s, op, b, u, r, partial, done);
+        HH_LAUNCH(k_residual_norm<2>, dim3((op.nx + 63) / 64, (op.nz + 3) / 4, bt.n),
+                  dim3(64, 4), 0, s, op, b, u, r, partial, done, bt.bs, bt.fs);
     else
-        HH_LAUNCH(k_residual_norm<1>, dim3((op.nx + 255) / 256), dim3(256), 0, s, op, b, u,
-                           r, partial, done);
+        HH_LAUNCH(k_residual_norm<1>, dim3((op.nx + 255) / 256, 1, bt.n), dim3(256), 0, s, op,
+                  b, u, r, partial, done, bt.bs, bt.fs);
     return hipGetLastError();
 }
 hipError_t launch_cycle_start(SolveState* st, const cplx* partial, int nb, cplx* g,
-                              HostRecord* rec, hipStream_t s) {
-    HH_LAUNCH(k_cycle_start, dim3(1), dim3(256), 0, s, st, partial, nb, g, rec);
+                              HostRecord* rec, hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_cycle_start, dim3(bt.n), dim3(256), 0, s, st, partial, nb, g, rec, bt.bs);
     return hipGetLastError();
 }
-hipError_t launch_givens_step(const GivensArgs& a, hipStream_t s) {
-    HH_LAUNCH(k_givens_step, dim3(1), dim3(256), 0, s, a);
+hipError_t launch_givens_step(const GivensArgs& a, hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_givens_step, dim3(bt.n), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 template <class ZC>
 hipError_t cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y, const ZC* Z,
-                        int64_t n, cplx* x, hipStream_t s) {
-    HH_LAUNCH(k_backsub_pred, dim3(1), dim3(256), 0, s, st, R, g, y);
-    HH_LAUNCH(k_update_pred<ZC>, dim3(node_blocks(n)), dim3(256), 0, s, st, Z, n, y, x);
-    HH_LAUNCH(k_cycle_end, dim3(1), dim3(64), 0, s, st);
+                        int64_t n, cplx* x, hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_backsub_pred, dim3(bt.n), dim3(256), 0, s, st, R, g, y, bt.bs);
+    HH_LAUNCH(k_update_pred<ZC>, dim3(node_blocks(n), bt.n), dim3(256), 0, s, st, Z, n, y, x,
+              bt.bs, bt.fs);
+    HH_LAUNCH(k_cycle_end, dim3(bt.n), dim3(64), 0, s, st, bt.bs);
     return hipGetLastError();
 }
 hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
-                               const cplx* Z, int64_t n, cplx* x, hipStream_t s) {
-    return cycle_finish(st, R, g, y, Z, n, x, s);
+                               const cplx* Z, int64_t n, cplx* x, hipStream_t s,
+                               const Batch& bt) {
+    return cycle_finish(st, R, g, y, Z, n, x, s, bt);
 }
 hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
-                               const cplxf* Z, int64_t n, cplx* x, hipStream_t s) {
-    return cycle_finish(st, R, g, y, Z, n, x, s);
+                               const cplxf* Z, int64_t n, cplx* x, hipStream_t s,
+                               const Batch& bt) {
+    return cycle_finish(st, R, g, y, Z, n, x, s, bt);
+}
+hipError_t launch_normalize_pred(const cplx* w, const SolveState* st, cplx* v, int64_t n,
+                                 hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_normalize_pred, dim3(node_blocks(n), bt.n), dim3(256), 0, s, w, st, v, n, bt.bs);
+    return hipGetLastError();
+}
+hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
+                             double tol, HostRecord* rec, double* hist, int64_t hist_stride,
+                             hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_solve_init, dim3(bt.n), dim3(256), 0, s, st, partial, nb, m, max_iters, tol,
+              rec, hist, bt.bs, hist_stride);
+    return hipGetLastError();
 }
 
 namespace {
@@ -623,16 +704,4 @@ hipError_t launch_to_c64(const cplx* a, cplxf* b, int64_t n, hipStream_t s) {
     HH_LAUNCH(k_to_c64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a, b, n);
     return hipGetLastError();
 }
-hipError_t launch_normalize_pred(const cplx* w, const SolveState* st, cplx* v, int64_t n,
-                                 hipStream_t s) {
-    HH_LAUNCH(k_normalize_pred, dim3(node_blocks(n)), dim3(256), 0, s, w, st, v, n);
-    return hipGetLastError();
-}
-hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
-                             double tol, HostRecord* rec, double* hist, hipStream_t s) {
-    HH_LAUNCH(k_solve_init, dim3(1), dim3(256), 0, s, st, partial, nb, m, max_iters, tol,
-                       rec, hist);
-    return hipGetLastError();
-}
-
 }  // namespace hh

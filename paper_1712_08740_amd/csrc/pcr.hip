@@ -27,9 +27,15 @@ __global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOpT<T> op, const cplx* 
                                                      const double* __restrict__ scale,
                                                      cplx* __restrict__ vout,
                                                      typename Cx<T>::type* __restrict__ x_out,
-                                                     const int* __restrict__ active) {
+                                                     const int* __restrict__ active, int64_t bs) {
     typedef typename Cx<T>::type C;
+    const int rb = blockIdx.x;                 // right-hand side
+    active = rhs_at(active, rb, bs);
     if (active && *active == 0) return;
+    src = rhs_nn(src, rb, bs);
+    scale = rhs_at(scale, rb, bs);
+    vout = rhs_at(vout, rb, bs);
+    x_out = rhs_nn(x_out, rb, bs);
     __shared__ C sa[PCR_MAXN], sb[PCR_MAXN], sc[PCR_MAXN], sd[PCR_MAXN];
     const int n = op.nx;
     const int i = threadIdx.x;
@@ -81,9 +87,10 @@ __global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOpT<T> op, const cplx* 
 
 template <class T>
 hipError_t pcr(const FineOpT<T>& op, const cplx* src, const double* scale, cplx* vout,
-               typename Cx<T>::type* x, const int* active, hipStream_t s) {
+               typename Cx<T>::type* x, const int* active, hipStream_t s, const Batch& bt) {
     if (op.ndim != 1 || op.nx > PCR_MAXN) return hipErrorInvalidValue;
-    HH_LAUNCH((k_pcr<T>), dim3(1), dim3(PCR_THREADS), 0, s, op, src, scale, vout, x, active);
+    HH_LAUNCH((k_pcr<T>), dim3(bt.n), dim3(PCR_THREADS), 0, s, op, src, scale, vout, x, active,
+              bt.bs);
     return hipGetLastError();
 }
 
@@ -94,12 +101,13 @@ hipError_t launch_pcr_solve(const FineOp& op, const cplx* d, cplx* x, hipStream_
 }
 
 hipError_t launch_pcr_norm(const FineOp& op, const cplx* src, const double* scale, cplx* vout,
-                           cplx* x, const int* active, hipStream_t s) {
-    return pcr(op, src, scale, vout, x, active, s);
+                           cplx* x, const int* active, hipStream_t s, const Batch& bt) {
+    return pcr(op, src, scale, vout, x, active, s, bt);
 }
 hipError_t launch_pcr_norm(const FineOpT<float>& op, const cplx* src, const double* scale,
-                           cplx* vout, cplxf* x, const int* active, hipStream_t s) {
-    return pcr(op, src, scale, vout, x, active, s);
+                           cplx* vout, cplxf* x, const int* active, hipStream_t s,
+                           const Batch& bt) {
+    return pcr(op, src, scale, vout, x, active, s, bt);
 }
 
 }  // namespace hh

@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
                                              int hz, int hx, int nzc, int nxc,
                                              typename OP::C* __restrict__ bc, double rscale,
                                              const int* __restrict__ active, int ntx, int ntiles,
-                                             GivensArgs giv) {
+                                             GivensArgs giv, int64_t bs) {
     typedef typename OP::C C;
     typedef typename OP::real T;
     constexpr int W1X = 2 * TCX + 5, W1Z = 2 * TCZ + 5;   // largest x1 region
@@ -154,12 +154,20 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
     __shared__ C s2[W1X * W1Z];
     __shared__ typename OP::Row srow[W1X * W1Z];           // rows of the x1 region
     __shared__ double s_scale;
+    const int rb = blockIdx.y;                             // right-hand side
     if ((int)blockIdx.x == ntiles) {                       // the hosted Givens step
-        givens_body(giv, reinterpret_cast<cplx*>(sb), reinterpret_cast<double*>(sw),
+        givens_body(giv, rb, reinterpret_cast<cplx*>(sb), reinterpret_cast<double*>(sw),
                     reinterpret_cast<cplx*>(s1));
         return;
     }
+    active = rhs_at(active, rb, bs);
     if (inactive(active)) return;
+    src = rhs_nn(src, rb, bs);
+    scale = rhs_at(scale, rb, bs);
+    npart = rhs_at(npart, rb, bs);
+    bout = rhs_at(bout, rb, bs);
+    x2out = rhs_nn(x2out, rb, bs);
+    bc = rhs_nn(bc, rb, bs);
     const int tile = xcd_tile(blockIdx.x, ntiles);
     const int nz = A.nz(), nx = A.nx();
     const int cx0 = (tile % ntx) * TCX, cz0 = (tile / ntx) * TCZ;
@@ -283,10 +291,17 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
                                            const typename OP::C* __restrict__ x2,
                                            const typename OP::C* __restrict__ e, int nxc,
                                            typename OP::C* __restrict__ out,
-                                           const int* __restrict__ active, int ntx, int ntiles) {
+                                           const int* __restrict__ active, int ntx, int ntiles,
+                                           int64_t bs) {
     typedef typename OP::C C;
     typedef typename OP::real T;
+    const int rb = blockIdx.y;                             // right-hand side
+    active = rhs_at(active, rb, bs);
     if (inactive(active)) return;
+    b = rhs_nn(b, rb, bs);
+    x2 = rhs_nn(x2, rb, bs);
+    e = rhs_nn(e, rb, bs);
+    out = rhs_nn(out, rb, bs);
     constexpr int WX = TX + 4, WZ = TZ + 4;
     constexpr int W3X = TX + 2, W3Z = TZ + 2;
     __shared__ C sp[WX * WZ];                         // x' (tile + 2)
@@ -395,12 +410,12 @@ template <class OP, class SC, int TCX, int TCZ>
 hipError_t down_launch(const OP& A, const SC* src, const double* scale, const cplx* npart,
                        int nbn, SC* bout, typename OP::C* x2, int hz, int hx, int nzc, int nxc,
                        typename OP::C* bc, const int* active, const GivensArgs& giv,
-                       hipStream_t s) {
+                       hipStream_t s, const Batch& bt) {
     const int ntx = (nxc + TCX - 1) / TCX, ntz = (nzc + TCZ - 1) / TCZ;
     const int ntiles = ntx * ntz;
-    const dim3 g(ntiles + (giv.st ? 1 : 0));
+    const dim3 g(ntiles + (giv.st ? 1 : 0), bt.n);
     HH_LAUNCH((k_down<OP, SC, TCX, TCZ>), g, dim3(NT), 0, s, A, src, scale, npart, nbn, bout, x2,
-              hz, hx, nzc, nxc, bc, inv2dc(hz, hx), active, ntx, ntiles, giv);
+              hz, hx, nzc, nxc, bc, inv2dc(hz, hx), active, ntx, ntiles, giv, bt.bs);
     return hipGetLastError();
 }
 
@@ -410,12 +425,12 @@ template <class OP, class SC>
 hipError_t down_dispatch(const OP& A, const SC* src, const double* scale, const cplx* npart,
                          int nbn, SC* bout, typename OP::C* x2, int hz, int hx, int nzc, int nxc,
                          typename OP::C* bc, const int* active, const GivensArgs& giv,
-                         hipStream_t s) {
+                         hipStream_t s, const Batch& bt) {
     if (big_tiles(A))
         return down_launch<OP, SC, 16, 4>(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc,
-                                          bc, active, giv, s);
+                                          bc, active, giv, s, bt);
     return down_launch<OP, SC, 8, 4>(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
-                                     active, giv, s);
+                                     active, giv, s, bt);
 }
 
 template <class OP>
@@ -428,19 +443,20 @@ int down_givens_capacity(const OP& A) {
 template <class OP, class SB, int TX, int TZ>
 hipError_t up_launch(const OP& A, int hz, int hx, const SB* b, const typename OP::C* x2,
                      const typename OP::C* e, int nxc, typename OP::C* out, const int* active,
-                     hipStream_t s) {
+                     hipStream_t s, const Batch& bt) {
     const int ntx = (A.nx() + TX - 1) / TX, ntz = (A.nz() + TZ - 1) / TZ;
-    HH_LAUNCH((k_up<OP, SB, TX, TZ>), dim3(ntx * ntz), dim3(NT), 0, s, A, hz, hx, b, x2, e, nxc,
-              out, active, ntx, ntx * ntz);
+    HH_LAUNCH((k_up<OP, SB, TX, TZ>), dim3(ntx * ntz, bt.n), dim3(NT), 0, s, A, hz, hx, b, x2, e,
+              nxc, out, active, ntx, ntx * ntz, bt.bs);
     return hipGetLastError();
 }
 
 template <class OP, class SB>
 hipError_t up_dispatch(const OP& A, int hz, int hx, const SB* b, const typename OP::C* x2,
                        const typename OP::C* e, int nxc, typename OP::C* out, const int* active,
-                       hipStream_t s) {
-    if (big_tiles(A)) return up_launch<OP, SB, 32, 8>(A, hz, hx, b, x2, e, nxc, out, active, s);
-    return up_launch<OP, SB, 16, 4>(A, hz, hx, b, x2, e, nxc, out, active, s);
+                       hipStream_t s, const Batch& bt) {
+    if (big_tiles(A))
+        return up_launch<OP, SB, 32, 8>(A, hz, hx, b, x2, e, nxc, out, active, s, bt);
+    return up_launch<OP, SB, 16, 4>(A, hz, hx, b, x2, e, nxc, out, active, s, bt);
 }
 
 template <class T>
@@ -461,18 +477,18 @@ Coarse9<T> coarse9(const CoarseOpT<T>& op) {
 hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, const double* scale,
                                const cplx* npart, int nbn, cplx* bout, cplx* x2, int hz, int hx,
                                int nzc, int nxc, cplx* bc, const int* active,
-                               const GivensArgs* giv, hipStream_t s) {
+                               const GivensArgs* giv, hipStream_t s, const Batch& bt) {
     const GivensArgs none{};
     return down_dispatch(fine5(op), src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
-                         active, giv ? *giv : none, s);
+                         active, giv ? *giv : none, s, bt);
 }
 hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, const double* scale,
                                const cplx* npart, int nbn, cplx* bout, cplxf* x2, int hz, int hx,
                                int nzc, int nxc, cplxf* bc, const int* active,
-                               const GivensArgs* giv, hipStream_t s) {
+                               const GivensArgs* giv, hipStream_t s, const Batch& bt) {
     const GivensArgs none{};
     return down_dispatch(fine5(op), src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
-                         active, giv ? *giv : none, s);
+                         active, giv ? *giv : none, s, bt);
 }
 
 int vc_fine_down_givens_capacity(const FineOp& op) { return down_givens_capacity(fine5(op)); }
@@ -481,36 +497,38 @@ int vc_fine_down_givens_capacity(const FineOpT<float>& op) {
 }
 
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz, int hx,
-                                 int nzc, int nxc, cplx* bc, const int* active, hipStream_t s) {
+                                 int nzc, int nxc, cplx* bc, const int* active, hipStream_t s,
+                                 const Batch& bt) {
     return down_dispatch(coarse9(op), b, nullptr, nullptr, 0, (cplx*)nullptr, x2, hz, hx, nzc,
-                         nxc, bc, active, GivensArgs{}, s);
+                         nxc, bc, active, GivensArgs{}, s, bt);
 }
 hipError_t launch_vc_coarse_down(const CoarseOpT<float>& op, const cplxf* b, cplxf* x2, int hz,
                                  int hx, int nzc, int nxc, cplxf* bc, const int* active,
-                                 hipStream_t s) {
+                                 hipStream_t s, const Batch& bt) {
     return down_dispatch(coarse9(op), b, nullptr, nullptr, 0, (cplxf*)nullptr, x2, hz, hx, nzc,
-                         nxc, bc, active, GivensArgs{}, s);
+                         nxc, bc, active, GivensArgs{}, s, bt);
 }
 
 hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b, const cplx* x2,
-                             const cplx* e, int nxc, cplx* out, const int* active, hipStream_t s) {
-    return up_dispatch(fine5(op), hz, hx, b, x2, e, nxc, out, active, s);
+                             const cplx* e, int nxc, cplx* out, const int* active, hipStream_t s,
+                             const Batch& bt) {
+    return up_dispatch(fine5(op), hz, hx, b, x2, e, nxc, out, active, s, bt);
 }
 hipError_t launch_vc_fine_up(const FineOpT<float>& op, int hz, int hx, const cplx* b,
                              const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
-                             const int* active, hipStream_t s) {
-    return up_dispatch(fine5(op), hz, hx, b, x2, e, nxc, out, active, s);
+                             const int* active, hipStream_t s, const Batch& bt) {
+    return up_dispatch(fine5(op), hz, hx, b, x2, e, nxc, out, active, s, bt);
 }
 
 hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b, const cplx* x2,
                                const cplx* e, int nxc, cplx* out, const int* active,
-                               hipStream_t s) {
-    return up_dispatch(coarse9(op), hz, hx, b, x2, e, nxc, out, active, s);
+                               hipStream_t s, const Batch& bt) {
+    return up_dispatch(coarse9(op), hz, hx, b, x2, e, nxc, out, active, s, bt);
 }
 hipError_t launch_vc_coarse_up(const CoarseOpT<float>& op, int hz, int hx, const cplxf* b,
                                const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
-                               const int* active, hipStream_t s) {
-    return up_dispatch(coarse9(op), hz, hx, b, x2, e, nxc, out, active, s);
+                               const int* active, hipStream_t s, const Batch& bt) {
+    return up_dispatch(coarse9(op), hz, hx, b, x2, e, nxc, out, active, s, bt);
 }
 
 namespace {

@@ -30,6 +30,7 @@ HH_NO_PRECOND = 1
 HH_PRECOND_F32 = 2
 HH_MAX_COARSE = 4096
 HH_MAX_1D = 1024
+HH_MAX_BATCH = 1024
 HH_KERNEL_NONE = 0
 HH_KERNEL_APPLY_DOT = 1
 HH_KERNEL_AXPY_DOT = 2
@@ -49,7 +50,7 @@ EXPORTED = [
     "hh_level_info", "hh_apply_operator", "hh_apply_level_operator", "hh_apply_precond",
     "hh_apply_precond_f32",
     "hh_orthogonalize_scratch_bytes", "hh_orthogonalize", "hh_kernel_timer_start",
-    "hh_kernel_timer_read",
+    "hh_kernel_timer_read", "hh_workspace_bytes_batch", "hh_solve_batch",
 ]
 
 KERNEL_IDS = {"none": HH_KERNEL_NONE, "apply_dot": HH_KERNEL_APPLY_DOT,
@@ -95,6 +96,11 @@ def _load():
                                             ctypes.c_size_t, _c_double_p, _c_double_p, _vp]),
         "hh_kernel_timer_start": (ctypes.c_int, [_vp, ctypes.c_int]),
         "hh_kernel_timer_read": (ctypes.c_int, [_vp, _c_i64_p, _c_double_p, _c_double_p]),
+        "hh_workspace_bytes_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _c_size_p]),
+        "hh_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_uint, _vp, ctypes.c_size_t,
+                                          _vp, _c_int_p, _c_double_p, _c_int_p, _c_double_p,
+                                          ctypes.c_int, _vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -135,6 +141,16 @@ def _dev_tensor(t: torch.Tensor, dtype, shape, name: str) -> torch.Tensor:
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t
+
+
+@dataclasses.dataclass
+class BatchResult:
+    u: torch.Tensor                  # (nrhs, *shape) complex128
+    iterations: np.ndarray           # (nrhs,)
+    true_rel_res: np.ndarray         # (nrhs,)
+    status: np.ndarray               # (nrhs,) per-source status
+    history: Optional[np.ndarray]    # (nrhs, hist_cap) or None
+    overall: int
 
 
 @dataclasses.dataclass
@@ -208,6 +224,46 @@ class Problem:
             ws = torch.empty(self.workspace_bytes(restart), dtype=torch.uint8, device=self.device)
             self._ws[restart] = ws
         return ws
+
+    def workspace_bytes_batch(self, restart: int, nrhs: int) -> int:
+        n = ctypes.c_size_t()
+        _check(_lib.hh_workspace_bytes_batch(self._handle, int(restart), int(nrhs),
+                                             ctypes.byref(n)), "hh_workspace_bytes_batch")
+        return n.value
+
+    def solve_batch(self, F: torch.Tensor, tol: float = 1e-6, restart: int = 30,
+                    max_iters: int = 2000, no_precond: bool = False, precond_f32: bool = False,
+                    U: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                    stream=None, hist_cap: int = 0) -> BatchResult:
+        """``hh_solve_batch``: F is (nrhs, *shape) complex128, one source per row."""
+        if F.dim() != len(self.shape) + 1:
+            raise ValueError(f"F must have shape (nrhs, {self.shape})")
+        nrhs = F.shape[0]
+        _dev_tensor(F, torch.complex128, (nrhs,) + tuple(self.shape), "F")
+        if U is None:
+            U = torch.empty_like(F)
+        else:
+            _dev_tensor(U, torch.complex128, (nrhs,) + tuple(self.shape), "U")
+        need = self.workspace_bytes_batch(restart, nrhs)
+        ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8,
+                                                                 device=self.device)
+        if ws.numel() * ws.element_size() < need:
+            raise ValueError(f"workspace needs {need} bytes")
+        its = (ctypes.c_int * nrhs)()
+        rel = (ctypes.c_double * nrhs)()
+        sts = (ctypes.c_int * nrhs)()
+        hist = np.zeros((nrhs, max(hist_cap, 1)), dtype=np.float64)
+        flags = (HH_NO_PRECOND if no_precond else 0) | (HH_PRECOND_F32 if precond_f32 else 0)
+        st = _check(_lib.hh_solve_batch(self._handle, nrhs, _vp(F.data_ptr()), float(tol),
+                                        int(restart), int(max_iters), flags, _vp(ws.data_ptr()),
+                                        ws.numel() * ws.element_size(), _vp(U.data_ptr()), its,
+                                        rel, sts,
+                                        hist.ctypes.data_as(_c_double_p) if hist_cap else None,
+                                        int(hist_cap), _vp(_stream_ptr(stream))),
+                    "hh_solve_batch")
+        return BatchResult(u=U, iterations=np.array(its[:]), true_rel_res=np.array(rel[:]),
+                           status=np.array(sts[:]), history=hist if hist_cap else None,
+                           overall=st)
 
     @property
     def num_levels(self) -> int:

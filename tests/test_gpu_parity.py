@@ -452,3 +452,121 @@ def test_f32_flag_validation(hh):
         P.solve(_t(w.source), tol=1e-6, restart=5, no_precond=True, precond_f32=True)
     r = P.solve(_t(w.source), tol=w.tol, restart=w.restart, precond_f32=True)
     assert r.status == 0 and r.true_rel_res <= w.tol
+
+
+# ---------------------------------------------------------------------------
+# several sources of one problem solved together (hh_solve_batch)
+# ---------------------------------------------------------------------------
+def _batch_sources(shape, positions):
+    F = np.zeros((len(positions),) + tuple(shape), dtype=np.complex128)
+    for i, pos in enumerate(positions):
+        if pos is not None:
+            F[(i,) + tuple(pos)] = 1.0
+    return F
+
+
+def _assert_batch_equals_single(P, F, **kw):
+    """Every source of a batch gives the bits of its solve alone."""
+    res = P.solve_batch(_t(F), **kw)
+    for i in range(F.shape[0]):
+        one = P.solve(_t(F[i]), **kw)
+        assert res.iterations[i] == one.iterations, i
+        assert res.true_rel_res[i] == one.true_rel_res, i
+        assert np.array_equal(_np(res.u[i]), _np(one.u)), i
+    return res
+
+
+def test_batch_equals_single_solves_401x201(hh):
+    """Sources at different depths converge after different iteration counts
+    (some restart, some do not); a zero source is done at once."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    F = _batch_sources(w.shape, [(5, 200), (100, 37), None, (200, 400), (0, 0)])
+    res = _assert_batch_equals_single(P, F, tol=w.tol, restart=w.restart)
+    assert res.overall == 0 and np.all(res.status == 0)
+    assert res.iterations[2] == 0
+    assert len(set(res.iterations.tolist())) >= 3
+    # one of them against the oracle
+    ref = solver.solve(w.slowness, w.omega, w.alpha, w.h, F[1], beta=w.beta, tol=w.tol,
+                       restart=w.restart)
+    assert abs(res.iterations[1] - ref.iterations) <= 1
+    assert np.linalg.norm(_np(res.u[1]) - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+@pytest.mark.parametrize("kw", [dict(restart=7, tol=1e-8), dict(restart=12, tol=1e-7,
+                                                               precond_f32=True),
+                                dict(restart=20, tol=1e-6, no_precond=True, max_iters=400)],
+                         ids=["f64_restarts", "f32", "no_precond"])
+def test_batch_equals_single_small_grid(hh, kw):
+    shape, h, freq = (33, 65), 10.0, 6.0
+    m = _model(shape, h, seed=3)
+    P = _problem(hh, m, 2 * np.pi * freq, 0.01, h)
+    F = _batch_sources(shape, [(3, 10), (16, 32), (32, 64), (1, 1), (20, 5), (7, 50), (30, 3),
+                               (12, 12), (25, 60)])
+    res = _assert_batch_equals_single(P, F, **kw)
+    H = op.helmholtz(m, 2 * np.pi * freq, 0.01, h)
+    for i in range(F.shape[0]):
+        b = op.weighted_rhs(F[i]).ravel()
+        r = np.linalg.norm(b - H @ _np(res.u[i]).ravel()) / np.linalg.norm(b)
+        if res.status[i] == 0:
+            assert r <= kw["tol"] * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("shape", [(1001,), (3, 3)], ids=str)
+def test_batch_1d_and_single_level(hh, shape):
+    if len(shape) == 1:
+        w = wl.layered_1d_well()
+        m, omega, h = w.slowness, w.omega, w.h
+        pos = [(100,), (500,), (1000,), (0,)]
+    else:
+        m, omega, h = _model(shape, 10.0), 2 * np.pi * 10.0, 10.0
+        pos = [(0, 0), (1, 1), (2, 1)]
+    P = _problem(hh, m, omega, 0.01, h)
+    F = _batch_sources(shape, pos)
+    _assert_batch_equals_single(P, F, tol=1e-8, restart=10)
+    _assert_batch_equals_single(P, F, tol=1e-8, restart=10, precond_f32=True)
+
+
+def test_batch_801x301_32_sources_per_frequency(hh):
+    """The batching configuration at full size: 801 x 301, 32 top-row sources at
+    each of 5 / 7.5 / 10 / 12.5 Hz (one problem per frequency, 32 sources per
+    batch). Every source meets 1e-6 on the residual recomputed in FP64 by the
+    oracle's operator; two sources per frequency equal their solves alone."""
+    slow, sources, freqs = wl.grf_801x301_sources()
+    shape = slow.shape
+    F = _batch_sources(shape, [(iz, ix) for ix, iz in sources])
+    for fz in freqs:
+        omega = 2 * np.pi * fz
+        P = _problem(hh, slow, omega, 0.01, 10.0)
+        res = P.solve_batch(_t(F), tol=1e-6, restart=30, precond_f32=True)
+        print(f"801x301 {fz} Hz: iterations {res.iterations.min()}..{res.iterations.max()}")
+        assert res.overall == 0 and np.all(res.status == 0)
+        H = op.helmholtz(slow, omega, 0.01, 10.0)
+        U = _np(res.u)
+        for i in range(F.shape[0]):
+            b = op.weighted_rhs(F[i]).ravel()
+            assert np.linalg.norm(b - H @ U[i].ravel()) <= 1e-6 * (1 + 1e-6) * np.linalg.norm(b)
+        for i in (0, 17):
+            one = P.solve(_t(F[i]), tol=1e-6, restart=30, precond_f32=True)
+            assert one.iterations == res.iterations[i]
+            assert np.array_equal(_np(one.u), U[i])
+        del P, res
+        torch.cuda.empty_cache()
+
+
+def test_batch_argument_checks(hh):
+    w = wl.layered_1d_well()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    F = _t(np.zeros((2, 1001), complex))
+    with pytest.raises(ValueError):
+        P.solve_batch(_t(np.zeros((2, 1000), complex)))
+    with pytest.raises(hh.HHError):
+        P.solve_batch(F, tol=2.0)
+    with pytest.raises(hh.HHError):
+        P.solve_batch(F, restart=0)
+    small = torch.empty(16, dtype=torch.uint8, device=DEV)
+    with pytest.raises(ValueError):
+        P.solve_batch(F, workspace=small)
+    res = P.solve_batch(F, tol=1e-6, restart=5)
+    assert np.all(res.iterations == 0) and np.all(res.status == 0)
+    assert float(torch.abs(res.u).max()) == 0.0
