@@ -37,7 +37,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grf_401x201",
-                    choices=["grf_401x201", "layered_1d_well", "grf_1201x401"])
+                    choices=["grf_401x201", "layered_1d_well", "grf_1201x401",
+                             "grf_801x301_batch"],
+                    help="grf_801x301_batch: 32 top-row sources x 4 frequencies, one batched "
+                         "solve of 32 sources per frequency (a step = all 128 solves)")
+    ap.add_argument("--max-coarse", type=int, default=None,
+                    help="dense limit of the coarsest multigrid grid (default 4096; the batched "
+                         "workload uses 16384)")
     ap.add_argument("--precision", default="f64", choices=["f64", "mixed"],
                     help="mixed: the preconditioner in complex64 inside the FP64 FGMRES")
     ap.add_argument("--kernel", default="auto",
@@ -119,6 +125,153 @@ def cpu_baseline(w, budget_s: float, gpu_iterations: int):
                           f"NumPy/SciPy FP64, 1 thread"}
 
 
+def cpu_baseline_batch(slow, sources, freqs, budget_s: float, its_by_freq, max_coarse: int):
+    """The oracle on the batched workload: per frequency, two truncated solves
+    of one source (10 and 30 iterations) give the set-up and per-iteration
+    time; each of the 32 sources of that frequency is priced at the iteration
+    count the GPU took for it (set-up once per frequency: the oracle builds its
+    hierarchy per solve, so this favours the oracle)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import solver
+    total, parts = 0.0, []
+    with threadpool_limits(limits=1):
+        for fz, its in zip(freqs, its_by_freq):
+            f = np.zeros(slow.shape, complex)
+            f[sources[0][1], sources[0][0]] = 1.0
+            om = 2 * np.pi * fz
+
+            def run(maxiter):
+                t = time.perf_counter()
+                solver.solve(slow, om, 0.01, 10.0, f, tol=1e-6, restart=30, maxiter=maxiter,
+                             max_coarse=max_coarse)
+                return time.perf_counter() - t
+            t10, t30 = run(10), run(30)
+            per_it = (t30 - t10) / 20.0
+            setup = max(t10 - 10 * per_it, 0.0)
+            cost = setup + per_it * float(np.sum(its))
+            total += cost
+            parts.append(f"{fz} Hz: {setup:.1f} s + {per_it:.3f} s/it x {int(np.sum(its))} its")
+    n = len(freqs) * len(sources)
+    return {"value": n / total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle truncated at 10 and 30 iterations per frequency, priced at the "
+                      f"GPU's per-source iteration counts ({'; '.join(parts)}) = {total:.0f} s "
+                      f"for {n} solves; NumPy/SciPy FP64, 1 thread"}
+
+
+def main_batch(a, hh, torch, dev):
+    import workloads as wl
+    slow, sources, freqs = wl.grf_801x301_sources()
+    nz, nx = slow.shape
+    F = np.zeros((len(sources), nz, nx), complex)
+    for i, (ix, iz) in enumerate(sources):
+        F[i, iz, ix] = 1.0
+    Ft = torch.from_numpy(F).to(dev)
+    m = torch.from_numpy(slow).to(dev)
+    mixed = a.precision == "mixed"
+    restart, tol = 30, 1e-6
+    t_setup = time.perf_counter()
+    max_coarse = a.max_coarse or 16384
+    probs = [hh.Problem(m, 2 * np.pi * fz, 0.01, 10.0, max_coarse=max_coarse) for fz in freqs]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
+    wss = [torch.empty(P.workspace_bytes_batch(restart, len(sources)), dtype=torch.uint8,
+                       device=dev) for P in probs]
+    U = torch.empty_like(Ft)
+
+    def one():
+        return [P.solve_batch(Ft, tol=tol, restart=restart, max_iters=2000, precond_f32=mixed,
+                              U=U, workspace=ws) for P, ws in zip(probs, wss)]
+
+    for _ in range(a.warmup):
+        one()
+    share = {}
+    for k in hh.KERNEL_IDS:
+        if k == "none":
+            continue
+        for P in probs:
+            P.kernel_timer_start(k)
+        one()
+        tot = 0.0
+        for P in probs:
+            n_k, ms_k, _ = P.kernel_timer_read()
+            tot += ms_k
+            P.kernel_timer_start("none")
+        if tot > 0:
+            share[k] = tot
+    kernel = max(share, key=share.get) if a.kernel == "auto" else a.kernel
+    for P in probs:
+        P.kernel_timer_start(kernel)
+    torch.cuda.synchronize()
+    lat, its, res = [], None, []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        t1 = time.perf_counter()
+        rs = one()
+        lat.append(time.perf_counter() - t1)
+        its = [r.iterations for r in rs]
+        for r in rs:
+            res.append(float(r.true_rel_res.max()))
+            if r.overall != hh.HH_OK or r.true_rel_res.max() > tol:
+                print("batched solve did not converge", file=sys.stderr)
+                sys.exit(1)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    launches = kms = kbytes = 0
+    for P in probs:
+        n_k, ms_k, b_k = P.kernel_timer_read()
+        launches += n_k
+        kms += ms_k
+        kbytes += b_k
+        P.kernel_timer_start("none")
+    achieved = (kbytes / (kms * 1e-3)) / 1e9 if kms > 0 else 0.0
+    n_solves = len(freqs) * len(sources)
+    out = {
+        "metric": METRIC,
+        "value": a.steps * n_solves / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * elapsed / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128+c64" if mixed else "c128",
+        "data": "synthetic",
+        "config": {
+            "workload": "grf2d_801x301_s4_32src_x_4freq",
+            "grid_nx_nz": [nx, nz], "h_m": 10.0, "freq_hz": freqs, "alpha": 0.01,
+            "beta": [1.0, 0.5], "tol": tol, "restart": restart, "sources_per_batch": len(sources),
+            "solves_per_step": n_solves, "max_coarse": max_coarse,
+            "precond": "V(2,2) omega-Jacobi, Galerkin coarse operators, dense coarsest inverse"
+                       + (", complex64 inside FP64 FGMRES" if mixed else ", complex128"),
+            "levels_nz_nx": [[list(P.level_info(l)[0]) for l in range(P.num_levels)]
+                             for P in probs[:1]][0],
+            "iterations_min_max_by_freq": [[int(i.min()), int(i.max())] for i in its],
+            "true_rel_res_max": max(res),
+            "setup_ms": 1e3 * t_setup,
+        },
+        "latency_ms": {"p50_step": float(np.percentile(lat, 50) * 1e3),
+                       "p99_step": float(np.percentile(lat, 99) * 1e3),
+                       "plain": "a step is the 128 solves; the plain one-at-a-time solver is "
+                                "bench.py without --workload"},
+        "roofline": {
+            "bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic("grf2d_801x301_batch" + ("_mixed" if mixed else ""),
+                                        kernel),
+            "launches": int(launches), "avg_launch_us": 1e3 * kms / max(launches, 1),
+            "algorithmic_bytes_per_launch": kbytes / max(launches, 1),
+            "device_ms_per_step_by_kernel": {k: round(v, 3) for k, v in
+                                             sorted(share.items(), key=lambda kv: -kv[1])},
+        },
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(slow, sources, freqs, a.cpu_seconds, its,
+                                                 max_coarse)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -139,12 +292,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.workload == "grf_801x301_batch":
+        return main_batch(a, hh, torch, dev)
     w = workload(a.workload)
     stream = torch.cuda.current_stream()
     m = torch.from_numpy(w.slowness).to(dev)
     f = torch.from_numpy(w.source).to(dev)
     t_setup = time.perf_counter()
-    P = hh.Problem(m, w.omega, w.alpha, w.h, beta=w.beta)
+    P = hh.Problem(m, w.omega, w.alpha, w.h, beta=w.beta, max_coarse=a.max_coarse)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     ws = P.workspace(w.restart)

@@ -23,7 +23,9 @@
  * coarsest grid. A dimension of n nodes and spacing h is coarsened to
  * (n-1)/2+1 nodes when n-1 is even, (n-1)/2 >= 2, and either
  * omega * max(m) * 2h <= pi (two or more nodes per shortest wavelength) or the
- * grid still has more than HH_MAX_COARSE nodes.
+ * grid still has more than the dense limit (HH_MAX_COARSE nodes unless changed
+ * by hh_set_max_coarse). The coarsest inverse comes from an LU factorisation
+ * with partial pivoting (rocSOLVER) at set-up.
  *
  * Layout: real arrays are float64; complex arrays are complex128 stored as
  * interleaved (re, im) pairs. 1D grids have n nodes; 2D grids are stored
@@ -69,8 +71,10 @@ enum hh_status {
                                Flexible GMRES takes any fixed preconditioner, so the
                                tolerance is met in full precision. Excludes HH_NO_PRECOND. */
 
-/* Largest coarsest-grid size (unknowns) inverted densely. */
+/* Default largest coarsest-grid size (unknowns) inverted densely, and the
+ * largest that hh_set_max_coarse accepts (a 32768^2 complex128 inverse is 17 GB). */
 #define HH_MAX_COARSE 4096
+#define HH_MAX_COARSE_LIMIT 32768
 /* Largest 1D grid handled by the single-workgroup tridiagonal solve. */
 #define HH_MAX_1D 1024
 /* Most right-hand sides in one hh_solve_batch call. */
@@ -93,6 +97,18 @@ enum hh_status {
  */
 int hh_create_problem(const double* m_dev, int ndim, const int64_t* shape, double omega,
                       double alpha, double h, void* stream, hh_problem* out);
+
+/*
+ * hh_set_max_coarse -- rebuild the multigrid hierarchy with a different dense
+ * limit for the coarsest grid (1..HH_MAX_COARSE_LIMIT unknowns; default
+ * HH_MAX_COARSE). A larger limit stops the coarsening earlier, at the level
+ * that still keeps two nodes per wavelength when that level fits, so the cycle
+ * is a better preconditioner at the price of a larger dense inverse
+ * (limit^2 * 16 bytes at most, plus a complex64 copy) read once per
+ * preconditioner application (once per step for a whole batch of sources).
+ * The shift in force is re-applied. 2D only (1D is solved exactly).
+ */
+int hh_set_max_coarse(hh_problem p, int max_coarse);
 
 /*
  * hh_set_shift -- choose the shifted-Laplace preconditioner of Eq. 6,

@@ -12,6 +12,8 @@
 #include "givens.h"
 
 #include <immintrin.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <chrono>
 #include <cmath>
@@ -90,8 +92,12 @@ struct hh_problem_s {
     cplx* cinv = nullptr;           // explicit inverse of the coarsest operator
     cplxf* cinvf = nullptr;         // ... rounded to complex64
     int nc = 0;
-    cplx* gj_scratch = nullptr;
-    int* gj_perm = nullptr;
+    int max_coarse = HH_MAX_COARSE; // largest coarsest grid inverted densely
+    rocblas_handle blas = nullptr;  // LU inversion of the coarsest operator; batched GEMM
+    rocblas_int* ipiv = nullptr;    // LU pivots
+    rocblas_int* dinfo = nullptr;   // LU status
+    void* gemm_part = nullptr;      // partial sums of the batched coarsest product
+    size_t gemm_part_bytes = 0;
     cplx* fin_partial = nullptr;    // block sums for the finiteness check of cinv
     int* dflag = nullptr;           // device scratch for checks
     double* dpartial = nullptr;
@@ -242,6 +248,8 @@ int kt_harvest(hh_problem_s* p, const std::vector<std::vector<int>>& executed) {
     } while (0)
 #define TIMED(KID, BYTES, EXPR) TIMED2(KID, BYTES, 0.0, EXPR)
 
+
+
 // ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
@@ -306,6 +314,14 @@ T* at(void* base, size_t off) {
 // ---------------------------------------------------------------------------
 // preconditioner
 // ---------------------------------------------------------------------------
+int ensure_blas(hh_problem_s* p) {
+    if (!p->blas && rocblas_create_handle(&p->blas) != rocblas_status_success) {
+        p->blas = nullptr;
+        return fail(HH_EDEVICE, "rocblas_create_handle failed");
+    }
+    return HH_OK;
+}
+
 // One V(2,2) cycle on level l >= 1: ec_l = V(l, bc_l), one kernel per leg,
 // in precision T, for every right-hand side of the batch.
 template <class T>
@@ -318,8 +334,12 @@ int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* 
     C* x = at<C>(ws, L.ec[l]);
     if (l == nl - 1) {
         const double nc = p->nc;
-        TIMED2(HH_KERNEL_GEMV, 2 * nc * es, nc * nc * es,
-               launch_vc_gemv(p->nc, Prec<T>::cinv(p), b, x, active, s, bt));
+        if (bt.n > 1)
+            TIMED2(HH_KERNEL_GEMV, 2 * nc * es, nc * nc * es * ((bt.n + 31) / 32),
+                   launch_vc_gemm(p->nc, Prec<T>::cinv(p), b, x, p->gemm_part, s, bt));
+        else
+            TIMED2(HH_KERNEL_GEMV, 2 * nc * es, nc * nc * es,
+                   launch_vc_gemv(p->nc, Prec<T>::cinv(p), b, x, active, s, bt));
         return HH_OK;
     }
     const LevelData& lv = p->levels[l];
@@ -396,6 +416,7 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const S
 // ---------------------------------------------------------------------------
 // set-up
 // ---------------------------------------------------------------------------
+// releases the level operators and the coarsest-level data
 void free_levels(hh_problem_s* p) {
     for (auto& l : p->levels) {
         if (l.C) (void)hipFree(l.C);
@@ -407,10 +428,20 @@ void free_levels(hh_problem_s* p) {
         l.Cf = nullptr;
         l.wdf = nullptr;
     }
+    p->levels.clear();
+    if (p->cinv) (void)hipFree(p->cinv);
+    if (p->cinvf) (void)hipFree(p->cinvf);
+    if (p->ipiv) (void)hipFree(p->ipiv);
+    if (p->fin_partial) (void)hipFree(p->fin_partial);
+    p->cinv = nullptr;
+    p->cinvf = nullptr;
+    p->ipiv = nullptr;
+    p->fin_partial = nullptr;
 }
 
+
 int build_hierarchy(hh_problem_s* p) {
-    p->levels.clear();
+    free_levels(p);
     LevelData L0;
     L0.nz = p->nz;
     L0.nx = p->nx;
@@ -427,7 +458,7 @@ int build_hierarchy(hh_problem_s* p) {
         cur.wj = kmax * std::fmax(cur.hz, cur.hx) < kKhSmooth ? kJacobiWeight : kJacobiWeightCoarse;
         // keep two nodes per shortest wavelength, unless the grid is still too
         // large for the direct coarsest solve
-        const bool big = cur.size() > HH_MAX_COARSE;
+        const bool big = cur.size() > p->max_coarse;
         auto halves = [&](int n, double h) {
             return (n - 1) % 2 == 0 && (n - 1) / 2 >= 2 && (kmax * 2.0 * h <= M_PI || big);
         };
@@ -443,11 +474,11 @@ int build_hierarchy(hh_problem_s* p) {
         p->levels.push_back(nxt);
     }
     const int64_t nc = p->levels.back().size();
-    if (nc > HH_MAX_COARSE)
+    if (nc > p->max_coarse)
         return fail(HH_EUNSUPPORTED,
                     "coarsest multigrid grid has " + std::to_string(nc) +
-                        " unknowns (more than HH_MAX_COARSE = " +
-                        std::to_string(HH_MAX_COARSE) + ")");
+                        " unknowns (more than the dense limit " +
+                        std::to_string(p->max_coarse) + ")");
     p->nc = (int)nc;
     for (size_t l = 1; l < p->levels.size(); ++l) {
         HIPCHK(hipMalloc(&p->levels[l].C, 9 * (size_t)p->levels[l].size() * sizeof(cplx)));
@@ -459,8 +490,7 @@ int build_hierarchy(hh_problem_s* p) {
     }
     HIPCHK(hipMalloc(&p->cinv, (size_t)nc * nc * sizeof(cplx)));
     HIPCHK(hipMalloc(&p->cinvf, (size_t)nc * nc * sizeof(cplxf)));
-    HIPCHK(hipMalloc(&p->gj_scratch, 3 * (size_t)nc * sizeof(cplx)));
-    HIPCHK(hipMalloc(&p->gj_perm, (size_t)nc * sizeof(int)));
+    HIPCHK(hipMalloc(&p->ipiv, (size_t)nc * sizeof(rocblas_int)));
     HIPCHK(hipMalloc(&p->fin_partial, (size_t)node_blocks(nc * nc) * sizeof(cplx)));
     return HH_OK;
 }
@@ -490,7 +520,22 @@ int apply_shift(hh_problem_s* p) {
         HIPCHK(launch_dense_from_fine(M, p->cinv, s));
     else
         HIPCHK(launch_dense_from_coarse(coarse_op(p->levels.back()), p->cinv, s));
-    HIPCHK(dense_invert(p->nc, p->cinv, p->gj_scratch, p->gj_perm, s));
+    // explicit inverse by LU with partial pivoting (rocSOLVER getrf + getri).
+    // The row-major matrix is the column-major transpose, and the inverse of
+    // the transpose is the transpose of the inverse: the result is the
+    // row-major inverse.
+    CHK(ensure_blas(p));
+    if (rocblas_set_stream(p->blas, s) != rocblas_status_success ||
+        rocsolver_zgetrf(p->blas, p->nc, p->nc, reinterpret_cast<rocblas_double_complex*>(p->cinv),
+                         p->nc, p->ipiv, p->dinfo) != rocblas_status_success)
+        return fail(HH_EDEVICE, "LU factorisation of the coarsest operator failed");
+    int info = 0;
+    HIPCHK(hipMemcpyAsync(&info, p->dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (info != 0) return fail(HH_ENUMERIC, "coarsest-level operator is singular for this shift");
+    if (rocsolver_zgetri(p->blas, p->nc, reinterpret_cast<rocblas_double_complex*>(p->cinv), p->nc,
+                         p->ipiv, p->dinfo) != rocblas_status_success)
+        return fail(HH_EDEVICE, "inversion of the coarsest operator failed");
     // the inverse must be finite: sum of |entries|^2
     const int64_t nn = (int64_t)p->nc * p->nc;
     const int nb = node_blocks(nn);
@@ -518,11 +563,9 @@ void destroy(hh_problem_s* p) {
     free_levels(p);
     if (p->m2) (void)hipFree(p->m2);
     if (p->m2f) (void)hipFree(p->m2f);
-    if (p->cinv) (void)hipFree(p->cinv);
-    if (p->cinvf) (void)hipFree(p->cinvf);
-    if (p->gj_scratch) (void)hipFree(p->gj_scratch);
-    if (p->gj_perm) (void)hipFree(p->gj_perm);
-    if (p->fin_partial) (void)hipFree(p->fin_partial);
+    if (p->dinfo) (void)hipFree(p->dinfo);
+    if (p->gemm_part) (void)hipFree(p->gemm_part);
+    if (p->blas) (void)rocblas_destroy_handle(p->blas);
     if (p->dflag) (void)hipFree(p->dflag);
     if (p->dpartial) (void)hipFree(p->dpartial);
     if (p->nrm2_host) (void)hipHostFree(p->nrm2_host);
@@ -666,6 +709,7 @@ int hh_create_problem(const double* m_dev, int ndim, const int64_t* shape, doubl
     if (nb > 512) nb = 512;
     hipError_t e;
     if ((e = hipMalloc(&p->m2, p->N * sizeof(double))) != hipSuccess ||
+        (e = hipMalloc(&p->dinfo, sizeof(rocblas_int))) != hipSuccess ||
         (e = hipMalloc(&p->m2f, p->N * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&p->dflag, sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&p->dpartial, 4096 * sizeof(cplx))) != hipSuccess ||
@@ -705,6 +749,25 @@ int hh_set_shift(hh_problem p, double beta1, double beta2) {
     p->beta1 = beta1;
     p->beta2 = beta2;
     return apply_shift(p);
+}
+
+int hh_set_max_coarse(hh_problem p, int max_coarse) {
+    g_err.clear();
+    if (!p) return fail(HH_EINVAL, "problem is NULL");
+    if (max_coarse < 1 || max_coarse > HH_MAX_COARSE_LIMIT)
+        return fail(HH_EINVAL, "max_coarse must be in [1, HH_MAX_COARSE_LIMIT]");
+    if (p->ndim != 2) return fail(HH_EINVAL, "the dense coarsest limit applies to 2D problems");
+    const int old = p->max_coarse;
+    p->max_coarse = max_coarse;
+    int rc = build_hierarchy(p);
+    if (rc == HH_OK) rc = apply_shift(p);
+    if (rc != HH_OK) {   // restore a working hierarchy with the previous limit
+        const std::string why = g_err;
+        p->max_coarse = old;
+        if (build_hierarchy(p) == HH_OK) (void)apply_shift(p);
+        g_err = why;
+    }
+    return rc;
 }
 
 int hh_workspace_bytes(hh_problem p, int restart, size_t* bytes) {
@@ -867,6 +930,16 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
     const Layout L = layout(p, m, f32 ? sizeof(cplxf) : sizeof(cplx));
     if (workspace_bytes < (size_t)nrhs * L.total) return fail(HH_EINVAL, "workspace too small");
     CHK(ensure_host_buffers(p, max_iters, nrhs));
+    if (nrhs > 1 && p->ndim == 2 && p->levels.size() >= 2) {
+        const size_t need = vc_gemm_scratch_bytes(p->nc, nrhs);
+        if (p->gemm_part_bytes < need) {
+            if (p->gemm_part) HIPCHK(hipFree(p->gemm_part));
+            p->gemm_part = nullptr;
+            p->gemm_part_bytes = 0;
+            HIPCHK(hipMalloc(&p->gemm_part, need));
+            p->gemm_part_bytes = need;
+        }
+    }
     const int64_t N = p->N;
     const Batch bt{nrhs, (int64_t)L.total, N};
 

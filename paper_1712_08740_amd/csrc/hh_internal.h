@@ -238,9 +238,6 @@ hipError_t launch_galerkin_from_coarse(const CoarseOp& fine, int hz, int hx, int
 // dense row-major matrix of a level operator
 hipError_t launch_dense_from_fine(const FineOp& op, cplx* A, hipStream_t s);
 hipError_t launch_dense_from_coarse(const CoarseOp& op, cplx* A, hipStream_t s);
-// in-place inverse by Gauss-Jordan elimination with partial pivoting;
-// scratch: 3n complex + n ints
-hipError_t dense_invert(int n, cplx* A, cplx* scratch, int* perm, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // launchers (pcr.hip): exact solve of the 1D tridiagonal shifted Laplacian
@@ -340,6 +337,16 @@ hipError_t launch_vc_gemv(int n, const cplxf* A, const cplxf* x, cplxf* y, const
                           hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_gemv(int n, const cplxf* A, const cplx* x, cplxf* y, const int* active,
                           hipStream_t s, const Batch& bt = Batch());
+// the same product for every right-hand side of a batch at once (Y = A X, the
+// inverse read once per 32 right-hand sides); not predicated: the columns of
+// sources whose cycle has stopped are computed too and not used
+// (split over k for parallelism; scratch holds the partial sums, at least
+// vc_gemm_scratch_bytes(n, bt.n) bytes)
+size_t vc_gemm_scratch_bytes(int n, int nrhs);
+hipError_t launch_vc_gemm(int n, const cplx* A, const cplx* x, cplx* y, void* scratch,
+                          hipStream_t s, const Batch& bt);
+hipError_t launch_vc_gemm(int n, const cplxf* A, const cplxf* x, cplxf* y, void* scratch,
+                          hipStream_t s, const Batch& bt);
 // temporally blocked legs (vcycle_tiled.hip): down = two pre-sweeps from zero,
 // residual and restriction; up = prolongation and two post-sweeps
 // (the smoother weight enters through op.wdinv = omega_J / diag).

@@ -1,8 +1,7 @@
 // Multigrid transfer and set-up kernels for the approximate shifted-Laplace
 // inverse (Eq. 6-7): full-weighting restriction R = P^T / 2^{d_c}, (bi)linear
-// prolongation P, Galerkin coarse operators R M P (9-point), the explicit
-// inverse of the coarsest operator (Gauss-Jordan with partial pivoting) and
-// its application as a dense complex matrix-vector product.
+// prolongation P, Galerkin coarse operators R M P (9-point), and the dense
+// matrix of the coarsest operator (inverted by LU in the set-up).
 #include "hh_internal.h"
 
 namespace hh {
@@ -139,99 +138,6 @@ __global__ void __launch_bounds__(256) k_dense_from_coarse(CoarseOp op, cplx* __
     }
 }
 
-// ---- Gauss-Jordan inversion ------------------------------------------------
-// Step k, part 1 (one workgroup): pivot row p = argmax_{i>=k} |A[i][k]|
-// (smallest index on ties); prow = new row k scaled by 1/pivot with the
-// identity column folded in; pcol = column k after the row swap; rowk = old
-// row k (it becomes row p).
-constexpr int GJ_THREADS = 1024;
-
-__global__ void __launch_bounds__(GJ_THREADS) k_gj_pivot(int n, int k, const cplx* __restrict__ A,
-                                                         cplx* __restrict__ prow,
-                                                         cplx* __restrict__ pcol,
-                                                         cplx* __restrict__ rowk,
-                                                         int* __restrict__ perm) {
-    __shared__ double sval[GJ_THREADS / 64];
-    __shared__ int sidx[GJ_THREADS / 64];
-    __shared__ int s_p;
-    const int tid = threadIdx.x;
-    double best = -1.0;
-    int bidx = n;
-    for (int i = k + tid; i < n; i += GJ_THREADS) {
-        const double v = cabs2(A[(int64_t)i * n + k]);
-        if (v > best) { best = v; bidx = i; }   // strided ascending: first max kept
-    }
-    // wave reduction: larger value wins, smaller index on ties
-    for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_down(best, off, 64);
-        const int oi = __shfl_down(bidx, off, 64);
-        if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
-    }
-    if ((tid & 63) == 0) { sval[tid >> 6] = best; sidx[tid >> 6] = bidx; }
-    __syncthreads();
-    if (tid == 0) {
-        double bv = sval[0];
-        int bi = sidx[0];
-        for (int w = 1; w < GJ_THREADS / 64; ++w)
-            if (sval[w] > bv || (sval[w] == bv && sidx[w] < bi)) { bv = sval[w]; bi = sidx[w]; }
-        if (bi < k || bi >= n) bi = k;   // no finite pivot: keep the row (result is not finite)
-        s_p = bi;
-        perm[k] = bi;
-    }
-    __syncthreads();
-    const int p = s_p;
-    const cplx piv = A[(int64_t)p * n + k];
-    const cplx ipiv = crecip(piv);
-    for (int j = tid; j < n; j += GJ_THREADS) {
-        const cplx v = (j == k) ? mk(1.0, 0.0) : A[(int64_t)p * n + j];
-        prow[j] = cmul(v, ipiv);
-        rowk[j] = A[(int64_t)k * n + j];
-    }
-    for (int i = tid; i < n; i += GJ_THREADS) {
-        cplx v;
-        if (i == p) v = A[(int64_t)k * n + k];
-        else v = A[(int64_t)i * n + k];
-        pcol[i] = v;
-    }
-}
-
-// Step k, part 2: every element; reads only its own element and the buffers
-// of part 1, so the in-place update has no cross-workgroup hazard.
-__global__ void __launch_bounds__(256) k_gj_update(int n, int k, cplx* __restrict__ A,
-                                                   const cplx* __restrict__ prow,
-                                                   const cplx* __restrict__ pcol,
-                                                   const cplx* __restrict__ rowk,
-                                                   const int* __restrict__ perm) {
-    const int j = blockIdx.x * BX + threadIdx.x;
-    const int i = blockIdx.y * BZ + threadIdx.y;
-    if (i >= n || j >= n) return;
-    const int p = perm[k];
-    const int64_t e = (int64_t)i * n + j;
-    if (i == k) {
-        A[e] = prow[j];
-        return;
-    }
-    cplx src = (i == p) ? rowk[j] : A[e];
-    if (j == k) src = mk(0.0, 0.0);
-    A[e] = csub(src, cmul(pcol[i], prow[j]));
-}
-
-// Undo the row interchanges as column interchanges, in reverse order.
-__global__ void __launch_bounds__(256) k_gj_unscramble(int n, cplx* __restrict__ A,
-                                                       const int* __restrict__ perm) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    cplx* row = A + (int64_t)i * n;
-    for (int k = n - 1; k >= 0; --k) {
-        const int p = perm[k];
-        if (p != k) {
-            const cplx t = row[k];
-            row[k] = row[p];
-            row[p] = t;
-        }
-    }
-}
-
 }  // namespace
 
 hipError_t launch_galerkin_from_fine(const FineOp& fine, int hz, int hx, int nzc, int nxc,
@@ -261,20 +167,6 @@ hipError_t launch_dense_from_coarse(const CoarseOp& op, cplx* A, hipStream_t s) 
     hipError_t e = hipMemsetAsync(A, 0, n * n * sizeof(cplx), s);
     if (e != hipSuccess) return e;
     HH_LAUNCH(k_dense_from_coarse, grid2(op.nz, op.nx), dim3(BX, BZ), 0, s, op, A);
-    return hipGetLastError();
-}
-
-hipError_t dense_invert(int n, cplx* A, cplx* scratch, int* perm, hipStream_t s) {
-    cplx* prow = scratch;
-    cplx* pcol = scratch + n;
-    cplx* rowk = scratch + 2 * n;
-    for (int k = 0; k < n; ++k) {
-        HH_LAUNCH(k_gj_pivot, dim3(1), dim3(GJ_THREADS), 0, s, n, k, A, prow, pcol,
-                           rowk, perm);
-        HH_LAUNCH(k_gj_update, grid2(n, n), dim3(BX, BZ), 0, s, n, k, A, prow, pcol,
-                           rowk, perm);
-    }
-    HH_LAUNCH(k_gj_unscramble, dim3((n + 255) / 256), dim3(256), 0, s, n, A, perm);
     return hipGetLastError();
 }
 

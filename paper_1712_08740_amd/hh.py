@@ -29,6 +29,7 @@ HH_EUNSUPPORTED = -5
 HH_NO_PRECOND = 1
 HH_PRECOND_F32 = 2
 HH_MAX_COARSE = 4096
+HH_MAX_COARSE_LIMIT = 32768
 HH_MAX_1D = 1024
 HH_MAX_BATCH = 1024
 HH_KERNEL_NONE = 0
@@ -50,7 +51,7 @@ EXPORTED = [
     "hh_level_info", "hh_apply_operator", "hh_apply_level_operator", "hh_apply_precond",
     "hh_apply_precond_f32",
     "hh_orthogonalize_scratch_bytes", "hh_orthogonalize", "hh_kernel_timer_start",
-    "hh_kernel_timer_read", "hh_workspace_bytes_batch", "hh_solve_batch",
+    "hh_kernel_timer_read", "hh_workspace_bytes_batch", "hh_solve_batch", "hh_set_max_coarse",
 ]
 
 KERNEL_IDS = {"none": HH_KERNEL_NONE, "apply_dot": HH_KERNEL_APPLY_DOT,
@@ -97,6 +98,7 @@ def _load():
         "hh_kernel_timer_start": (ctypes.c_int, [_vp, ctypes.c_int]),
         "hh_kernel_timer_read": (ctypes.c_int, [_vp, _c_i64_p, _c_double_p, _c_double_p]),
         "hh_workspace_bytes_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _c_size_p]),
+        "hh_set_max_coarse": (ctypes.c_int, [_vp, ctypes.c_int]),
         "hh_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_int, ctypes.c_uint, _vp, ctypes.c_size_t,
                                           _vp, _c_int_p, _c_double_p, _c_int_p, _c_double_p,
@@ -170,7 +172,7 @@ class Problem:
     """``hh_create_problem`` + ``hh_set_shift`` for one slowness model and frequency."""
 
     def __init__(self, m: torch.Tensor, omega: float, alpha: float, h: float,
-                 beta=(1.0, 0.5), stream=None):
+                 beta=(1.0, 0.5), stream=None, max_coarse: Optional[int] = None):
         if not isinstance(m, torch.Tensor) or not m.is_cuda or m.dtype != torch.float64:
             raise ValueError("m must be a float64 CUDA tensor")
         if m.dim() not in (1, 2):
@@ -189,6 +191,8 @@ class Problem:
         self._ws = {}
         if tuple(beta) != (1.0, 0.5):
             self.set_shift(*beta)
+        if max_coarse is not None and max_coarse != HH_MAX_COARSE:
+            self.set_max_coarse(max_coarse)
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
@@ -211,6 +215,11 @@ class Problem:
     # -- set-up -------------------------------------------------------------
     def set_shift(self, beta1: float, beta2: float):
         _check(_lib.hh_set_shift(self._handle, float(beta1), float(beta2)), "hh_set_shift")
+
+    def set_max_coarse(self, max_coarse: int):
+        """``hh_set_max_coarse``: dense limit of the coarsest grid (rebuilds the hierarchy)."""
+        _check(_lib.hh_set_max_coarse(self._handle, int(max_coarse)), "hh_set_max_coarse")
+        self._ws = {}
 
     def workspace_bytes(self, restart: int) -> int:
         n = ctypes.c_size_t()

@@ -465,14 +465,34 @@ def _batch_sources(shape, positions):
     return F
 
 
-def _assert_batch_equals_single(P, F, **kw):
-    """Every source of a batch gives the bits of its solve alone."""
+# A batch applies the coarsest inverse to all its sources as one GEMM, whose
+# summation order differs from the single solve's matrix-vector product; every
+# other operation is the same per source. The two iterations therefore differ
+# by rounding (1e-16 per product, carried through at most a few hundred steps):
+# same iteration count (a convergence test sitting on the tolerance may flip by
+# one), and with equal counts the wavefields agree to 1e-10 (complex128
+# preconditioner) or 1e-8 (complex64 preconditioner: its rounding differences
+# are eps32 = 6e-8 per product instead of 1e-16; measured 2e-10 on 801 x 301);
+# with counts one apart both have met the tolerance and agree to the 1e-6 bar.
+BATCH_REL = 1e-10
+BATCH_REL_F32 = 1e-8
+
+
+def _assert_batch_equals_single(P, F, exact=False, **kw):
+    """Every source of a batch gives its solve alone, to rounding (to the bit
+    where no GEMM is involved: exact)."""
     res = P.solve_batch(_t(F), **kw)
     for i in range(F.shape[0]):
         one = P.solve(_t(F[i]), **kw)
-        assert res.iterations[i] == one.iterations, i
-        assert res.true_rel_res[i] == one.true_rel_res, i
-        assert np.array_equal(_np(res.u[i]), _np(one.u)), i
+        if exact:
+            assert res.iterations[i] == one.iterations, i
+            assert np.array_equal(_np(res.u[i]), _np(one.u)), i
+        assert abs(int(res.iterations[i]) - one.iterations) <= 1, i
+        assert res.status[i] == one.status, i
+        u, u1 = _np(res.u[i]), _np(one.u)
+        same = BATCH_REL_F32 if kw.get("precond_f32") else BATCH_REL
+        bound = same if res.iterations[i] == one.iterations else 1e-6
+        assert np.linalg.norm(u - u1) <= bound * max(np.linalg.norm(u1), 1e-300), i
     return res
 
 
@@ -523,21 +543,28 @@ def test_batch_1d_and_single_level(hh, shape):
         pos = [(0, 0), (1, 1), (2, 1)]
     P = _problem(hh, m, omega, 0.01, h)
     F = _batch_sources(shape, pos)
-    _assert_batch_equals_single(P, F, tol=1e-8, restart=10)
-    _assert_batch_equals_single(P, F, tol=1e-8, restart=10, precond_f32=True)
+    # exact 1D solve / fine grid = coarsest level: the batch runs the same
+    # kernels per source (no GEMM), so the bits agree
+    _assert_batch_equals_single(P, F, exact=True, tol=1e-8, restart=10)
+    _assert_batch_equals_single(P, F, exact=True, tol=1e-8, restart=10, precond_f32=True)
+
+
+BATCH_MAX_COARSE = 16384
 
 
 def test_batch_801x301_32_sources_per_frequency(hh):
     """The batching configuration at full size: 801 x 301, 32 top-row sources at
     each of 5 / 7.5 / 10 / 12.5 Hz (one problem per frequency, 32 sources per
-    batch). Every source meets 1e-6 on the residual recomputed in FP64 by the
-    oracle's operator; two sources per frequency equal their solves alone."""
+    batch, coarsest dense limit 16384). Every source meets 1e-6 on the residual
+    recomputed in FP64 by the oracle's operator; two sources per frequency equal
+    their solves alone."""
     slow, sources, freqs = wl.grf_801x301_sources()
     shape = slow.shape
     F = _batch_sources(shape, [(iz, ix) for ix, iz in sources])
     for fz in freqs:
         omega = 2 * np.pi * fz
         P = _problem(hh, slow, omega, 0.01, 10.0)
+        P.set_max_coarse(BATCH_MAX_COARSE)
         res = P.solve_batch(_t(F), tol=1e-6, restart=30, precond_f32=True)
         print(f"801x301 {fz} Hz: iterations {res.iterations.min()}..{res.iterations.max()}")
         assert res.overall == 0 and np.all(res.status == 0)
@@ -548,8 +575,9 @@ def test_batch_801x301_32_sources_per_frequency(hh):
             assert np.linalg.norm(b - H @ U[i].ravel()) <= 1e-6 * (1 + 1e-6) * np.linalg.norm(b)
         for i in (0, 17):
             one = P.solve(_t(F[i]), tol=1e-6, restart=30, precond_f32=True)
-            assert one.iterations == res.iterations[i]
-            assert np.array_equal(_np(one.u), U[i])
+            assert abs(one.iterations - int(res.iterations[i])) <= 1
+            bound = BATCH_REL_F32 if one.iterations == res.iterations[i] else 1e-6
+            assert np.linalg.norm(_np(one.u) - U[i]) <= bound * np.linalg.norm(U[i])
         del P, res
         torch.cuda.empty_cache()
 
@@ -570,3 +598,56 @@ def test_batch_argument_checks(hh):
     res = P.solve_batch(F, tol=1e-6, restart=5)
     assert np.all(res.iterations == 0) and np.all(res.status == 0)
     assert float(torch.abs(res.u).max()) == 0.0
+
+
+@pytest.mark.parametrize("fz", [12.5, 5.0])
+def test_max_coarse_hierarchy_matches_oracle(hh, fz):
+    """A larger dense limit: same levels as the oracle's rule with that limit,
+    the cycle equals the oracle's, and the solve takes the oracle's iteration
+    count (12.5 Hz on 801 x 301: 74 instead of 427 with the default limit)."""
+    slow, sources, _ = wl.grf_801x301_sources()
+    omega = 2 * np.pi * fz
+    P = _problem(hh, slow, omega, 0.01, 10.0)
+    P.set_max_coarse(BATCH_MAX_COARSE)
+    V = mg.VCycle(slow, omega, 1.0, 0.5, 10.0, max_coarse=BATCH_MAX_COARSE)
+    assert [P.level_shape(l) for l in range(P.num_levels)] == [l.shape for l in V.levels]
+    v = wl.random_complex(slow.shape, 4)
+    z = _np(P.apply_precond(_t(v)))
+    ref = V(v.ravel()).reshape(slow.shape)
+    assert np.linalg.norm(z - ref) <= 1e-10 * np.linalg.norm(ref)
+    z32 = _np(P.apply_precond(_t(v), f32=True)).astype(np.complex128)
+    assert np.linalg.norm(z32 - ref) <= F32_CYCLE_TOL * np.linalg.norm(ref)
+    f = np.zeros(slow.shape, complex)
+    f[0, sources[0][0]] = 1.0
+    res = P.solve(_t(f), tol=1e-6, restart=30)
+    H = op.helmholtz(slow, omega, 0.01, 10.0)
+    b = op.weighted_rhs(f)
+    ref = ogm.gmres(lambda x: H @ x, b, 1e-6, 30, 800, prec=V, flexible=True)
+    ref.x = ref.x.reshape(slow.shape)
+    print(f"801x301 {fz} Hz, dense limit {BATCH_MAX_COARSE}: GPU {res.iterations}, "
+          f"oracle {ref.iterations}")
+    _check_solve(res, ref, 1e-6)
+
+
+def test_max_coarse_argument_checks(hh):
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    for bad in (0, hh.HH_MAX_COARSE_LIMIT + 1):
+        with pytest.raises(hh.HHError):
+            P.set_max_coarse(bad)
+    P.set_max_coarse(1000)            # coarsens further: 26 x 51 -> 26 x 26
+    assert P.level_shape(P.num_levels - 1) == (26, 26)
+    res = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    assert res.status == 0 and res.true_rel_res <= w.tol
+    # 26 x 26 cannot be halved again: unsupported, and the previous hierarchy stays
+    with pytest.raises(hh.HHError):
+        P.set_max_coarse(100)
+    assert P.level_shape(P.num_levels - 1) == (26, 26)
+    res = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    assert res.status == 0 and res.true_rel_res <= w.tol
+    P.set_max_coarse(hh.HH_MAX_COARSE)
+    assert P.level_shape(P.num_levels - 1) == (26, 51)
+    w1 = wl.layered_1d_well()
+    P1 = _problem(hh, w1.slowness, w1.omega, w1.alpha, w1.h)
+    with pytest.raises(hh.HHError):
+        P1.set_max_coarse(8192)
