@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grf_401x201",
                     choices=["grf_401x201", "layered_1d_well", "grf_1201x401",
-                             "grf_801x301_batch"],
+                             "grf_801x301_batch", "serving"],
                     help="grf_801x301_batch: 32 top-row sources x 4 frequencies, one batched "
                          "solve of 32 sources per frequency (a step = all 128 solves)")
     ap.add_argument("--max-coarse", type=int, default=None,
@@ -50,6 +50,12 @@ def parse():
                     help="kernel class for the roofline figure; 'auto' (default) times every "
                          "class over one warm-up solve and takes the one with the most device time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=200,
+                    help="serving: requests in the Poisson stream (mean 200/s)")
+    ap.add_argument("--serve-workers", type=int, default=4,
+                    help="serving: concurrent streams")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0,
+                    help="serving: device memory budget for admitted requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the solves, copy a buffer of this many MiB once on the device "
                          "(a plain copy kernel of known size, to scale hardware byte counters)")
@@ -272,6 +278,66 @@ def main_batch(a, hh, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def main_serving(a, hh, torch, dev):
+    """A Poisson stream of single-source requests (grids 201x101 .. 1601x601,
+    3-20 Hz, per-request seeded models) through the request loop: solves/s over
+    the stream and p50/p99 latency from arrival to result."""
+    import workloads as wl
+    from paper_1712_08740_amd import serve
+    stream = wl.serving_stream(n_requests=a.requests, rate_hz=200.0, seed=5)
+    reqs = []
+    t_gen = time.perf_counter()
+    for r in stream:
+        w = wl.random_field_2d(r["nx"], r["nz"], 10.0, seed=r["seed"], freq_hz=r["freq_hz"],
+                               src=r["src"])
+        reqs.append((r["t_arrival"], serve.Request(
+            id=r["id"], slowness=w.slowness, h=w.h, freq_hz=r["freq_hz"], source=w.source,
+            precond_f32=a.precision == "mixed")))
+    t_gen = time.perf_counter() - t_gen
+    # warm-up: one small request through the library (kernel loading, LU library)
+    serve.solve_one(reqs[0][1], dev, torch.cuda.current_stream())
+    srv = serve.Server(int(a.serve_budget_gib * (1 << 30)), workers=a.serve_workers)
+    t0 = time.perf_counter()
+    for t_arr, rq in reqs:
+        wait = t_arr - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        srv.submit(rq)
+    res = srv.results(timeout=3600)
+    wall = time.perf_counter() - t0
+    srv.close()
+    results = [res[i] for i in sorted(res)]
+    st = serve.summarize(results, wall)
+    by_grid = {}
+    for (_, rq), r in zip(reqs, results):
+        key = f"{rq.slowness.shape[1]}x{rq.slowness.shape[0]}"
+        by_grid.setdefault(key, []).append(r.latency * 1e3)
+    out = {
+        "metric": METRIC,
+        "value": st["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": len(results), "warmup": 1,
+        "ms_per_step": 1e3 * wall / len(results),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "c128+c64" if a.precision == "mixed" else "c128",
+        "data": "synthetic",
+        "config": {"workload": f"serving_poisson200_{a.requests}req",
+                   "grids_nx_nz": [list(g) for g in wl.SERVING_GRIDS], "freq_hz": [3.0, 20.0],
+                   "h_m": 10.0, "alpha": 0.01, "tol": 1e-6, "restart": 30,
+                   "workers": a.serve_workers, "budget_gib": a.serve_budget_gib,
+                   "converged": st["converged"], "max_iterations": st["max_iterations"],
+                   "model_generation_s": t_gen},
+        "latency_ms": {"p50": st["latency_p50_ms"], "p99": st["latency_p99_ms"],
+                       "queue_p50": st["queue_p50_ms"], "queue_p99": st["queue_p99_ms"],
+                       "p50_by_grid": {k: float(np.percentile(v, 50)) for k, v in by_grid.items()},
+                       "plain": "bench.py without --workload is the plain one-at-a-time solver"},
+        "peak_admitted_gib": srv.peak_in_use / 2 ** 30,
+        "max_concurrent": srv.max_concurrent,
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -294,6 +360,8 @@ def main():
         del src, dst
     if a.workload == "grf_801x301_batch":
         return main_batch(a, hh, torch, dev)
+    if a.workload == "serving":
+        return main_serving(a, hh, torch, dev)
     w = workload(a.workload)
     stream = torch.cuda.current_stream()
     m = torch.from_numpy(w.slowness).to(dev)

@@ -119,6 +119,19 @@ int hh_set_max_coarse(hh_problem p, int max_coarse);
  */
 int hh_set_shift(hh_problem p, double beta1, double beta2);
 
+/*
+ * hh_footprint_bytes -- device memory a solve will need, before anything is
+ * created (host-side planning only; for admission control by HBM footprint):
+ * *problem_b = what hh_create_problem (+ hh_set_max_coarse(max_coarse)) would
+ * allocate for the operators, *workspace_b = the workspace of hh_solve_batch
+ * with nrhs sources (nrhs = 1: hh_solve) plus the batched coarsest product's
+ * scratch. max_slowness = max(m) decides the coarsening (as in the solve).
+ * flags as for hh_solve (the estimate is the complex128 one, an upper bound).
+ */
+int hh_footprint_bytes(int ndim, const int64_t* shape, double omega, double max_slowness,
+                       double h, int max_coarse, int restart, int nrhs, unsigned flags,
+                       size_t* problem_b, size_t* workspace_b);
+
 /* Bytes of device workspace hh_solve needs for a given restart length. */
 int hh_workspace_bytes(hh_problem p, int restart, size_t* bytes);
 

@@ -440,8 +440,10 @@ void free_levels(hh_problem_s* p) {
 }
 
 
-int build_hierarchy(hh_problem_s* p) {
-    free_levels(p);
+// Level grids, spacings, halving flags and smoother weights (host only; no
+// device memory). EUNSUPPORTED when the coarsest grid exceeds the dense limit.
+int plan_levels(hh_problem_s* p) {
+    p->levels.clear();
     LevelData L0;
     L0.nz = p->nz;
     L0.nx = p->nx;
@@ -480,6 +482,35 @@ int build_hierarchy(hh_problem_s* p) {
                         " unknowns (more than the dense limit " +
                         std::to_string(p->max_coarse) + ")");
     p->nc = (int)nc;
+    return HH_OK;
+}
+
+// Device bytes the handle owns for its operators (levels, coarsest inverse
+// and its LU pivots and check partials, m^2 in both precisions, scratch),
+// from a planned hierarchy.
+size_t problem_bytes(const hh_problem_s* p) {
+    size_t b = align_up((size_t)p->N * (sizeof(double) + sizeof(float))) + align_up(sizeof(int)) +
+               align_up(4096 * sizeof(cplx)) + align_up(sizeof(rocblas_int));
+    const size_t nl = p->levels.size();
+    for (size_t l = 0; l < nl; ++l) {
+        const size_t n = (size_t)p->levels[l].size();
+        if (l >= 1) b += align_up(9 * n * sizeof(cplx)) + align_up(9 * n * sizeof(cplxf));
+        if (l + 1 < nl) b += align_up(n * sizeof(cplx)) + align_up(n * sizeof(cplxf));
+    }
+    if (p->ndim == 2) {
+        const size_t nc = (size_t)p->nc;
+        b += align_up(nc * nc * sizeof(cplx)) + align_up(nc * nc * sizeof(cplxf)) +
+             align_up(nc * sizeof(rocblas_int)) +
+             align_up((size_t)node_blocks((int64_t)nc * nc) * sizeof(cplx));
+    }
+    return b;
+}
+
+int build_hierarchy(hh_problem_s* p) {
+    free_levels(p);
+    CHK(plan_levels(p));
+    const int64_t nc = p->nc;
+    if (p->ndim == 1) return HH_OK;
     for (size_t l = 1; l < p->levels.size(); ++l) {
         HIPCHK(hipMalloc(&p->levels[l].C, 9 * (size_t)p->levels[l].size() * sizeof(cplx)));
         HIPCHK(hipMalloc(&p->levels[l].Cf, 9 * (size_t)p->levels[l].size() * sizeof(cplxf)));
@@ -749,6 +780,39 @@ int hh_set_shift(hh_problem p, double beta1, double beta2) {
     p->beta1 = beta1;
     p->beta2 = beta2;
     return apply_shift(p);
+}
+
+int hh_footprint_bytes(int ndim, const int64_t* shape, double omega, double max_slowness,
+                       double h, int max_coarse, int restart, int nrhs, unsigned flags,
+                       size_t* problem_b, size_t* workspace_b) {
+    g_err.clear();
+    if (!shape || !problem_b || !workspace_b) return fail(HH_EINVAL, "NULL argument");
+    if (ndim != 1 && ndim != 2) return fail(HH_EINVAL, "ndim must be 1 or 2");
+    for (int d = 0; d < ndim; ++d)
+        if (shape[d] < 3 || shape[d] > (1 << 24))
+            return fail(HH_EINVAL, "every grid dimension must be in [3, 2^24]");
+    if (!finite_pos(omega) || !finite_pos(max_slowness) || !finite_pos(h))
+        return fail(HH_EINVAL, "omega, max_slowness and h must be finite and > 0");
+    if (max_coarse < 1 || max_coarse > HH_MAX_COARSE_LIMIT)
+        return fail(HH_EINVAL, "max_coarse must be in [1, HH_MAX_COARSE_LIMIT]");
+    if (restart < 1 || restart > kMaxRestart) return fail(HH_EINVAL, "restart must be in [1, 1024]");
+    if (nrhs < 1 || nrhs > HH_MAX_BATCH) return fail(HH_EINVAL, "nrhs must be in [1, HH_MAX_BATCH]");
+    if (flags & ~(HH_NO_PRECOND | HH_PRECOND_F32)) return fail(HH_EINVAL, "unknown flag");
+    hh_problem_s q;                 // host-side plan only: nothing is allocated
+    q.ndim = ndim;
+    q.nz = ndim == 2 ? (int)shape[0] : 1;
+    q.nx = ndim == 2 ? (int)shape[1] : (int)shape[0];
+    q.N = (int64_t)q.nz * q.nx;
+    q.omega = omega;
+    q.h = h;
+    q.mmax = max_slowness;
+    q.max_coarse = max_coarse;
+    CHK(plan_levels(&q));
+    *problem_b = problem_bytes(&q);
+    *workspace_b = (size_t)nrhs * layout(&q, restart).total;
+    if (nrhs > 1 && ndim == 2 && q.levels.size() >= 2)
+        *workspace_b += align_up(vc_gemm_scratch_bytes(q.nc, nrhs));
+    return HH_OK;
 }
 
 int hh_set_max_coarse(hh_problem p, int max_coarse) {

@@ -52,6 +52,7 @@ EXPORTED = [
     "hh_apply_precond_f32",
     "hh_orthogonalize_scratch_bytes", "hh_orthogonalize", "hh_kernel_timer_start",
     "hh_kernel_timer_read", "hh_workspace_bytes_batch", "hh_solve_batch", "hh_set_max_coarse",
+    "hh_footprint_bytes",
 ]
 
 KERNEL_IDS = {"none": HH_KERNEL_NONE, "apply_dot": HH_KERNEL_APPLY_DOT,
@@ -99,6 +100,10 @@ def _load():
         "hh_kernel_timer_read": (ctypes.c_int, [_vp, _c_i64_p, _c_double_p, _c_double_p]),
         "hh_workspace_bytes_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _c_size_p]),
         "hh_set_max_coarse": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "hh_footprint_bytes": (ctypes.c_int, [ctypes.c_int, _c_i64_p, ctypes.c_double,
+                                              ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int, ctypes.c_uint,
+                                              _c_size_p, _c_size_p]),
         "hh_solve_batch": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_double, ctypes.c_int,
                                           ctypes.c_int, ctypes.c_uint, _vp, ctypes.c_size_t,
                                           _vp, _c_int_p, _c_double_p, _c_int_p, _c_double_p,
@@ -112,6 +117,22 @@ def _load():
 
 
 _lib = _load()
+
+
+def footprint_bytes(shape, omega: float, max_slowness: float, h: float,
+                    max_coarse: int = None, restart: int = 30, nrhs: int = 1,
+                    precond_f32: bool = False):
+    """``hh_footprint_bytes``: (problem bytes, workspace bytes) a solve of this
+    size will allocate on the device; host-side planning only."""
+    shape = tuple(int(v) for v in shape)
+    sh = (ctypes.c_int64 * 2)(*(shape + (0,) * (2 - len(shape))))
+    pb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.hh_footprint_bytes(len(shape), sh, float(omega), float(max_slowness), float(h),
+                                   HH_MAX_COARSE if max_coarse is None else int(max_coarse),
+                                   int(restart), int(nrhs),
+                                   HH_PRECOND_F32 if precond_f32 else 0, ctypes.byref(pb),
+                                   ctypes.byref(wb)), "hh_footprint_bytes")
+    return pb.value, wb.value
 
 
 class HHError(RuntimeError):

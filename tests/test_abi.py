@@ -71,3 +71,47 @@ def test_null_handles_rejected(lib):
     assert L.hh_destroy_problem(None) == 0
     assert L.hh_orthogonalize_scratch_bytes(1000, 0, ctypes.byref(n)) == -1
     assert L.hh_orthogonalize_scratch_bytes(1000, 4, ctypes.byref(n)) == 0 and n.value > 0
+
+
+def test_footprint_plans_the_oracle_hierarchy(lib):
+    """hh_footprint_bytes plans on the host (no device): the operator bytes are
+    those of the levels the oracle's coarsening rule gives (9 complex
+    coefficients per coarse node and an omega/diag per smoothing node, each in
+    complex128 and complex64, m^2 in float64 and float32, and the coarsest
+    inverse in both precisions), within the 256-byte alignment of each buffer
+    and the fixed scratch; the workspace grows with restart and sources."""
+    import numpy as np
+    import workloads as wl
+    from oracle import multigrid as mg
+    cases = [(wl.grf_401x201(), 4096), (wl.grf_401x201(), 1000)]
+    slow, _, freqs = wl.grf_801x301_sources()
+    for fz in freqs:
+        w = wl.random_field_2d(801, 301, 10.0, seed=4, freq_hz=fz, src=(12, 0))
+        cases.append((w, 16384))
+    for w, mc in cases:
+        kmax = w.omega * w.slowness.max()
+        shapes = mg.level_shapes(w.shape, (w.h, w.h), kmax, max_coarse=mc)
+        n = [a * b for a, b in shapes]
+        nc = n[-1]
+        expect = (12 * n[0] + sum(216 * v for v in n[1:]) + sum(24 * v for v in n[:-1])
+                  + 24 * nc * nc + 4 * nc + 16 * ((nc * nc + 255) // 256) + 16 * 4096)
+        pb, wb = lib.footprint_bytes(w.shape, w.omega, w.slowness.max(), w.h, max_coarse=mc)
+        assert expect <= pb <= expect + 256 * (2 * len(n) + 16), (w.name, mc)
+        _, wb2 = lib.footprint_bytes(w.shape, w.omega, w.slowness.max(), w.h, max_coarse=mc,
+                                     restart=60)
+        _, wb3 = lib.footprint_bytes(w.shape, w.omega, w.slowness.max(), w.h, max_coarse=mc,
+                                     nrhs=3)
+        N = w.slowness.size
+        assert wb2 - wb >= 2 * 30 * N * 16          # 30 more V and Z columns
+        assert wb3 >= 3 * wb
+    pb, wb = lib.footprint_bytes((1001,), 2 * np.pi * 10, 1 / 1500, 5.0, restart=50)
+    assert pb < 100_000 and wb >= (51 + 50) * 1001 * 16
+
+
+def test_footprint_rejects_bad_arguments(lib):
+    with pytest.raises(lib.HHError):
+        lib.footprint_bytes((201, 401), -1.0, 1e-3, 10.0)
+    with pytest.raises(lib.HHError):
+        lib.footprint_bytes((201, 401), 60.0, 1e-3, 10.0, max_coarse=0)
+    with pytest.raises(lib.HHError):           # 26 x 26 cannot be coarsened below 100 nodes
+        lib.footprint_bytes((201, 401), 60.0, 1 / 1500, 10.0, max_coarse=100)
