@@ -54,7 +54,7 @@ def parse():
                     help="serving: requests in the Poisson stream (mean 200/s)")
     ap.add_argument("--serve-workers", type=int, default=4,
                     help="serving: concurrent streams")
-    ap.add_argument("--serve-budget-gib", type=float, default=64.0,
+    ap.add_argument("--serve-budget-gib", type=float, default=128.0,
                     help="serving: device memory budget for admitted requests")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="before the solves, copy a buffer of this many MiB once on the device "

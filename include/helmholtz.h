@@ -98,6 +98,11 @@ enum hh_status {
 int hh_create_problem(const double* m_dev, int ndim, const int64_t* shape, double omega,
                       double alpha, double h, void* stream, hh_problem* out);
 
+/* hh_create_problem with the dense limit of the coarsest grid given at once
+ * (1..HH_MAX_COARSE_LIMIT; see hh_set_max_coarse), saving a rebuild. */
+int hh_create_problem_ex(const double* m_dev, int ndim, const int64_t* shape, double omega,
+                         double alpha, double h, int max_coarse, void* stream, hh_problem* out);
+
 /*
  * hh_set_max_coarse -- rebuild the multigrid hierarchy with a different dense
  * limit for the coarsest grid (1..HH_MAX_COARSE_LIMIT unknowns; default

@@ -706,7 +706,14 @@ const char* hh_last_error(void) { return g_err.c_str(); }
 
 int hh_create_problem(const double* m_dev, int ndim, const int64_t* shape, double omega,
                       double alpha, double h, void* stream, hh_problem* out) {
+    return hh_create_problem_ex(m_dev, ndim, shape, omega, alpha, h, HH_MAX_COARSE, stream, out);
+}
+
+int hh_create_problem_ex(const double* m_dev, int ndim, const int64_t* shape, double omega,
+                         double alpha, double h, int max_coarse, void* stream, hh_problem* out) {
     g_err.clear();
+    if (max_coarse < 1 || max_coarse > HH_MAX_COARSE_LIMIT)
+        return fail(HH_EINVAL, "max_coarse must be in [1, HH_MAX_COARSE_LIMIT]");
     if (!out) return fail(HH_EINVAL, "out is NULL");
     *out = nullptr;
     if (!m_dev) return fail(HH_EINVAL, "m_dev is NULL");
@@ -732,6 +739,7 @@ int hh_create_problem(const double* m_dev, int ndim, const int64_t* shape, doubl
     p->alpha = alpha;
     p->h = h;
     p->stream = static_cast<hipStream_t>(stream);
+    p->max_coarse = max_coarse;
     auto bail = [&](int code) {
         destroy(p);
         return code;

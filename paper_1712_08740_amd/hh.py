@@ -52,7 +52,7 @@ EXPORTED = [
     "hh_apply_precond_f32",
     "hh_orthogonalize_scratch_bytes", "hh_orthogonalize", "hh_kernel_timer_start",
     "hh_kernel_timer_read", "hh_workspace_bytes_batch", "hh_solve_batch", "hh_set_max_coarse",
-    "hh_footprint_bytes",
+    "hh_footprint_bytes", "hh_create_problem_ex",
 ]
 
 KERNEL_IDS = {"none": HH_KERNEL_NONE, "apply_dot": HH_KERNEL_APPLY_DOT,
@@ -100,6 +100,9 @@ def _load():
         "hh_kernel_timer_read": (ctypes.c_int, [_vp, _c_i64_p, _c_double_p, _c_double_p]),
         "hh_workspace_bytes_batch": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _c_size_p]),
         "hh_set_max_coarse": (ctypes.c_int, [_vp, ctypes.c_int]),
+        "hh_create_problem_ex": (ctypes.c_int, [_vp, ctypes.c_int, _c_i64_p, ctypes.c_double,
+                                                ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                _vp, ctypes.POINTER(_vp)]),
         "hh_footprint_bytes": (ctypes.c_int, [ctypes.c_int, _c_i64_p, ctypes.c_double,
                                               ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                               ctypes.c_int, ctypes.c_int, ctypes.c_uint,
@@ -205,15 +208,14 @@ class Problem:
         self._handle = _vp()
         shape = (ctypes.c_int64 * 2)(*self.shape)
         self._setup_stream = stream if stream is not None else torch.cuda.current_stream()
-        _check(_lib.hh_create_problem(_vp(m.data_ptr()), m.dim(), shape, float(omega),
-                                      float(alpha), float(h),
-                                      _vp(self._setup_stream.cuda_stream),
-                                      ctypes.byref(self._handle)), "hh_create_problem")
+        mc = HH_MAX_COARSE if max_coarse is None else int(max_coarse)
+        _check(_lib.hh_create_problem_ex(_vp(m.data_ptr()), m.dim(), shape, float(omega),
+                                         float(alpha), float(h), mc,
+                                         _vp(self._setup_stream.cuda_stream),
+                                         ctypes.byref(self._handle)), "hh_create_problem_ex")
         self._ws = {}
         if tuple(beta) != (1.0, 0.5):
             self.set_shift(*beta)
-        if max_coarse is not None and max_coarse != HH_MAX_COARSE:
-            self.set_max_coarse(max_coarse)
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
