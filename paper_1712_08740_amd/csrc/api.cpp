@@ -12,8 +12,6 @@
 #include "givens.h"
 
 #include <immintrin.h>
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <chrono>
 #include <cmath>
@@ -93,9 +91,7 @@ struct hh_problem_s {
     cplxf* cinvf = nullptr;         // ... rounded to complex64
     int nc = 0;
     int max_coarse = HH_MAX_COARSE; // largest coarsest grid inverted densely
-    rocblas_handle blas = nullptr;  // LU inversion of the coarsest operator; batched GEMM
-    rocblas_int* ipiv = nullptr;    // LU pivots
-    rocblas_int* dinfo = nullptr;   // LU status
+    void* band = nullptr;           // banded LU scratch of the coarsest inverse
     void* gemm_part = nullptr;      // partial sums of the batched coarsest product
     size_t gemm_part_bytes = 0;
     cplx* fin_partial = nullptr;    // block sums for the finiteness check of cinv
@@ -314,14 +310,6 @@ T* at(void* base, size_t off) {
 // ---------------------------------------------------------------------------
 // preconditioner
 // ---------------------------------------------------------------------------
-int ensure_blas(hh_problem_s* p) {
-    if (!p->blas && rocblas_create_handle(&p->blas) != rocblas_status_success) {
-        p->blas = nullptr;
-        return fail(HH_EDEVICE, "rocblas_create_handle failed");
-    }
-    return HH_OK;
-}
-
 // One V(2,2) cycle on level l >= 1: ec_l = V(l, bc_l), one kernel per leg,
 // in precision T, for every right-hand side of the batch.
 template <class T>
@@ -431,11 +419,11 @@ void free_levels(hh_problem_s* p) {
     p->levels.clear();
     if (p->cinv) (void)hipFree(p->cinv);
     if (p->cinvf) (void)hipFree(p->cinvf);
-    if (p->ipiv) (void)hipFree(p->ipiv);
+    if (p->band) (void)hipFree(p->band);
     if (p->fin_partial) (void)hipFree(p->fin_partial);
     p->cinv = nullptr;
     p->cinvf = nullptr;
-    p->ipiv = nullptr;
+    p->band = nullptr;
     p->fin_partial = nullptr;
 }
 
@@ -490,7 +478,7 @@ int plan_levels(hh_problem_s* p) {
 // from a planned hierarchy.
 size_t problem_bytes(const hh_problem_s* p) {
     size_t b = align_up((size_t)p->N * (sizeof(double) + sizeof(float))) + align_up(sizeof(int)) +
-               align_up(4096 * sizeof(cplx)) + align_up(sizeof(rocblas_int));
+               align_up(4096 * sizeof(cplx));
     const size_t nl = p->levels.size();
     for (size_t l = 0; l < nl; ++l) {
         const size_t n = (size_t)p->levels[l].size();
@@ -499,8 +487,9 @@ size_t problem_bytes(const hh_problem_s* p) {
     }
     if (p->ndim == 2) {
         const size_t nc = (size_t)p->nc;
+        const LevelData& lc = p->levels.back();
         b += align_up(nc * nc * sizeof(cplx)) + align_up(nc * nc * sizeof(cplxf)) +
-             align_up(nc * sizeof(rocblas_int)) +
+             align_up(band_scratch_bytes(lc.nz, lc.nx)) +
              align_up((size_t)node_blocks((int64_t)nc * nc) * sizeof(cplx));
     }
     return b;
@@ -521,7 +510,8 @@ int build_hierarchy(hh_problem_s* p) {
     }
     HIPCHK(hipMalloc(&p->cinv, (size_t)nc * nc * sizeof(cplx)));
     HIPCHK(hipMalloc(&p->cinvf, (size_t)nc * nc * sizeof(cplxf)));
-    HIPCHK(hipMalloc(&p->ipiv, (size_t)nc * sizeof(rocblas_int)));
+    const LevelData& lc = p->levels.back();
+    HIPCHK(hipMalloc(&p->band, band_scratch_bytes(lc.nz, lc.nx)));
     HIPCHK(hipMalloc(&p->fin_partial, (size_t)node_blocks(nc * nc) * sizeof(cplx)));
     return HH_OK;
 }
@@ -551,22 +541,14 @@ int apply_shift(hh_problem_s* p) {
         HIPCHK(launch_dense_from_fine(M, p->cinv, s));
     else
         HIPCHK(launch_dense_from_coarse(coarse_op(p->levels.back()), p->cinv, s));
-    // explicit inverse by LU with partial pivoting (rocSOLVER getrf + getri).
-    // The row-major matrix is the column-major transpose, and the inverse of
-    // the transpose is the transpose of the inverse: the result is the
-    // row-major inverse.
-    CHK(ensure_blas(p));
-    if (rocblas_set_stream(p->blas, s) != rocblas_status_success ||
-        rocsolver_zgetrf(p->blas, p->nc, p->nc, reinterpret_cast<rocblas_double_complex*>(p->cinv),
-                         p->nc, p->ipiv, p->dinfo) != rocblas_status_success)
-        return fail(HH_EDEVICE, "LU factorisation of the coarsest operator failed");
-    int info = 0;
-    HIPCHK(hipMemcpyAsync(&info, p->dinfo, sizeof(int), hipMemcpyDeviceToHost, s));
+    // explicit inverse from a banded LU (the coarsest operator is a stencil)
+    const LevelData& lc = p->levels.back();
+    HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int), s));
+    HIPCHK(band_invert(lc.nz, lc.nx, p->cinv, p->band, p->dflag, s));
+    int zero_pivot = 0;
+    HIPCHK(hipMemcpyAsync(&zero_pivot, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (info != 0) return fail(HH_ENUMERIC, "coarsest-level operator is singular for this shift");
-    if (rocsolver_zgetri(p->blas, p->nc, reinterpret_cast<rocblas_double_complex*>(p->cinv), p->nc,
-                         p->ipiv, p->dinfo) != rocblas_status_success)
-        return fail(HH_EDEVICE, "inversion of the coarsest operator failed");
+    if (zero_pivot) return fail(HH_ENUMERIC, "coarsest-level operator is singular for this shift");
     // the inverse must be finite: sum of |entries|^2
     const int64_t nn = (int64_t)p->nc * p->nc;
     const int nb = node_blocks(nn);
@@ -594,9 +576,7 @@ void destroy(hh_problem_s* p) {
     free_levels(p);
     if (p->m2) (void)hipFree(p->m2);
     if (p->m2f) (void)hipFree(p->m2f);
-    if (p->dinfo) (void)hipFree(p->dinfo);
     if (p->gemm_part) (void)hipFree(p->gemm_part);
-    if (p->blas) (void)rocblas_destroy_handle(p->blas);
     if (p->dflag) (void)hipFree(p->dflag);
     if (p->dpartial) (void)hipFree(p->dpartial);
     if (p->nrm2_host) (void)hipHostFree(p->nrm2_host);
@@ -748,7 +728,7 @@ int hh_create_problem_ex(const double* m_dev, int ndim, const int64_t* shape, do
     if (nb > 512) nb = 512;
     hipError_t e;
     if ((e = hipMalloc(&p->m2, p->N * sizeof(double))) != hipSuccess ||
-        (e = hipMalloc(&p->dinfo, sizeof(rocblas_int))) != hipSuccess ||
+
         (e = hipMalloc(&p->m2f, p->N * sizeof(float))) != hipSuccess ||
         (e = hipMalloc(&p->dflag, sizeof(int))) != hipSuccess ||
         (e = hipMalloc(&p->dpartial, 4096 * sizeof(cplx))) != hipSuccess ||

@@ -239,6 +239,14 @@ hipError_t launch_galerkin_from_coarse(const CoarseOp& fine, int hz, int hx, int
 hipError_t launch_dense_from_fine(const FineOp& op, cplx* A, hipStream_t s);
 hipError_t launch_dense_from_coarse(const CoarseOp& op, cplx* A, hipStream_t s);
 
+// explicit inverse of the coarsest operator (bandlu.hip): A (row-major dense
+// nz*nx x nz*nx, a 5- or 9-point stencil) is replaced by its inverse; scratch
+// of band_scratch_bytes(nz, nx); flag[0] set to 1 on a zero/non-finite pivot
+// (clear it first)
+int band_halfwidth(int nz, int nx);
+size_t band_scratch_bytes(int nz, int nx);
+hipError_t band_invert(int nz, int nx, cplx* A, void* scratch, int* flag, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // launchers (pcr.hip): exact solve of the 1D tridiagonal shifted Laplacian
 // ---------------------------------------------------------------------------

@@ -77,9 +77,10 @@ def test_footprint_plans_the_oracle_hierarchy(lib):
     """hh_footprint_bytes plans on the host (no device): the operator bytes are
     those of the levels the oracle's coarsening rule gives (9 complex
     coefficients per coarse node and an omega/diag per smoothing node, each in
-    complex128 and complex64, m^2 in float64 and float32, and the coarsest
-    inverse in both precisions), within the 256-byte alignment of each buffer
-    and the fixed scratch; the workspace grows with restart and sources."""
+    complex128 and complex64, m^2 in float64 and float32, the coarsest inverse
+    in both precisions and the banded LU of the coarsest stencil), within the
+    256-byte alignment of each buffer and the fixed scratch; the workspace
+    grows with restart and sources."""
     import numpy as np
     import workloads as wl
     from oracle import multigrid as mg
@@ -93,8 +94,10 @@ def test_footprint_plans_the_oracle_hierarchy(lib):
         shapes = mg.level_shapes(w.shape, (w.h, w.h), kmax, max_coarse=mc)
         n = [a * b for a, b in shapes]
         nc = n[-1]
+        bw = min(shapes[-1]) + 1                    # half-bandwidth of the coarsest stencil
         expect = (12 * n[0] + sum(216 * v for v in n[1:]) + sum(24 * v for v in n[:-1])
-                  + 24 * nc * nc + 4 * nc + 16 * ((nc * nc + 255) // 256) + 16 * 4096)
+                  + 24 * nc * nc + 16 * nc * (4 * bw + 2) + 16 * ((nc * nc + 255) // 256)
+                  + 16 * 4096)
         pb, wb = lib.footprint_bytes(w.shape, w.omega, w.slowness.max(), w.h, max_coarse=mc)
         assert expect <= pb <= expect + 256 * (2 * len(n) + 16), (w.name, mc)
         _, wb2 = lib.footprint_bytes(w.shape, w.omega, w.slowness.max(), w.h, max_coarse=mc,
