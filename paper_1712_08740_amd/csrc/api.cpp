@@ -289,8 +289,8 @@ Layout layout(const hh_problem_s* p, int m, size_t es = sizeof(cplx)) {
     L.nbN = node_blocks(p->N);
     L.nbS = norm_blocks(p->N);
     L.nbmax = L.nbA > L.nbN ? L.nbA : L.nbN;
-    L.partial = take((size_t)L.nbmax * (m + 1) * c);
-    L.h1 = take((size_t)(m + 1) * c);
+    L.partial = take((size_t)L.nbmax * 2 * (m + 1) * c);
+    L.h1 = take((size_t)2 * (m + 1) * c);
     L.h2 = take((size_t)(m + 1) * c);
     L.R = take((size_t)(m + 1) * m * c);
     L.cs = take((size_t)m * sizeof(double));
@@ -347,56 +347,41 @@ int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* 
     return HH_OK;
 }
 
-// z = M^{-1} v in precision T (v and vout stay complex128). Inside a solve
-// (st given) v = st->scale * src is also written to vout (the normalised
-// Krylov basis vector) and every kernel is predicated on st->active;
-// stand-alone (st == NULL) v = src. With giv (multigrid only) the first leg
-// normalises by 1/||src|| from the norm partials in giv->partial and hosts the
-// Givens step of the previous column. All pointers are those of the first
-// right-hand side; the others follow at the batch stride.
+// z = M^{-1} v in precision T (v stays complex128), for every right-hand side
+// of the batch; every kernel is predicated on *active (NULL: unconditional).
 template <class T>
-int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const SolveState* st,
-            cplx* vout, typename Cx<T>::type* z, hipStream_t s,
-            const GivensArgs* giv = nullptr, const Batch& bt = Batch()) {
+int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const int* active,
+            typename Cx<T>::type* z, hipStream_t s, const Batch& bt = Batch()) {
     typedef typename Cx<T>::type C;
     const double es = (double)sizeof(C), rs = (double)sizeof(T);
     const double N = (double)p->N;
-    const double* scale = st ? &st->scale : nullptr;
-    const int* active = st ? &st->active : nullptr;
     const auto M = Prec<T>::fine(p);
     if (p->ndim == 1) {
-        // src in, v and z out; m^2 shared
-        TIMED2(HH_KERNEL_PCR, (32.0 + es) * N, rs * N,
-               launch_pcr_norm(M, src, scale, vout, z, active, s, bt));
+        // v in, z out; m^2 shared
+        TIMED2(HH_KERNEL_PCR, (16.0 + es) * N, rs * N,
+               launch_pcr_norm(M, src, nullptr, nullptr, z, active, s, bt));
         return HH_OK;
     }
     const int nl = (int)p->levels.size();
     if (nl == 1) {   // the fine grid is the coarsest: dense inverse only
-        const cplx* b = src;
-        if (st) {
-            HIPCHK(launch_normalize_pred(src, st, vout, p->N, s, bt));
-            b = vout;
-        }
         const double nc = p->nc;
         TIMED2(HH_KERNEL_GEMV, 2 * nc * es, nc * nc * es,
-               launch_vc_gemv(p->nc, Prec<T>::cinv(p), b, z, active, s, bt));
+               launch_vc_gemv(p->nc, Prec<T>::cinv(p), src, z, active, s, bt));
         return HH_OK;
     }
     const LevelData& lv = p->levels[0];
     const LevelData& nx = p->levels[1];
     C* x2 = at<C>(ws, L.t[0]);
     const double N1 = (double)nx.size();
-    // down: w in, v out (complex128), x2 out, the coarse right-hand side out;
-    // up: v in (complex128), x2 in, z out, the coarse correction in; both read
-    // m^2 and omega/diag (shared by the right-hand sides)
-    TIMED2(HH_KERNEL_VC_DOWN, (32.0 + es) * N + es * N1, (rs + es) * N,
-           launch_vc_fine_down(M, src, scale, giv ? giv->partial : nullptr, giv ? giv->nb : 0,
-                               vout, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
-                               at<C>(ws, L.bc[1]), active, giv, s, bt));
-    const cplx* b = vout ? vout : src;
+    // down: v in (complex128), x2 out, the coarse right-hand side out; up: v in,
+    // x2 in, z out, the coarse correction in; both read m^2 and omega/diag
+    // (shared by the right-hand sides)
+    TIMED2(HH_KERNEL_VC_DOWN, (16.0 + es) * N + es * N1, (rs + es) * N,
+           launch_vc_fine_down(M, src, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+                               at<C>(ws, L.bc[1]), active, s, bt));
     CHK(vcycle_coarse<T>(p, L, ws, 1, active, s, bt));
     TIMED2(HH_KERNEL_VC_UP, (16.0 + 2.0 * es) * N + es * N1, (rs + es) * N,
-           launch_vc_fine_up(M, lv.halve_z, lv.halve_x, b, x2, at<C>(ws, L.ec[1]), nx.nx, z,
+           launch_vc_fine_up(M, lv.halve_z, lv.halve_x, src, x2, at<C>(ws, L.ec[1]), nx.nx, z,
                              active, s, bt));
     return HH_OK;
 }
@@ -897,7 +882,7 @@ int hh_apply_precond(hh_problem p, const void* v_dev, void* z_dev, void* workspa
     const Layout L = layout(p, 1);
     if (workspace_bytes < L.total) return fail(HH_EINVAL, "workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    CHK(precond<double>(p, L, workspace_dev, static_cast<const cplx*>(v_dev), nullptr, nullptr,
+    CHK(precond<double>(p, L, workspace_dev, static_cast<const cplx*>(v_dev), nullptr,
                         static_cast<cplx*>(z_dev), s));
     HIPCHK(hipStreamSynchronize(s));
     return HH_OK;
@@ -914,7 +899,7 @@ int hh_apply_precond_f32(hh_problem p, const void* v_dev, void* z_dev, void* wor
     const Layout L = layout(p, 1, sizeof(cplxf));
     if (workspace_bytes < L.total) return fail(HH_EINVAL, "workspace too small");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    CHK(precond<float>(p, L, workspace_dev, static_cast<const cplx*>(v_dev), nullptr, nullptr,
+    CHK(precond<float>(p, L, workspace_dev, static_cast<const cplx*>(v_dev), nullptr,
                        static_cast<cplxf*>(z_dev), s));
     HIPCHK(hipStreamSynchronize(s));
     return HH_OK;
@@ -1026,27 +1011,28 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
                              s, bt));
     HIPCHK(hipMemsetAsync(u, 0, (size_t)nrhs * N * sizeof(cplx), s));
 
-    // The Givens step of column j runs inside the first V-cycle leg of step
-    // j + 1 when the multigrid path is taken; the last column's (or one whose
-    // next step is not enqueued) runs as a kernel of its own.
-    const bool fold = !no_prec && p->ndim == 2 && p->levels.size() >= 2 &&
-                      m <= (f32 ? vc_fine_down_givens_capacity(op_Mf(p))
-                                : vc_fine_down_givens_capacity(op_M(p)));
-    const GivensArgs giv{st, h1, h2, partial, L.nbS, R, cs, sn, g, drec, dhist,
-                         (int64_t)L.total, p->hist_stride};
+    // Arnoldi with delayed reorthogonalisation: step j preconditions and applies
+    // H to u_j = V_j (projected once, not yet normalised), reduces the
+    // projections of u_j and w = H z_j on V_0..V_j in one pass, then one pass
+    // over the basis normalises v_j and projects w into V_{j+1}; the Givens
+    // step of column j - 1 runs as an extra workgroup of that pass (column j - 1
+    // needs step j's reorthogonalisation coefficients). A full cycle ends with
+    // the projections of u_m and the Givens step of column m - 1.
+    const GivensArgs giv{st, h1, h2, R, cs, sn, g, drec, dhist, (int64_t)L.total,
+                         p->hist_stride};
+    cplx* red = h1;
 
     std::vector<std::vector<int>> executed;   // Arnoldi steps that did work, per cycle and RHS
     double min_est = 1.0;
     auto est_of = [&](int rb) { return ((const volatile HostRecord*)(p->rec + rb))->est; };
     for (int cycle = 1;; ++cycle) {
         p->kt.cycle = cycle;
-        HIPCHK(launch_residual_norm(H, b, u, w, partial, &st->done, s, bt));
+        HIPCHK(launch_residual_norm(H, b, u, V, partial, &st->done, s, bt));   // u_0 = r
         HIPCHK(launch_cycle_start(st, partial, L.nbA, g, drec, s, bt));
         // close to convergence: learn whether this cycle opens before enqueuing it
         if (min_est <= tol)
             CHK(wait_for(p, nrhs, s,
                          [&](const RecView& r) { return r.done || r.cycles >= cycle; }));
-        bool givens_pending = false;
         bool closed = false;
         for (int j = 0; j < m; ++j) {
             if (j >= kLookahead)
@@ -1065,41 +1051,40 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
             }
             p->kt.j = j;
             const int kk = j + 1;
-            cplx* vj = V + (size_t)j * N;
-            const GivensArgs* gv = givens_pending ? &giv : nullptr;
+            cplx* uj = V + (size_t)j * N;
             if (no_prec) {
-                HIPCHK(launch_normalize_pred(w, st, vj, N, s, bt));
-                TIMED(HH_KERNEL_APPLY_DOT, (40.0 + 16.0 * kk) * (double)N,
-                      launch_apply_dot(H, vj, w, V, kk, partial, active, s, bt));
+                // z_j = u_j: kept in Z (V_j is normalised in place below)
+                cplx* zz = Z + (size_t)j * N;
+                HIPCHK(hipMemcpy2DAsync(zz, L.total, uj, L.total, (size_t)N * sizeof(cplx), nrhs,
+                                        hipMemcpyDeviceToDevice, s));
+                TIMED2(HH_KERNEL_APPLY_DOT, (32.0 + 16.0 * kk) * (double)N, 8.0 * (double)N,
+                       launch_apply_dot(H, zz, w, V, kk, partial, active, s, bt));
             } else if (f32) {
                 cplxf* zz = Zf + (size_t)j * N;
-                CHK(precond<float>(p, L, ws, w, st, vj, zz, s, gv, bt));
+                CHK(precond<float>(p, L, ws, uj, active, zz, s, bt));
                 TIMED2(HH_KERNEL_APPLY_DOT, (24.0 + 16.0 * kk) * (double)N, 8.0 * (double)N,
                        launch_apply_dot(H, zz, w, V, kk, partial, active, s, bt));
             } else {
                 cplx* zz = Z + (size_t)j * N;
-                CHK(precond<double>(p, L, ws, w, st, vj, zz, s, gv, bt));
+                CHK(precond<double>(p, L, ws, uj, active, zz, s, bt));
                 TIMED2(HH_KERNEL_APPLY_DOT, (32.0 + 16.0 * kk) * (double)N, 8.0 * (double)N,
                        launch_apply_dot(H, zz, w, V, kk, partial, active, s, bt));
             }
-            givens_pending = false;
-            TIMED(HH_KERNEL_REDUCE, 16.0 * kk * (L.nbA + 1),
-                  launch_reduce_pred(partial, L.nbA, kk, h1, active, s, bt));
-            TIMED(HH_KERNEL_AXPY_DOT, (kk + 2) * 16.0 * (double)N,
-                  launch_axpy_dot(V, N, kk, h1, w, partial, active, s, bt));
-            TIMED(HH_KERNEL_REDUCE, 16.0 * kk * (L.nbN + 1),
-                  launch_reduce_pred(partial, L.nbN, kk, h2, active, s, bt));
-            TIMED(HH_KERNEL_AXPY_NORM, (kk + 2) * 16.0 * (double)N,
-                  launch_axpy_norm(V, N, kk, h2, w, partial, active, s, bt));
-            if (fold) {
-                givens_pending = true;
-            } else {
-                TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbS, launch_givens_step(giv, s, bt));
-            }
+            TIMED(HH_KERNEL_REDUCE, 16.0 * 2 * kk * (L.nbA + 1),
+                  launch_reduce_pred(partial, L.nbA, 2 * kk, red, active, s, bt));
+            // V_0..V_{j-1}, u_j and w in; v_j and u_{j+1} out
+            TIMED(HH_KERNEL_AXPY_DOT, (j + 4) * 16.0 * (double)N,
+                  launch_axpy_dcgs(V, N, j, red, w, active, &giv, s, bt));
         }
-        // a pending step after a break belongs to a cycle the device has closed
-        if (givens_pending && !closed)
-            TIMED(HH_KERNEL_GIVENS, 16.0 * L.nbS, launch_givens_step(giv, s, bt));
+        if (!closed) {
+            // a full cycle: projections of u_m on the basis and its norm, then
+            // the Givens step of the last column
+            TIMED(HH_KERNEL_AXPY_NORM, (m + 2) * 16.0 * (double)N,
+                  launch_dot_blocks(V, N, m + 1, V + (size_t)m * N, partial, s, bt));
+            TIMED(HH_KERNEL_REDUCE, 16.0 * (m + 1) * (L.nbN + 1),
+                  launch_reduce_pred(partial, L.nbN, m + 1, red, active, s, bt));
+            TIMED(HH_KERNEL_GIVENS, 16.0 * (m + 1), launch_givens_tail(giv, s, bt));
+        }
         // the cycle closes on a step for every right-hand side (or they ended at its start)
         CHK(wait_for(p, nrhs, s, [&](const RecView& r) { return r.done || r.stops >= cycle; }));
         std::vector<int> ex(nrhs, 0);
@@ -1117,7 +1102,7 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
         if (f32)
             HIPCHK(launch_cycle_finish(st, R, g, y, Zf, N, u, s, bt));
         else
-            HIPCHK(launch_cycle_finish(st, R, g, y, no_prec ? V : Z, N, u, s, bt));
+            HIPCHK(launch_cycle_finish(st, R, g, y, Z, N, u, s, bt));
         if (all_done) break;                        // non-finite values inside the cycle
     }
     HIPCHK(hipStreamSynchronize(s));

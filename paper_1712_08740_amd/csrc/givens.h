@@ -1,35 +1,17 @@
-// Device-side pieces of the Givens least-squares update shared by the
-// stand-alone Givens kernel and the V-cycle kernel that hosts the step as one
-// extra workgroup (so the update overlaps the next step's first leg instead
-// of taking a launch of its own).
+// Device-side pieces of the Arnoldi step with delayed reorthogonalisation and
+// of the Givens least-squares update, shared by the kernel that hosts the
+// Givens step as one extra workgroup and the stand-alone kernel that closes a
+// cycle.
 #pragma once
 
 #include "hh_internal.h"
 
 namespace hh {
 
-// Sum of partial[t].x for t < nb, computed by the 64 lanes of one wavefront in
-// a fixed order (lane-strided sums, then an xor butterfly, so every lane ends
-// with the same bits). Callers that must agree on a norm (the Givens step and
-// the kernel that normalises the next basis vector) both use this.
-__device__ __forceinline__ double wave_sum_re(const cplx* __restrict__ partial, int nb, int lane) {
-    double acc = 0.0;
-    for (int t = lane; t < nb; t += 64) acc += partial[t].x;
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    return acc;
-}
-
-// 1 / ||w|| from the sum of squares, 0 for a zero vector (breakdown)
-__device__ __forceinline__ double inv_norm(double sumsq) {
-    return sumsq > 0.0 ? 1.0 / sqrt(sumsq) : 0.0;
-}
-
 struct GivensArgs {
     SolveState* st;           // nullptr: no Givens step in this launch
-    const cplx* h1;           // first projections of the column
-    const cplx* h2;           // second projections
-    const cplx* partial;      // per-block sums of |w|^2 (first nb entries, .x)
-    int nb;
+    const cplx* red;          // reduced projections of this step: [V^H u, V^H w]
+    cplx* hprev;              // previous step's projections of w and h_jj
     cplx* R;                  // (m + 1) x m triangular factor, column-major
     double* cs;               // rotations
     cplx* sn;
@@ -40,22 +22,72 @@ struct GivensArgs {
     int64_t hist_stride;      // entries between the histories of consecutive right-hand sides
 };
 
-// Capacity (in columns) of LDS staging a caller provides: scol holds
-// cap + 2 complex values, scs and ssn cap values each.
-//
-// Givens step on column j of the Hessenberg matrix (the least-squares part of
-// GMRES, Eq. 7's outer solver): column = h1 + h2 with h_{j+1,j} = ||w||, the
-// previous rotations applied, a new rotation that zeroes h_{j+1,j}, the rotated
-// right-hand side, the residual estimate |g_{j+1}| / beta0 and the decision to
-// stop the cycle. Called by every thread of one workgroup (blockDim >= 64)
-// for right-hand side rb.
-__device__ inline void givens_body(const GivensArgs& ga, int rb, cplx* scol, double* scs,
-                                   cplx* ssn) {
+// Sum over i < n of f(i) by the 64 lanes of wavefront 0 in a fixed order
+// (lane-strided partial sums, then an xor butterfly: every lane of wave 0
+// ends with the same bits).
+template <class F>
+__device__ __forceinline__ cplx wave_csum(int n, int lane, F f) {
+    cplx acc = mk(0.0, 0.0);
+    for (int i = lane; i < n; i += 64) acc = cadd(acc, f(i));
+    for (int o = 32; o > 0; o >>= 1) {
+        acc.x += __shfl_xor(acc.x, o, 64);
+        acc.y += __shfl_xor(acc.y, o, 64);
+    }
+    return acc;
+}
+
+// Coefficients of the Arnoldi step with delayed reorthogonalisation, from the
+// reduced projections red = [a_0..a_{j-1}, alpha, b_0..b_{j-1}, gamma] of
+// u = V_j (a = V^H u, alpha = u^H u, b = V^H w, gamma = u^H w over the
+// previous basis V_0..V_{j-1}; w = A z_j):
+//   nu   = ||u - V a|| = sqrt(alpha - |a|^2)        (Pythagoras)
+//   h_jj = v_j^H w = (gamma - a^H b) / nu
+//   c    = b - a h_jj / nu,  d = h_jj / nu
+// Every block computes them in the same fixed order. sa[i] = a_i,
+// sc[i] = c_i; *inv_nu = 1/nu (0 when nu = 0), *d, *h = h_jj (thread 0).
+__device__ inline void dcgs_coeffs(const cplx* red, int j, cplx* sa, cplx* sc, double* inv_nu,
+                                   cplx* d, cplx* h, double* nu_out) {
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    const int nt = blockDim.x * blockDim.y;
+    for (int i = tid; i < j; i += nt) sa[i] = red[i];
+    __syncthreads();
+    if (tid < 64) {
+        const cplx saa = wave_csum(j, tid, [&](int i) { return mk(cabs2(sa[i]), 0.0); });
+        const cplx sab = wave_csum(j, tid, [&](int i) { return cmulc(sa[i], red[j + 1 + i]); });
+        if (tid == 0) {
+            const double nu2 = red[j].x - saa.x;
+            const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+            const double inu = nu > 0.0 ? 1.0 / nu : 0.0;
+            const cplx hh = cscale(csub(red[2 * j + 1], sab), inu);
+            *inv_nu = inu;
+            *h = hh;
+            *d = cscale(hh, inu);
+            *nu_out = nu;
+        }
+    }
+    __syncthreads();
+    const cplx dd = *d;
+    for (int i = tid; i < j; i += nt) sc[i] = csub(red[j + 1 + i], cmul(sa[i], dd));
+}
+
+// Givens step of the delayed-reorthogonalisation Arnoldi process (the
+// least-squares part of GMRES, Eq. 7's outer solver), run at step j by every
+// thread of one workgroup for right-hand side rb. Column j-1 of the Hessenberg
+// matrix becomes known here: entries i <= j-1 are the previous step's
+// projections (hprev) plus this step's reorthogonalisation coefficients a_i,
+// and the subdiagonal is nu. The previous rotations are applied, a new one
+// zeroes the subdiagonal, and g, the residual estimate |g_j| / beta0 and the
+// stop decision follow (estimate at tol, budget spent, breakdown, non-finite).
+// At j = 0 there is no column yet: g_0 = nu (the cycle's initial residual).
+// With tail set (after the last step of a cycle, red holding only
+// [V^H u, u^H u]) column j-1 is the last of the cycle and the cycle stops.
+// LDS: sa, sc of j+2 complex each, scol of j+2 complex, scs of j+2 doubles.
+__device__ inline void givens_dcgs(const GivensArgs& ga, int rb, bool tail, cplx* sa, cplx* sc,
+                                   cplx* scol, double* scs) {
     GivensArgs a = ga;                 // this right-hand side's state
     a.st = rhs_nn(ga.st, rb, ga.bs);
-    a.h1 = rhs_nn(ga.h1, rb, ga.bs);
-    a.h2 = rhs_nn(ga.h2, rb, ga.bs);
-    a.partial = rhs_nn(ga.partial, rb, ga.bs);
+    a.red = rhs_nn(ga.red, rb, ga.bs);
+    a.hprev = rhs_nn(ga.hprev, rb, ga.bs);
     a.R = rhs_nn(ga.R, rb, ga.bs);
     a.cs = rhs_nn(ga.cs, rb, ga.bs);
     a.sn = rhs_nn(ga.sn, rb, ga.bs);
@@ -67,25 +99,58 @@ __device__ inline void givens_body(const GivensArgs& ga, int rb, cplx* scol, dou
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     const int nt = blockDim.x * blockDim.y;
     const int j = st->j;
-    double hn2 = 0.0;
-    if (tid < 64) hn2 = wave_sum_re(a.partial, a.nb, tid);
-    for (int i = tid; i <= j; i += nt) scol[i] = cadd(a.h1[i], a.h2[i]);
-    for (int i = tid; i < j; i += nt) {
-        scs[i] = a.cs[i];
-        ssn[i] = a.sn[i];
+    __shared__ double s_inv_nu, s_nu;
+    __shared__ cplx s_d, s_h;
+    if (tail) {
+        // red = [a_0..a_{j-1}, alpha] only
+        for (int i = tid; i < j; i += nt) sa[i] = a.red[i];
+        __syncthreads();
+        if (tid < 64) {
+            const cplx saa = wave_csum(j, tid, [&](int i) { return mk(cabs2(sa[i]), 0.0); });
+            if (tid == 0) {
+                const double nu2 = a.red[j].x - saa.x;
+                s_nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+            }
+        }
+        __syncthreads();
+    } else {
+        dcgs_coeffs(a.red, j, sa, sc, &s_inv_nu, &s_d, &s_h, &s_nu);
+    }
+    // stage column j-1 and the previous rotations
+    for (int i = tid; i < j; i += nt) scol[i] = cadd(a.hprev[i], sa[i]);
+    for (int i = tid; i + 1 < j; i += nt) scs[i] = a.cs[i];
+    // (sc is free once its c_i are no longer needed: the sines go there)
+    __syncthreads();
+    cplx* ssn = sc;
+    if (!tail) {
+        // keep this step's w-projections and h_jj for the next column
+        for (int i = tid; i < j; i += nt) a.hprev[i] = a.red[j + 1 + i];
     }
     __syncthreads();
+    for (int i = tid; i + 1 < j; i += nt) ssn[i] = a.sn[i];
+    __syncthreads();
     if (tid != 0) return;
-    const int ld = st->m + 1;
-    cplx* col = scol;
-    const double hn = sqrt(hn2);
-    col[j + 1] = mk(hn, 0.0);
-    for (int i = 0; i < j; ++i) {
-        const cplx p = col[i], q = col[i + 1];
-        col[i] = cadd(cscale(p, scs[i]), cmul(ssn[i], q));
-        col[i + 1] = csub(cscale(q, scs[i]), cmulc(ssn[i], p));
+    const double hn = s_nu;
+    if (!tail) a.hprev[j] = s_h;
+    if (j == 0) {                      // first step of the cycle: no column yet
+        a.g[0] = mk(hn, 0.0);
+        st->j = 1;
+        st->k = 0;
+        HostRecord* rec = a.rec;
+        rec->jstep = 1;
+        __threadfence_system();
+        rec->seq += 1;
+        return;
     }
-    const cplx av = col[j];
+    const int col = j - 1;             // the column completed at this step
+    const int ld = st->m + 1;
+    scol[j] = mk(hn, 0.0);
+    for (int i = 0; i < col; ++i) {
+        const cplx p = scol[i], q = scol[i + 1];
+        scol[i] = cadd(cscale(p, scs[i]), cmul(ssn[i], q));
+        scol[i + 1] = csub(cscale(q, scs[i]), cmulc(ssn[i], p));
+    }
+    const cplx av = scol[col];
     double c;
     cplx s;
     if (hn == 0.0) {
@@ -100,23 +165,22 @@ __device__ inline void givens_body(const GivensArgs& ga, int rb, cplx* scol, dou
         c = aa / t;
         s = cscale(mk(av.x / aa, av.y / aa), hn / t);
     }
-    a.cs[j] = c;
-    a.sn[j] = s;
-    col[j] = cadd(cscale(av, c), cscale(s, hn));
-    col[j + 1] = mk(0.0, 0.0);
-    cplx* Rcol = a.R + (int64_t)j * ld;
-    for (int i = 0; i <= j + 1; ++i) Rcol[i] = col[i];
-    const cplx gj = a.g[j];
-    a.g[j + 1] = csub(mk(0.0, 0.0), cmulc(s, gj));
-    a.g[j] = cscale(gj, c);
-    const double est = sqrt(cabs2(a.g[j + 1])) / st->beta0;
+    a.cs[col] = c;
+    a.sn[col] = s;
+    scol[col] = cadd(cscale(av, c), cscale(s, hn));
+    scol[col + 1] = mk(0.0, 0.0);
+    cplx* Rcol = a.R + (int64_t)col * ld;
+    for (int i = 0; i <= col + 1; ++i) Rcol[i] = scol[i];
+    const cplx gj = a.g[col];
+    a.g[col + 1] = csub(mk(0.0, 0.0), cmulc(s, gj));
+    a.g[col] = cscale(gj, c);
+    const double est = sqrt(cabs2(a.g[col + 1])) / st->beta0;
     const int it = st->it + 1;
     const int bad = !(isfinite(est) && isfinite(hn));
-    const int stop = bad || hn == 0.0 || est <= st->tol || it >= st->max_iters || j + 1 >= st->m;
+    const int stop = tail || bad || hn == 0.0 || est <= st->tol || it >= st->max_iters;
     st->it = it;
     st->j = j + 1;
-    st->k = j + 1;
-    st->scale = inv_norm(hn2);
+    st->k = col + 1;
     if (stop) __hip_atomic_store(&st->active, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (bad) {
         st->done = 1;
@@ -126,7 +190,7 @@ __device__ inline void givens_body(const GivensArgs& ga, int rb, cplx* scol, dou
     a.hist[it] = est;
     rec->it = it;
     rec->est = est;
-    rec->jstep = j + 1;
+    rec->jstep = tail ? j : j + 1;
     rec->status = st->status;
     __threadfence_system();          // the fields above are visible before the flags
     if (stop) rec->stops += 1;

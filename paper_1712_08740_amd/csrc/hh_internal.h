@@ -293,7 +293,8 @@ struct HostRecord {
 
 
 // ---- fused, predicated Arnoldi kernels (krylov.hip) -----------------------
-// w = H z and partial[i*nb + blk] = block sums of conj(V_i) w (nb = apply_blocks)
+// w = H z and, with u = V_{k-1}, partial[i*nb + blk] = block sums of conj(V_i) u
+// and partial[(k+i)*nb + blk] = block sums of conj(V_i) w, i < k (nb = apply_blocks)
 hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx* V, int k,
                             cplx* partial, const int* active, hipStream_t s,
                             const Batch& bt = Batch());
@@ -322,7 +323,15 @@ hipError_t launch_residual_norm(const FineOp& op, const cplx* b, const cplx* u, 
 hipError_t launch_cycle_start(SolveState* st, const cplx* partial, int nb, cplx* g,
                               HostRecord* rec, hipStream_t s, const Batch& bt = Batch());
 struct GivensArgs;
-hipError_t launch_givens_step(const GivensArgs& a, hipStream_t s, const Batch& bt = Batch());
+// Arnoldi step with delayed reorthogonalisation, second pass (see krylov.hip):
+// V_j <- reorthogonalised, normalised u = V_j; V_{j+1} <- w projected once;
+// red = the reduced [V_{0..j}^H u, V_{0..j}^H w]; with giv, one extra
+// workgroup per right-hand side runs the Givens step of column j - 1
+hipError_t launch_axpy_dcgs(cplx* V, int64_t n, int j, const cplx* red, const cplx* w,
+                            const int* active, const GivensArgs* giv, hipStream_t s,
+                            const Batch& bt = Batch());
+// the Givens step closing a full cycle (red = [V_{0..m-1}^H V_m, V_m^H V_m])
+hipError_t launch_givens_tail(const GivensArgs& a, hipStream_t s, const Batch& bt = Batch());
 // y = R^{-1} g, x += Z y for the st->k columns of the cycle, then st->k = 0
 hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
                                const cplx* Z, int64_t n, cplx* x, hipStream_t s,
@@ -330,8 +339,6 @@ hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cpl
 hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
                                const cplxf* Z, int64_t n, cplx* x, hipStream_t s,
                                const Batch& bt = Batch());
-hipError_t launch_normalize_pred(const cplx* w, const SolveState* st, cplx* v, int64_t n,
-                                 hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
                              double tol, HostRecord* rec, double* hist, int64_t hist_stride,
                              hipStream_t s, const Batch& bt = Batch());
@@ -358,23 +365,13 @@ hipError_t launch_vc_gemm(int n, const cplxf* A, const cplxf* x, cplxf* y, void*
 // temporally blocked legs (vcycle_tiled.hip): down = two pre-sweeps from zero,
 // residual and restriction; up = prolongation and two post-sweeps
 // (the smoother weight enters through op.wdinv = omega_J / diag).
-// The fine down leg normalises its input: v = s * src is written to bout and
-// the outputs are those of v, with s = *scale, or s = 1/||src|| from the
-// per-block sums of |src|^2 in npart (nbn entries) when npart is given. With
-// giv non-null and giv->st set, one extra workgroup per right-hand side
-// performs that Givens step (restart length at most
-// vc_fine_down_givens_capacity(op)).
-hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, const double* scale,
-                               const cplx* npart, int nbn, cplx* bout, cplx* x2, int hz, int hx,
-                               int nzc, int nxc, cplx* bc, const int* active,
-                               const GivensArgs* giv, hipStream_t s, const Batch& bt = Batch());
-int vc_fine_down_givens_capacity(const FineOp& op);
-// single-precision cycle: the Krylov vector (src, bout) stays complex128
-hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, const double* scale,
-                               const cplx* npart, int nbn, cplx* bout, cplxf* x2, int hz, int hx,
-                               int nzc, int nxc, cplxf* bc, const int* active,
-                               const GivensArgs* giv, hipStream_t s, const Batch& bt = Batch());
-int vc_fine_down_givens_capacity(const FineOpT<float>& op);
+hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, cplx* x2, int hz, int hx,
+                               int nzc, int nxc, cplx* bc, const int* active, hipStream_t s,
+                               const Batch& bt = Batch());
+// single-precision cycle: the Krylov vector src stays complex128
+hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, cplxf* x2, int hz,
+                               int hx, int nzc, int nxc, cplxf* bc, const int* active,
+                               hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_coarse_down(const CoarseOpT<float>& op, const cplxf* b, cplxf* x2, int hz,
                                  int hx, int nzc, int nxc, cplxf* bc, const int* active,
                                  hipStream_t s, const Batch& bt = Batch());

@@ -108,8 +108,11 @@ __device__ __forceinline__ void block_dots(const cplx* V, int64_t n, int k, bool
 
 __device__ __forceinline__ bool off(const int* active) { return active && *active == 0; }
 
-// w = H z (fine operator) and the first projections V^H w; for k <= KMAX the
-// basis values are loaded up front (all in flight together)
+// w = H z (fine operator) and the projections of the Arnoldi step with
+// delayed reorthogonalisation: with u = V_{k-1} (the new, not yet
+// reorthogonalised vector), partial[i] = block sums of conj(V_i) u and
+// partial[k + i] = block sums of conj(V_i) w, i < k. For k <= KMAX the basis
+// values are loaded up front (all in flight together).
 template <int NDIM, int KMAX, class ZC>
 __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const ZC* __restrict__ z,
                                                    cplx* __restrict__ w,
@@ -145,6 +148,7 @@ __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const ZC* __restri
         for (int i = 0; i < KMAX; ++i)
             v[i] = (valid && i < k) ? V[(int64_t)i * n + p] : mk(0.0, 0.0);
     }
+    const cplx up = valid ? V[(int64_t)(k - 1) * n + p] : mk(0.0, 0.0);
     cplx wp = mk(0.0, 0.0);
     if (valid) {
         const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
@@ -163,18 +167,24 @@ __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const ZC* __restri
     }
     if (KMAX > 0) {
 #pragma unroll
-        for (int c0 = 0; c0 < KMAX; c0 += KC) {
-            if (c0 >= k) break;
-            cplx d[KC];
+        for (int set = 0; set < 2; ++set) {
+            const cplx x = set == 0 ? up : wp;
 #pragma unroll
-            for (int c = 0; c < KC; ++c) d[c] = cmulc(v[c0 + c], wp);
-            cplx sum;
-            int idx;
-            block_multi_sum(d, lds, tid, &sum, &idx);
-            if (idx >= 0 && c0 + idx < k) partial[(int64_t)(c0 + idx) * nb + blk] = sum;
+            for (int c0 = 0; c0 < KMAX; c0 += KC) {
+                if (c0 >= k) break;
+                cplx d[KC];
+#pragma unroll
+                for (int c = 0; c < KC; ++c) d[c] = cmulc(v[c0 + c], x);
+                cplx sum;
+                int idx;
+                block_multi_sum(d, lds, tid, &sum, &idx);
+                if (idx >= 0 && c0 + idx < k)
+                    partial[(int64_t)(set * k + c0 + idx) * nb + blk] = sum;
+            }
         }
     } else {
-        block_dots(V, n, k, valid, p, wp, partial, nb, blk, lds, tid);
+        block_dots(V, n, k, valid, p, up, partial, nb, blk, lds, tid);
+        block_dots(V, n, k, valid, p, wp, partial + (int64_t)k * nb, nb, blk, lds, tid);
     }
 }
 
@@ -259,6 +269,81 @@ __global__ void __launch_bounds__(256) k_axpy_dot(const cplx* __restrict__ V, in
         }
         block_dots(V, n, k, valid, pp, wp, partial, nb, blk, lds, tid);
     }
+}
+
+// Second pass of the Arnoldi step with delayed reorthogonalisation (one pass
+// over the basis): from the reduced projections red = [V^H u, V^H w] (u =
+// V_j, 2(j+1) values) every block derives (dcgs_coeffs) nu = ||u - V a||, the
+// new Hessenberg entry h_jj = v_j^H w and c = b - a h_jj / nu, then
+//   V_j     <- (u - sum_i a_i V_i) / nu          (the reorthogonalised v_j)
+//   V_{j+1} <- w - sum_i c_i V_i - (h_jj / nu) u  (w projected once: the next u)
+// With giv.st set, one extra workgroup performs the Givens step of column j-1
+// (which needed this step's reorthogonalisation coefficients).
+// LDS (dynamic): 3 (j + 2) complex + (j + 2) doubles.
+template <int KMAX>
+__global__ void __launch_bounds__(256) k_axpy_dcgs(cplx* __restrict__ V, int64_t n, int j,
+                                                   const cplx* __restrict__ red,
+                                                   const cplx* __restrict__ w,
+                                                   const int* __restrict__ active, int64_t bs,
+                                                   int nbn, GivensArgs giv) {
+    extern __shared__ cplx dsm[];
+    cplx* sa = dsm;
+    cplx* sc = dsm + (j + 2);
+    const int rb = blockIdx.y;
+    if ((int)blockIdx.x == nbn) {                 // the hosted Givens step (column j - 1)
+        givens_dcgs(giv, rb, false, sa, sc, dsm + 2 * (j + 2),
+                    reinterpret_cast<double*>(dsm + 3 * (j + 2)));
+        return;
+    }
+    // read atomically: the Givens workgroup of this launch may clear it
+    active = rhs_at(active, rb, bs);
+    if (active && __hip_atomic_load(const_cast<int*>(active), __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) == 0)
+        return;
+    V = rhs_nn(V, rb, bs);
+    red = rhs_nn(red, rb, bs);
+    w = rhs_nn(w, rb, bs);
+    const int tid = threadIdx.x;
+    __shared__ double s_inv_nu, s_nu;
+    __shared__ cplx s_d, s_h;
+    // a_i, c_i and the scalars, identical in every block (fixed-order sums)
+    dcgs_coeffs(red, j, sa, sc, &s_inv_nu, &s_d, &s_h, &s_nu);
+    __syncthreads();
+    const double inv_nu = s_inv_nu;
+    const cplx dd = s_d;
+    const int64_t p = (int64_t)blockIdx.x * 256 + tid;
+    if (p >= n) return;
+    const cplx up = V[(int64_t)j * n + p];
+    const cplx wp = w[p];
+    cplx acc_v = up, acc_u = csub(wp, cmul(dd, up));
+    if (KMAX > 0 && j <= KMAX) {
+        cplx v[KMAX > 0 ? KMAX : 1];
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) v[i] = i < j ? V[(int64_t)i * n + p] : mk(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i) {
+            if (i < j) {
+                acc_v = csub(acc_v, cmul(sa[i], v[i]));
+                acc_u = csub(acc_u, cmul(sc[i], v[i]));
+            }
+        }
+    } else {
+        for (int c0 = 0; c0 < j; c0 += KC) {
+            cplx v[KC];
+#pragma unroll
+            for (int c = 0; c < KC; ++c)
+                v[c] = (c0 + c < j) ? V[(int64_t)(c0 + c) * n + p] : mk(0.0, 0.0);
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                if (c0 + c < j) {
+                    acc_v = csub(acc_v, cmul(sa[c0 + c], v[c]));
+                    acc_u = csub(acc_u, cmul(sc[c0 + c], v[c]));
+                }
+            }
+        }
+    }
+    V[(int64_t)j * n + p] = cscale(acc_v, inv_nu);
+    V[(int64_t)(j + 1) * n + p] = acc_u;
 }
 
 // w -= V h, then ||w||^2 per block. At most kNormBlocks blocks (grid-stride
@@ -414,12 +499,12 @@ __global__ void __launch_bounds__(256) k_cycle_start(SolveState* st, const cplx*
     __threadfence_system();
 }
 
-// Givens step on column j as a kernel of its own (single block)
-__global__ void __launch_bounds__(256) k_givens_step(GivensArgs a) {
-    __shared__ cplx scol[kMaxColumns + 2];
-    __shared__ double scs[kMaxColumns];
-    __shared__ cplx ssn[kMaxColumns];
-    givens_body(a, blockIdx.x, scol, scs, ssn);
+// Givens step that closes a full cycle (column m - 1), from the projections of
+// the last vector u = V_m on the basis (red = [V_0..V_{m-1}^H u, u^H u]).
+__global__ void __launch_bounds__(256) k_givens_tail(GivensArgs a) {
+    __shared__ cplx sa[kMaxColumns + 2], scol[kMaxColumns + 2], sc[kMaxColumns + 2];
+    __shared__ double scs[kMaxColumns + 2];
+    givens_dcgs(a, blockIdx.x, true, sa, sc, scol, scs);
 }
 
 // y = R^{-1} g (k = st->k columns), then u += Z y; one block of 256 threads
@@ -480,21 +565,6 @@ __global__ void __launch_bounds__(256) k_update_pred(const SolveState* st,
 // after the update of a cycle: mark k = 0 so a repeated end-of-cycle is a no-op
 __global__ void k_cycle_end(SolveState* st, int64_t bs) {
     if (threadIdx.x == 0) rhs_at(st, (int)blockIdx.x, bs)->k = 0;
-}
-
-// v_j = s * w (normalisation, used when no preconditioner reads w first)
-__global__ void __launch_bounds__(256) k_normalize_pred(const cplx* __restrict__ w,
-                                                        const SolveState* st,
-                                                        cplx* __restrict__ v, int64_t n,
-                                                        int64_t bs) {
-    const int rb = blockIdx.y;
-    st = rhs_nn(st, rb, bs);
-    if (st->active == 0) return;
-    w = rhs_nn(w, rb, bs);
-    v = rhs_nn(v, rb, bs);
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
-    v[p] = cscale(w[p], st->scale);
 }
 
 // solve prologue: beta0 = ||b|| from partials; sets done when b == 0 or not finite
@@ -647,8 +717,28 @@ hipError_t launch_cycle_start(SolveState* st, const cplx* partial, int nb, cplx*
     HH_LAUNCH(k_cycle_start, dim3(bt.n), dim3(256), 0, s, st, partial, nb, g, rec, bt.bs);
     return hipGetLastError();
 }
-hipError_t launch_givens_step(const GivensArgs& a, hipStream_t s, const Batch& bt) {
-    HH_LAUNCH(k_givens_step, dim3(bt.n), dim3(256), 0, s, a);
+hipError_t launch_givens_tail(const GivensArgs& a, hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_givens_tail, dim3(bt.n), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_axpy_dcgs(cplx* V, int64_t n, int j, const cplx* red, const cplx* w,
+                            const int* active, const GivensArgs* giv, hipStream_t s,
+                            const Batch& bt) {
+    const int nbn = node_blocks(n);
+    const GivensArgs none{};
+    const GivensArgs& g = giv ? *giv : none;
+    const dim3 grid(nbn + (giv ? 1 : 0), bt.n), b(256);
+    const size_t shm = 3 * (size_t)(j + 2) * sizeof(cplx) + (size_t)(j + 2) * sizeof(double);
+    if (j <= 8)
+        HH_LAUNCH(k_axpy_dcgs<8>, grid, b, shm, s, V, n, j, red, w, active, bt.bs, nbn, g);
+    else if (j <= 16)
+        HH_LAUNCH(k_axpy_dcgs<16>, grid, b, shm, s, V, n, j, red, w, active, bt.bs, nbn, g);
+    else if (j <= 32)
+        HH_LAUNCH(k_axpy_dcgs<32>, grid, b, shm, s, V, n, j, red, w, active, bt.bs, nbn, g);
+    else if (j <= 48)
+        HH_LAUNCH(k_axpy_dcgs<48>, grid, b, shm, s, V, n, j, red, w, active, bt.bs, nbn, g);
+    else
+        HH_LAUNCH(k_axpy_dcgs<0>, grid, b, shm, s, V, n, j, red, w, active, bt.bs, nbn, g);
     return hipGetLastError();
 }
 template <class ZC>
@@ -669,11 +759,6 @@ hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cpl
                                const cplxf* Z, int64_t n, cplx* x, hipStream_t s,
                                const Batch& bt) {
     return cycle_finish(st, R, g, y, Z, n, x, s, bt);
-}
-hipError_t launch_normalize_pred(const cplx* w, const SolveState* st, cplx* v, int64_t n,
-                                 hipStream_t s, const Batch& bt) {
-    HH_LAUNCH(k_normalize_pred, dim3(node_blocks(n), bt.n), dim3(256), 0, s, w, st, v, n, bt.bs);
-    return hipGetLastError();
 }
 hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
                              double tol, HostRecord* rec, double* hist, int64_t hist_stride,

@@ -13,7 +13,7 @@
 // The operator of a level is a policy: Fine5 (level 0: the matrix-free
 // 5-point stencil of M with absorbing rows, coefficients from m^2) or Coarse9
 // (Galerkin levels: 9 complex coefficient planes).
-#include "givens.h"
+#include "hh_internal.h"
 
 namespace hh {
 
@@ -118,54 +118,28 @@ __device__ __forceinline__ bool in_grid(int z, int x, int nz, int nx) {
 // axis the fine region of the residual is [2c0 - 1, 2(c0 + TC) - 1], along
 // an unhalved axis [c0, c0 + TC - 1]; x2 needs one more node on each side,
 // x1 (and b, D) two more.
-//
-// The leg is linear in its input, so the normalisation of the Krylov vector
-// (v = s * src) is applied to the outputs only: s comes from *scale, or, when
-// npart is given, from the per-block sums of |src|^2 (s = 1/||src||), and the
-// sweeps run on src while that sum is still in flight. With giv.st set the
-// launch has one workgroup more, which performs the Givens step of the
-// previous Arnoldi column.
 // ---------------------------------------------------------------------------
-// Columns of a Givens step the LDS of a down-leg block can stage: the fields
-// sb, sw and s1 (W1 values of type C each) hold the column (cap + 2 complex128),
-// the cosines and the sines.
-template <class C, int W1>
-constexpr int givens_capacity() { return (int)(W1 * sizeof(C) / sizeof(cplx)) - 2; }
-
-// SC is the type of src and bout: complex128 on the fine level (the Krylov
-// vectors) whatever the precision of the cycle, the level's own type below.
+// SC is the type of src: complex128 on the fine level (the Krylov vector)
+// whatever the precision of the cycle, the level's own type below.
 template <class OP, class SC, int TCX, int TCZ>
 __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
-                                             const double* __restrict__ scale,
-                                             const cplx* __restrict__ npart, int nbn,
-                                             SC* __restrict__ bout,
                                              typename OP::C* __restrict__ x2out,
                                              int hz, int hx, int nzc, int nxc,
                                              typename OP::C* __restrict__ bc, double rscale,
                                              const int* __restrict__ active, int ntx, int ntiles,
-                                             GivensArgs giv, int64_t bs) {
+                                             int64_t bs) {
     typedef typename OP::C C;
     typedef typename OP::real T;
     constexpr int W1X = 2 * TCX + 5, W1Z = 2 * TCZ + 5;   // largest x1 region
-    // 16-byte aligned: the hosted Givens step stages complex128 values here
-    __shared__ __align__(16) C sb[W1X * W1Z];
-    __shared__ __align__(16) C sw[W1X * W1Z];               // omega_J / diag
-    __shared__ __align__(16) C s1[W1X * W1Z];
+    __shared__ C sb[W1X * W1Z];
+    __shared__ C sw[W1X * W1Z];                             // omega_J / diag
+    __shared__ C s1[W1X * W1Z];
     __shared__ C s2[W1X * W1Z];
     __shared__ typename OP::Row srow[W1X * W1Z];           // rows of the x1 region
-    __shared__ double s_scale;
     const int rb = blockIdx.y;                             // right-hand side
-    if ((int)blockIdx.x == ntiles) {                       // the hosted Givens step
-        givens_body(giv, rb, reinterpret_cast<cplx*>(sb), reinterpret_cast<double*>(sw),
-                    reinterpret_cast<cplx*>(s1));
-        return;
-    }
     active = rhs_at(active, rb, bs);
     if (inactive(active)) return;
     src = rhs_nn(src, rb, bs);
-    scale = rhs_at(scale, rb, bs);
-    npart = rhs_at(npart, rb, bs);
-    bout = rhs_at(bout, rb, bs);
     x2out = rhs_nn(x2out, rb, bs);
     bc = rhs_nn(bc, rb, bs);
     const int tile = xcd_tile(blockIdx.x, ntiles);
@@ -200,24 +174,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
             s1[i] = x1;
         }
     }
-    if (npart && threadIdx.x < 64) {
-        const double t = wave_sum_re(npart, nbn, threadIdx.x);
-        if (threadIdx.x == 0) s_scale = inv_norm(t);
-    }
     __syncthreads();
-    const double s = npart ? s_scale : (scale ? scale[0] : 1.0);
-    if (bout) {
-        const int tox = ohx - olx + 1, ton = tox * (ohz - olz + 1);
-        for (int t = threadIdx.x; t < ton; t += NT) {
-            const int qz = olz + t / tox, qx = olx + t % tox;
-            if (qz >= nz || qx >= nx) continue;
-            const int64_t q = (int64_t)qz * nx + qx;
-            if constexpr (sizeof(SC) == sizeof(C))
-                bout[q] = cscale(sb[(qz - oz) * wx + (qx - ox)], s);
-            else
-                bout[q] = cscale(src[q], s);   // full precision of the Krylov vector
-        }
-    }
     // phase 2: x2 on the x1 region shrunk by one node (stored at the same local index)
     const int w2x = wx - 2, n2 = w2x * (wz - 2);
 #pragma unroll
@@ -233,7 +190,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
                 const C ax = A.apply(r, s1, i, wx);
                 x2 = cadd(s1[i], cmul(csub(sb[i], ax), sw[i]));
                 if (qz >= olz && qz <= ohz && qx >= olx && qx <= ohx)
-                    x2out[(int64_t)qz * nx + qx] = cscale(x2, (T)s);
+                    x2out[(int64_t)qz * nx + qx] = x2;
             }
             s2[i] = x2;
         }
@@ -269,7 +226,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
                 acc = cadd(acc, cscale(s1[(lz + dz) * wx + (lx + dx)], w));
             }
         }
-        bc[(int64_t)Iz * nxc + Ix] = cscale(acc, (T)(rscale * s));
+        bc[(int64_t)Iz * nxc + Ix] = cscale(acc, (T)rscale);
     }
 }
 
@@ -407,37 +364,25 @@ bool big_tiles(const OP& A) {
 }
 
 template <class OP, class SC, int TCX, int TCZ>
-hipError_t down_launch(const OP& A, const SC* src, const double* scale, const cplx* npart,
-                       int nbn, SC* bout, typename OP::C* x2, int hz, int hx, int nzc, int nxc,
-                       typename OP::C* bc, const int* active, const GivensArgs& giv,
-                       hipStream_t s, const Batch& bt) {
+hipError_t down_launch(const OP& A, const SC* src, typename OP::C* x2, int hz, int hx, int nzc,
+                       int nxc, typename OP::C* bc, const int* active, hipStream_t s,
+                       const Batch& bt) {
     const int ntx = (nxc + TCX - 1) / TCX, ntz = (nzc + TCZ - 1) / TCZ;
     const int ntiles = ntx * ntz;
-    const dim3 g(ntiles + (giv.st ? 1 : 0), bt.n);
-    HH_LAUNCH((k_down<OP, SC, TCX, TCZ>), g, dim3(NT), 0, s, A, src, scale, npart, nbn, bout, x2,
-              hz, hx, nzc, nxc, bc, inv2dc(hz, hx), active, ntx, ntiles, giv, bt.bs);
+    HH_LAUNCH((k_down<OP, SC, TCX, TCZ>), dim3(ntiles, bt.n), dim3(NT), 0, s, A, src, x2, hz, hx,
+              nzc, nxc, bc, inv2dc(hz, hx), active, ntx, ntiles, bt.bs);
     return hipGetLastError();
 }
 
 // Large tiles (less halo work) for the big 5-point grid; small tiles (more
 // blocks in flight, and room in LDS for the 9-coefficient rows) elsewhere.
 template <class OP, class SC>
-hipError_t down_dispatch(const OP& A, const SC* src, const double* scale, const cplx* npart,
-                         int nbn, SC* bout, typename OP::C* x2, int hz, int hx, int nzc, int nxc,
-                         typename OP::C* bc, const int* active, const GivensArgs& giv,
-                         hipStream_t s, const Batch& bt) {
+hipError_t down_dispatch(const OP& A, const SC* src, typename OP::C* x2, int hz, int hx, int nzc,
+                         int nxc, typename OP::C* bc, const int* active, hipStream_t s,
+                         const Batch& bt) {
     if (big_tiles(A))
-        return down_launch<OP, SC, 16, 4>(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc,
-                                          bc, active, giv, s, bt);
-    return down_launch<OP, SC, 8, 4>(A, src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
-                                     active, giv, s, bt);
-}
-
-template <class OP>
-int down_givens_capacity(const OP& A) {
-    typedef typename OP::C C;
-    return big_tiles(A) ? givens_capacity<C, (2 * 16 + 5) * (2 * 4 + 5)>()
-                        : givens_capacity<C, (2 * 8 + 5) * (2 * 4 + 5)>();
+        return down_launch<OP, SC, 16, 4>(A, src, x2, hz, hx, nzc, nxc, bc, active, s, bt);
+    return down_launch<OP, SC, 8, 4>(A, src, x2, hz, hx, nzc, nxc, bc, active, s, bt);
 }
 
 template <class OP, class SB, int TX, int TZ>
@@ -474,39 +419,26 @@ Coarse9<T> coarse9(const CoarseOpT<T>& op) {
 
 }  // namespace
 
-hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, const double* scale,
-                               const cplx* npart, int nbn, cplx* bout, cplx* x2, int hz, int hx,
-                               int nzc, int nxc, cplx* bc, const int* active,
-                               const GivensArgs* giv, hipStream_t s, const Batch& bt) {
-    const GivensArgs none{};
-    return down_dispatch(fine5(op), src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
-                         active, giv ? *giv : none, s, bt);
+hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, cplx* x2, int hz, int hx,
+                               int nzc, int nxc, cplx* bc, const int* active, hipStream_t s,
+                               const Batch& bt) {
+    return down_dispatch(fine5(op), src, x2, hz, hx, nzc, nxc, bc, active, s, bt);
 }
-hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, const double* scale,
-                               const cplx* npart, int nbn, cplx* bout, cplxf* x2, int hz, int hx,
-                               int nzc, int nxc, cplxf* bc, const int* active,
-                               const GivensArgs* giv, hipStream_t s, const Batch& bt) {
-    const GivensArgs none{};
-    return down_dispatch(fine5(op), src, scale, npart, nbn, bout, x2, hz, hx, nzc, nxc, bc,
-                         active, giv ? *giv : none, s, bt);
-}
-
-int vc_fine_down_givens_capacity(const FineOp& op) { return down_givens_capacity(fine5(op)); }
-int vc_fine_down_givens_capacity(const FineOpT<float>& op) {
-    return down_givens_capacity(fine5(op));
+hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, cplxf* x2, int hz,
+                               int hx, int nzc, int nxc, cplxf* bc, const int* active,
+                               hipStream_t s, const Batch& bt) {
+    return down_dispatch(fine5(op), src, x2, hz, hx, nzc, nxc, bc, active, s, bt);
 }
 
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz, int hx,
                                  int nzc, int nxc, cplx* bc, const int* active, hipStream_t s,
                                  const Batch& bt) {
-    return down_dispatch(coarse9(op), b, nullptr, nullptr, 0, (cplx*)nullptr, x2, hz, hx, nzc,
-                         nxc, bc, active, GivensArgs{}, s, bt);
+    return down_dispatch(coarse9(op), b, x2, hz, hx, nzc, nxc, bc, active, s, bt);
 }
 hipError_t launch_vc_coarse_down(const CoarseOpT<float>& op, const cplxf* b, cplxf* x2, int hz,
                                  int hx, int nzc, int nxc, cplxf* bc, const int* active,
                                  hipStream_t s, const Batch& bt) {
-    return down_dispatch(coarse9(op), b, nullptr, nullptr, 0, (cplxf*)nullptr, x2, hz, hx, nzc,
-                         nxc, bc, active, GivensArgs{}, s, bt);
+    return down_dispatch(coarse9(op), b, x2, hz, hx, nzc, nxc, bc, active, s, bt);
 }
 
 hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b, const cplx* x2,

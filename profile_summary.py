@@ -34,8 +34,9 @@ CLASSES = {
     "vc_up_coarse": ("k_up<Coarse9", ["vcycle_tiled.hip", "hh_internal.h"]),
     "gemv": ("k_gemv_pred", ["coarsest.hip", "hh_internal.h"]),
     "apply_dot": ("k_apply_dot", ["krylov.hip", "hh_internal.h", "givens.h"]),
-    "axpy_dot": ("k_axpy_dot", ["krylov.hip", "hh_internal.h", "givens.h"]),
-    "axpy_norm": ("k_axpy_norm", ["krylov.hip", "hh_internal.h", "givens.h"]),
+    "axpy_dot": ("k_axpy_dcgs", ["krylov.hip", "hh_internal.h", "givens.h"]),
+    "axpy_norm": ("k_dot_blocks", ["krylov.hip", "hh_internal.h", "givens.h"]),
+    "givens": ("k_givens_tail", ["krylov.hip", "hh_internal.h", "givens.h"]),
     "reduce": ("k_reduce_pred", ["krylov.hip", "hh_internal.h", "givens.h"]),
     "pcr": ("k_pcr", ["pcr.hip", "hh_internal.h"]),
 }
