@@ -350,12 +350,9 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
 
 inline double inv2dc(int hz, int hx) { return 1.0 / (double)((hz ? 2 : 1) * (hx ? 2 : 1)); }
 
-// tiles: large grids use larger tiles (less halo work), small grids smaller
-// tiles (more blocks in flight)
-constexpr int64_t kBigLevel = 40000;
+// the up leg on 5-point grids of at least this many nodes takes large tiles
+constexpr int64_t kBigLevel = 200000;
 
-// Large tiles (less halo work) for the big 5-point grid; small tiles (more
-// blocks in flight, and room in LDS for the 9-coefficient rows) elsewhere.
 template <class OP>
 bool big_tiles(const OP& A) {
     if constexpr (sizeof(typename OP::Row) <= 32)
@@ -374,15 +371,15 @@ hipError_t down_launch(const OP& A, const SC* src, typename OP::C* x2, int hz, i
     return hipGetLastError();
 }
 
-// Large tiles (less halo work) for the big 5-point grid; small tiles (more
-// blocks in flight, and room in LDS for the 9-coefficient rows) elsewhere.
+// Tiles of 4 x 4 coarse nodes (an 8 x 8 fine block and its halo) on every
+// level: the legs are latency-bound up to a few 100k nodes, where more blocks in
+// flight beat the extra halo work, and past that the down leg still gains
+// (measured on the 401 x 201 and 1201 x 401 hierarchies).
 template <class OP, class SC>
 hipError_t down_dispatch(const OP& A, const SC* src, typename OP::C* x2, int hz, int hx, int nzc,
                          int nxc, typename OP::C* bc, const int* active, hipStream_t s,
                          const Batch& bt) {
-    if (big_tiles(A))
-        return down_launch<OP, SC, 16, 4>(A, src, x2, hz, hx, nzc, nxc, bc, active, s, bt);
-    return down_launch<OP, SC, 8, 4>(A, src, x2, hz, hx, nzc, nxc, bc, active, s, bt);
+    return down_launch<OP, SC, 4, 4>(A, src, x2, hz, hx, nzc, nxc, bc, active, s, bt);
 }
 
 template <class OP, class SB, int TX, int TZ>
@@ -395,13 +392,14 @@ hipError_t up_launch(const OP& A, int hz, int hx, const SB* b, const typename OP
     return hipGetLastError();
 }
 
+// Up leg: 8 x 4-node tiles, and 32 x 8 (less halo work) on large 5-point grids.
 template <class OP, class SB>
 hipError_t up_dispatch(const OP& A, int hz, int hx, const SB* b, const typename OP::C* x2,
                        const typename OP::C* e, int nxc, typename OP::C* out, const int* active,
                        hipStream_t s, const Batch& bt) {
     if (big_tiles(A))
         return up_launch<OP, SB, 32, 8>(A, hz, hx, b, x2, e, nxc, out, active, s, bt);
-    return up_launch<OP, SB, 16, 4>(A, hz, hx, b, x2, e, nxc, out, active, s, bt);
+    return up_launch<OP, SB, 8, 4>(A, hz, hx, b, x2, e, nxc, out, active, s, bt);
 }
 
 template <class T>

@@ -17,7 +17,8 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libhh.so")
+# the in-tree build; HH_LIB_PATH points at another build of the same sources
+LIB_PATH = os.environ.get("HH_LIB_PATH") or os.path.join(_HERE, "libhh.so")
 
 HH_OK = 0
 HH_NOT_CONVERGED = 1
