@@ -94,7 +94,6 @@ struct hh_problem_s {
     void* band = nullptr;           // banded LU scratch of the coarsest inverse
     void* gemm_part = nullptr;      // partial sums of the batched coarsest product
     size_t gemm_part_bytes = 0;
-    cplx* fin_partial = nullptr;    // block sums for the finiteness check of cinv
     int* dflag = nullptr;           // device scratch for checks
     double* dpartial = nullptr;
     cplx* nrm2_host = nullptr;      // pinned
@@ -310,6 +309,14 @@ T* at(void* base, size_t off) {
 // ---------------------------------------------------------------------------
 // preconditioner
 // ---------------------------------------------------------------------------
+// Grid of level l >= 1 as the legs of level l - 1 see it: the vectors of the
+// coarsest level are in the band numbering of its inverse.
+CGrid coarse_grid(const hh_problem_s* p, int l) {
+    const LevelData& lv = p->levels[l];
+    const bool last = l + 1 == (int)p->levels.size();
+    return CGrid{lv.nz, lv.nx, last && band_renumbered(lv.nz, lv.nx) ? 1 : 0};
+}
+
 // One V(2,2) cycle on level l >= 1: ec_l = V(l, bc_l), one kernel per leg,
 // in precision T, for every right-hand side of the batch.
 template <class T>
@@ -338,12 +345,12 @@ int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* 
     // down: b in, x2 out, the coarser right-hand side out; up: x2, b in, x out,
     // the coarser correction in; both read the 9 coefficients and omega/diag
     TIMED2(HH_KERNEL_VC_DOWN_COARSE, 2.0 * es * nl_ + es * nn_, 10.0 * es * nl_,
-           launch_vc_coarse_down(A, b, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+           launch_vc_coarse_down(A, b, x2, lv.halve_z, lv.halve_x, coarse_grid(p, l + 1),
                                  at<C>(ws, L.bc[l + 1]), active, s, bt));
     CHK(vcycle_coarse<T>(p, L, ws, l + 1, active, s, bt));
     TIMED2(HH_KERNEL_VC_UP_COARSE, 3.0 * es * nl_ + es * nn_, 10.0 * es * nl_,
-           launch_vc_coarse_up(A, lv.halve_z, lv.halve_x, b, x2, at<C>(ws, L.ec[l + 1]), nx.nx, x,
-                               active, s, bt));
+           launch_vc_coarse_up(A, lv.halve_z, lv.halve_x, b, x2, at<C>(ws, L.ec[l + 1]),
+                               coarse_grid(p, l + 1), x, active, s, bt));
     return HH_OK;
 }
 
@@ -377,12 +384,12 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const i
     // x2 in, z out, the coarse correction in; both read m^2 and omega/diag
     // (shared by the right-hand sides)
     TIMED2(HH_KERNEL_VC_DOWN, (16.0 + es) * N + es * N1, (rs + es) * N,
-           launch_vc_fine_down(M, src, x2, lv.halve_z, lv.halve_x, nx.nz, nx.nx,
+           launch_vc_fine_down(M, src, x2, lv.halve_z, lv.halve_x, coarse_grid(p, 1),
                                at<C>(ws, L.bc[1]), active, s, bt));
     CHK(vcycle_coarse<T>(p, L, ws, 1, active, s, bt));
     TIMED2(HH_KERNEL_VC_UP, (16.0 + 2.0 * es) * N + es * N1, (rs + es) * N,
-           launch_vc_fine_up(M, lv.halve_z, lv.halve_x, src, x2, at<C>(ws, L.ec[1]), nx.nx, z,
-                             active, s, bt));
+           launch_vc_fine_up(M, lv.halve_z, lv.halve_x, src, x2, at<C>(ws, L.ec[1]),
+                             coarse_grid(p, 1), z, active, s, bt));
     return HH_OK;
 }
 
@@ -405,11 +412,9 @@ void free_levels(hh_problem_s* p) {
     if (p->cinv) (void)hipFree(p->cinv);
     if (p->cinvf) (void)hipFree(p->cinvf);
     if (p->band) (void)hipFree(p->band);
-    if (p->fin_partial) (void)hipFree(p->fin_partial);
     p->cinv = nullptr;
     p->cinvf = nullptr;
     p->band = nullptr;
-    p->fin_partial = nullptr;
 }
 
 
@@ -459,7 +464,7 @@ int plan_levels(hh_problem_s* p) {
 }
 
 // Device bytes the handle owns for its operators (levels, coarsest inverse
-// and its LU pivots and check partials, m^2 in both precisions, scratch),
+// and the band factorisation scratch, m^2 in both precisions),
 // from a planned hierarchy.
 size_t problem_bytes(const hh_problem_s* p) {
     size_t b = align_up((size_t)p->N * (sizeof(double) + sizeof(float))) + align_up(sizeof(int)) +
@@ -474,8 +479,7 @@ size_t problem_bytes(const hh_problem_s* p) {
         const size_t nc = (size_t)p->nc;
         const LevelData& lc = p->levels.back();
         b += align_up(nc * nc * sizeof(cplx)) + align_up(nc * nc * sizeof(cplxf)) +
-             align_up(band_scratch_bytes(lc.nz, lc.nx)) +
-             align_up((size_t)node_blocks((int64_t)nc * nc) * sizeof(cplx));
+             align_up(band_scratch_bytes(lc.nz, lc.nx));
     }
     return b;
 }
@@ -497,7 +501,6 @@ int build_hierarchy(hh_problem_s* p) {
     HIPCHK(hipMalloc(&p->cinvf, (size_t)nc * nc * sizeof(cplxf)));
     const LevelData& lc = p->levels.back();
     HIPCHK(hipMalloc(&p->band, band_scratch_bytes(lc.nz, lc.nx)));
-    HIPCHK(hipMalloc(&p->fin_partial, (size_t)node_blocks(nc * nc) * sizeof(cplx)));
     return HH_OK;
 }
 
@@ -526,25 +529,17 @@ int apply_shift(hh_problem_s* p) {
         HIPCHK(launch_dense_from_fine(M, p->cinv, s));
     else
         HIPCHK(launch_dense_from_coarse(coarse_op(p->levels.back()), p->cinv, s));
-    // explicit inverse from a banded LU (the coarsest operator is a stencil)
+    // explicit inverse from a banded LU (the coarsest operator is a stencil); with
+    // a coarser level the inverse stays in the band numbering, and the legs of the
+    // level above read and write the coarsest vectors in that numbering
     const LevelData& lc = p->levels.back();
     HIPCHK(hipMemsetAsync(p->dflag, 0, sizeof(int), s));
-    HIPCHK(band_invert(lc.nz, lc.nx, p->cinv, p->band, p->dflag, s));
-    int zero_pivot = 0;
-    HIPCHK(hipMemcpyAsync(&zero_pivot, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(band_invert(lc.nz, lc.nx, p->cinv, p->band, p->dflag, nl == 1, s));
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, p->dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (zero_pivot) return fail(HH_ENUMERIC, "coarsest-level operator is singular for this shift");
-    // the inverse must be finite: sum of |entries|^2
+    if (bad) return fail(HH_ENUMERIC, "coarsest-level operator is singular for this shift");
     const int64_t nn = (int64_t)p->nc * p->nc;
-    const int nb = node_blocks(nn);
-    cplx* partial = p->fin_partial;
-    cplx* out = reinterpret_cast<cplx*>(p->dpartial);
-    HIPCHK(launch_dot_blocks(p->cinv, nn, 1, p->cinv, partial, s));
-    HIPCHK(launch_reduce_pred(partial, nb, 1, out, nullptr, s));
-    HIPCHK(hipMemcpyAsync(p->nrm2_host, out, sizeof(cplx), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (!std::isfinite(p->nrm2_host->x))
-        return fail(HH_ENUMERIC, "coarsest-level operator is singular for this shift");
     // complex64 copies for the single-precision preconditioner
     for (int l = 0; l < nl; ++l) {
         const LevelData& lv = p->levels[l];

@@ -21,8 +21,6 @@ namespace hh {
 namespace {
 
 constexpr int LU_THREADS = 1024;
-constexpr int SOLVE_COLS = 16;      // columns of the inverse per solve workgroup
-constexpr int SOLVE_W = 256;        // circular window of the solve (> b)
 
 struct Numbering {
     int nz, nx;
@@ -79,10 +77,10 @@ __global__ void __launch_bounds__(LU_THREADS) k_band_lu(cplx* __restrict__ AB, i
     }
 }
 
-// Lc[i][t] = L(i+1+t, i), Uc[i][t] = U(i-1-t, i) (0 outside), Ud[i] = U(i, i)
+// Lc[i][t] = L(i+1+t, i), Uc[i][t] = U(i-1-t, i) (0 outside), Ui[i] = 1 / U(i, i)
 __global__ void __launch_bounds__(256) k_band_split(const cplx* __restrict__ AB, int64_t n, int b,
                                                     cplx* __restrict__ Lc, cplx* __restrict__ Uc,
-                                                    cplx* __restrict__ Ud) {
+                                                    cplx* __restrict__ Ui) {
     const int w = 2 * b + 1;
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= n * b) return;
@@ -91,113 +89,187 @@ __global__ void __launch_bounds__(256) k_band_split(const cplx* __restrict__ AB,
     const int64_t rl = i + 1 + t, ru = i - 1 - t;
     Lc[e] = rl < n ? AB[rl * w + (b - 1 - t)] : mk(0.0, 0.0);
     Uc[e] = ru >= 0 ? AB[ru * w + (b + 1 + t)] : mk(0.0, 0.0);
-    if (t == 0) Ud[i] = AB[i * w + b];
+    if (t == 0) Ui[i] = cdiv(mk(1.0, 0.0), AB[i * w + b]);
 }
 
-// Columns c0 .. c0+SOLVE_COLS-1 of (A'^T)^{-1}: forward with unit L from e_c,
-// backward with U, both right-looking over a circular window in LDS; the
-// result (row orig(c) of A^{-1}) is written into Ainv, which holds the forward
-// result in between. The next row's factor entries (and, backward, the
-// forward results) are loaded one step ahead.
-__global__ void __launch_bounds__(64) k_band_solve(const cplx* __restrict__ Lc,
-                                                   const cplx* __restrict__ Uc,
-                                                   const cplx* __restrict__ Ud, int n, int b,
-                                                   Numbering num, cplx* __restrict__ Ainv) {
-    constexpr int C = SOLVE_COLS, W = SOLVE_W, SLOTS = SOLVE_W / 64;
-    __shared__ cplx win[C][W];
+// Columns c0 .. c0+C-1 of M^{-1} (M = L U, the transposed renumbered operator)
+// by forward substitution with the unit lower factor from e_c, then backward
+// substitution with U, both right-looking, by one wavefront. The rows that the
+// current row can still update (at most b below it, or above it going back)
+// stay in registers: rows are taken in blocks of 64, row base + 64 s + lane in
+// slot s of lane `lane`, and when a block is done its slot 0 is written out and
+// the slots shift by one. At each row the lane that owns it passes its C values
+// to the others through LDS; factor entries are loaded D rows ahead. The
+// forward result is kept in `out` and read back by the backward pass.
+//
+// out receives row c0+c of A'^{-1} (A' = M^T): at (c0+c) n + q in the band
+// numbering, or at orig(c0+c) n + orig(q) (the natural numbering of A^{-1})
+// when `natural` is set. flag[0] |= 2 for a non-finite entry of the inverse.
+template <int SLOTS, int C, int D>
+__global__ void __launch_bounds__(64) k_band_inv(const cplx* __restrict__ Lc,
+                                                 const cplx* __restrict__ Uc,
+                                                 const cplx* __restrict__ Ui, int n, int b,
+                                                 Numbering num, int natural,
+                                                 cplx* __restrict__ out, int* __restrict__ flag) {
+    static_assert(64 % D == 0, "D divides the block of 64 rows");
     const int lane = threadIdx.x;
     const int c0 = blockIdx.x * C;
     const int nc = min(C, n - c0);
-    for (int c = 0; c < C; ++c)
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) win[c][lane + 64 * s] = mk(0.0, 0.0);
-    __syncthreads();
-    if (lane < nc) win[lane][(c0 + lane) % W] = mk(1.0, 0.0);
-    const int64_t myrow = lane < nc ? num.orig(c0 + lane) : 0;
-    __syncthreads();
-    auto load_band = [&](const cplx* F, int i, cplx* out) {
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            const int t = lane + 64 * s;
-            out[s] = (i >= 0 && i < n && t < b) ? F[(int64_t)i * b + t] : mk(0.0, 0.0);
-        }
+    __shared__ cplx ybuf[2][C];
+    auto at = [&](int c, int64_t q) -> int64_t {
+        return natural ? num.orig(c0 + c) * (int64_t)n + num.orig(q) : (int64_t)(c0 + c) * n + q;
     };
-    // forward: y = L^{-1} e_c (rows before c are zero)
-    cplx l[SLOTS], ln[SLOTS];
-    load_band(Lc, c0, l);
-    for (int i = c0; i < n; ++i) {
-        load_band(Lc, i + 1, ln);
-        cplx yi[C];
+    cplx acc[SLOTS][C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) yi[c] = c < nc ? win[c][i % W] : mk(0.0, 0.0);
-        __syncthreads();
-        if (lane < nc) {
-            Ainv[myrow * n + num.orig(i)] = yi[lane];
-            win[lane][i % W] = mk(0.0, 0.0);
-        }
+    for (int s = 0; s < SLOTS; ++s)
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            if (c >= nc) continue;
+        for (int c = 0; c < C; ++c)
+            acc[s][c] = mk((s == 0 && lane == c && c < nc) ? 1.0 : 0.0, 0.0);
+
+    // ---- forward: y = L^{-1} e_c, rows c0 .. n-1 (the rows above c0 are zero)
+    // L(row, i) = Lc[i][row - i - 1] for the row of slot s in the block at base
+    auto lval = [&](int i, int base, int s) -> cplx {
+        const int row = base + 64 * s + lane;
+        const int t = row - i - 1;
+        return (i < n && t >= 0 && t < b && row < n) ? Lc[(int64_t)i * b + t] : mk(0.0, 0.0);
+    };
+    cplx fv[D][SLOTS];
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                const int t = lane + 64 * s;
-                if (t < b) {
-                    cplx& y = win[c][(i + 1 + t) % W];
-                    y = csub(y, cmul(l[s], yi[c]));
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) fv[d][s] = lval(c0 + d, c0, s);
+    for (int base = c0; base < n; base += 64) {
+        for (int g = 0; g < 64 && base + g < n; g += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int i = base + g + d;
+                if (i < n) {
+                    if (lane == g + d) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) ybuf[i & 1][c] = acc[0][c];
+                    }
+                    __syncthreads();
+                    cplx l[SLOTS];
+                    const int bn = (g + d + D >= 64) ? base + 64 : base;   // block of row i + D
+#pragma unroll
+                    for (int s = 0; s < SLOTS; ++s) {
+                        l[s] = fv[d][s];
+                        fv[d][s] = lval(i + D, bn, s);
+                    }
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const cplx y = ybuf[i & 1][c];
+#pragma unroll
+                        for (int s = 0; s < SLOTS; ++s)
+                            if (64 * s <= g + d + b) acc[s][c] = csub(acc[s][c], cmul(l[s], y));
+                    }
                 }
             }
         }
+        const int row = base + lane;
+        if (row < n) {
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) l[s] = ln[s];
-        __syncthreads();
-    }
-    // backward: x = U^{-1} y, accumulating the updates of later rows in the window
-    cplx u[SLOTS], un[SLOTS];
-    load_band(Uc, n - 1, u);
-    cplx d = Ud[n - 1];
-    // lane c < nc keeps its own column's forward value of the current row
-    cplx yv = (lane < nc && n - 1 >= c0 + lane) ? Ainv[myrow * n + num.orig(n - 1)]
-                                                : mk(0.0, 0.0);
-    for (int i = n - 1; i >= 0; --i) {
-        load_band(Uc, i - 1, un);
-        const cplx dn = i > 0 ? Ud[i - 1] : mk(1.0, 0.0);
-        const cplx yvn = (lane < nc && i > 0 && i - 1 >= c0 + lane)
-                             ? Ainv[myrow * n + num.orig(i - 1)] : mk(0.0, 0.0);
-        // x_i for every column: lane c computes its own, then all lanes read them
-        if (lane < nc) {
-            const cplx xi = cdiv(cadd(yv, win[lane][i % W]), d);
-            Ainv[myrow * n + num.orig(i)] = xi;
-            win[lane][i % W] = xi;                 // slot i is free after this step: stage x_i
+            for (int c = 0; c < C; ++c)
+                if (c < nc) out[at(c, row)] = acc[0][c];
         }
-        __syncthreads();
-        cplx xi[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) xi[c] = c < nc ? win[c][i % W] : mk(0.0, 0.0);
-        __syncthreads();
-        if (lane < nc) win[lane][i % W] = mk(0.0, 0.0);
+        for (int s = 0; s + 1 < SLOTS; ++s)
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            if (c >= nc) continue;
+            for (int c = 0; c < C; ++c) acc[s][c] = acc[s + 1][c];
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) {
-                const int t = lane + 64 * s;
-                if (t < b && i - 1 - t >= 0) {
-                    cplx& z = win[c][(i - 1 - t + W) % W];
-                    z = csub(z, cmul(u[s], xi[c]));
+        for (int c = 0; c < C; ++c) acc[SLOTS - 1][c] = mk(0.0, 0.0);
+    }
+    // the forward results are read back by other lanes: complete the stores and
+    // read them past the first-level cache
+    __threadfence();
+    __syncthreads();
+    auto yval = [&](int row, int c) -> cplx {
+        if (row < c0 || c >= nc) return mk(0.0, 0.0);
+        double* q = reinterpret_cast<double*>(out + at(c, row));
+        return mk(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                  __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    };
+
+    // ---- backward: x = U^{-1} y, rows n-1 .. 0; row top - 64 s - lane in slot s
+    auto uval = [&](int i, int top, int s) -> cplx {
+        const int row = top - 64 * s - lane;
+        const int t = i - 1 - row;
+        return (i >= 0 && t >= 0 && t < b && row >= 0) ? Uc[(int64_t)i * b + t] : mk(0.0, 0.0);
+    };
+    const int top0 = n - 1;
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[s][c] = yval(top0 - 64 * s - lane, c);
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) fv[d][s] = uval(top0 - d, top0, s);
+    cplx dinv = top0 - lane >= 0 ? Ui[top0 - lane] : mk(0.0, 0.0);
+    bool bad = false;
+    for (int top = top0; top >= 0; top -= 64) {
+        // the slot entering after this block, and the diagonal of the next block
+        cplx ynext[C];
+        const int rn = top - 64 * SLOTS - lane;
+#pragma unroll
+        for (int c = 0; c < C; ++c) ynext[c] = yval(rn, c);
+        const cplx dnext = top - 64 - lane >= 0 ? Ui[top - 64 - lane] : mk(0.0, 0.0);
+        for (int g = 0; g < 64 && top - g >= 0; g += D) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int i = top - g - d;
+                if (i >= 0) {
+                    if (lane == g + d) {
+#pragma unroll
+                        for (int c = 0; c < C; ++c) {
+                            acc[0][c] = cmul(acc[0][c], dinv);
+                            ybuf[i & 1][c] = acc[0][c];
+                        }
+                    }
+                    __syncthreads();
+                    cplx u[SLOTS];
+                    const int tn = (g + d + D >= 64) ? top - 64 : top;     // block of row i - D
+#pragma unroll
+                    for (int s = 0; s < SLOTS; ++s) {
+                        u[s] = fv[d][s];
+                        fv[d][s] = uval(i - D, tn, s);
+                    }
+#pragma unroll
+                    for (int c = 0; c < C; ++c) {
+                        const cplx x = ybuf[i & 1][c];
+#pragma unroll
+                        for (int s = 0; s < SLOTS; ++s)
+                            if (64 * s <= g + d + b) acc[s][c] = csub(acc[s][c], cmul(u[s], x));
+                    }
                 }
             }
         }
+        const int row = top - lane;
+        if (row >= 0) {
 #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) u[s] = un[s];
-        d = dn;
-        yv = yvn;
-        __syncthreads();
+            for (int c = 0; c < C; ++c)
+                if (c < nc) {
+                    const cplx v = acc[0][c];
+                    bad = bad || !(isfinite(v.x) && isfinite(v.y));
+                    out[at(c, row)] = v;
+                }
+        }
+#pragma unroll
+        for (int s = 0; s + 1 < SLOTS; ++s)
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[s][c] = acc[s + 1][c];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[SLOTS - 1][c] = ynext[c];
+        dinv = dnext;
     }
+    if (bad) atomicOr(flag, 2);
 }
 
 }  // namespace
 
 int band_halfwidth(int nz, int nx) { return (nz < nx ? nz : nx) + 1; }
+
+bool band_renumbered(int nz, int nx) { return nz < nx; }
 
 size_t band_scratch_bytes(int nz, int nx) {
     const int64_t n = (int64_t)nz * nx;
@@ -205,22 +277,38 @@ size_t band_scratch_bytes(int nz, int nx) {
     return (size_t)(n * (2 * b + 1) + 2 * n * b + n) * sizeof(cplx);
 }
 
-hipError_t band_invert(int nz, int nx, cplx* A, void* scratch, int* flag, hipStream_t s) {
+template <int SLOTS, int C, int D>
+static void inv_launch(const cplx* Lc, const cplx* Uc, const cplx* Ui, int n, int b, Numbering num,
+                       int natural, cplx* A, int* flag, hipStream_t s) {
+    HH_LAUNCH((k_band_inv<SLOTS, C, D>), dim3((unsigned)((n + C - 1) / C)), dim3(64), 0, s, Lc, Uc,
+              Ui, n, b, num, natural, A, flag);
+}
+
+hipError_t band_invert(int nz, int nx, cplx* A, void* scratch, int* flag, bool natural,
+                       hipStream_t s) {
     const int64_t n = (int64_t)nz * nx;
     const int b = band_halfwidth(nz, nx);
-    if (b >= SOLVE_W || b > 256) return hipErrorInvalidValue;
-    Numbering num{nz, nx, nz < nx};
+    if (b > 255) return hipErrorInvalidValue;
+    Numbering num{nz, nx, band_renumbered(nz, nx)};
     cplx* AB = static_cast<cplx*>(scratch);
     cplx* Lc = AB + n * (2 * b + 1);
     cplx* Uc = Lc + n * b;
-    cplx* Ud = Uc + n * b;
+    cplx* Ui = Uc + n * b;
     HH_LAUNCH(k_band_extract, dim3((unsigned)((n * (2 * b + 1) + 255) / 256)), dim3(256), 0, s, A,
               n, b, num, AB);
     HH_LAUNCH(k_band_lu, dim3(1), dim3(LU_THREADS), 0, s, AB, (int)n, b, flag);
     HH_LAUNCH(k_band_split, dim3((unsigned)((n * b + 255) / 256)), dim3(256), 0, s, AB, n, b, Lc,
-              Uc, Ud);
-    HH_LAUNCH(k_band_solve, dim3((unsigned)((n + SOLVE_COLS - 1) / SOLVE_COLS)), dim3(64), 0, s, Lc,
-              Uc, Ud, (int)n, b, num, A);
+              Uc, Ui);
+    // the window of a block of 64 rows reaches b rows further: 1 + ceil(b / 64) slots
+    const int nat = natural || !num.zfast ? 1 : 0;
+    if (b <= 64)
+        inv_launch<2, 16, 8>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
+    else if (b <= 128)
+        inv_launch<3, 16, 8>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
+    else if (b <= 192)
+        inv_launch<4, 8, 4>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
+    else
+        inv_launch<5, 8, 4>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
     return hipGetLastError();
 }
 

@@ -241,11 +241,16 @@ hipError_t launch_dense_from_coarse(const CoarseOp& op, cplx* A, hipStream_t s);
 
 // explicit inverse of the coarsest operator (bandlu.hip): A (row-major dense
 // nz*nx x nz*nx, a 5- or 9-point stencil) is replaced by its inverse; scratch
-// of band_scratch_bytes(nz, nx); flag[0] set to 1 on a zero/non-finite pivot
-// (clear it first)
+// of band_scratch_bytes(nz, nx). The factorisation numbers the grid with z
+// fastest when band_renumbered(nz, nx) (nz < nx); the inverse is then stored in
+// that numbering (entry (q1, q2) for grid nodes q = ix nz + iz) unless
+// `natural` is set. flag[0] |= 1 on a zero/non-finite pivot, |= 2 on a
+// non-finite entry of the inverse (clear it first).
 int band_halfwidth(int nz, int nx);
+bool band_renumbered(int nz, int nx);
 size_t band_scratch_bytes(int nz, int nx);
-hipError_t band_invert(int nz, int nx, cplx* A, void* scratch, int* flag, hipStream_t s);
+hipError_t band_invert(int nz, int nx, cplx* A, void* scratch, int* flag, bool natural,
+                       hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // launchers (pcr.hip): exact solve of the 1D tridiagonal shifted Laplacian
@@ -365,30 +370,39 @@ hipError_t launch_vc_gemm(int n, const cplxf* A, const cplxf* x, cplxf* y, void*
 // temporally blocked legs (vcycle_tiled.hip): down = two pre-sweeps from zero,
 // residual and restriction; up = prolongation and two post-sweeps
 // (the smoother weight enters through op.wdinv = omega_J / diag).
+// The next coarser grid: its shape, and whether its vectors are stored x-major
+// (node (iz, ix) at ix nz + iz: the band numbering of the coarsest inverse)
+// instead of z-major.
+struct CGrid {
+    int nz, nx, xmajor;
+    __host__ __device__ int64_t at(int iz, int ix) const {
+        return xmajor ? (int64_t)ix * nz + iz : (int64_t)iz * nx + ix;
+    }
+};
 hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, cplx* x2, int hz, int hx,
-                               int nzc, int nxc, cplx* bc, const int* active, hipStream_t s,
+                               CGrid cg, cplx* bc, const int* active, hipStream_t s,
                                const Batch& bt = Batch());
 // single-precision cycle: the Krylov vector src stays complex128
 hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, cplxf* x2, int hz,
-                               int hx, int nzc, int nxc, cplxf* bc, const int* active,
+                               int hx, CGrid cg, cplxf* bc, const int* active,
                                hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_coarse_down(const CoarseOpT<float>& op, const cplxf* b, cplxf* x2, int hz,
-                                 int hx, int nzc, int nxc, cplxf* bc, const int* active,
+                                 int hx, CGrid cg, cplxf* bc, const int* active,
                                  hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_fine_up(const FineOpT<float>& op, int hz, int hx, const cplx* b,
-                             const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
+                             const cplxf* x2, const cplxf* e, CGrid cg, cplxf* out,
                              const int* active, hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_coarse_up(const CoarseOpT<float>& op, int hz, int hx, const cplxf* b,
-                               const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
+                               const cplxf* x2, const cplxf* e, CGrid cg, cplxf* out,
                                const int* active, hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz,
-                                 int hx, int nzc, int nxc, cplx* bc, const int* active,
+                                 int hx, CGrid cg, cplx* bc, const int* active,
                                  hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b,
-                             const cplx* x2, const cplx* e, int nxc, cplx* out, const int* active,
+                             const cplx* x2, const cplx* e, CGrid cg, cplx* out, const int* active,
                              hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b,
-                               const cplx* x2, const cplx* e, int nxc, cplx* out,
+                               const cplx* x2, const cplx* e, CGrid cg, cplx* out,
                                const int* active, hipStream_t s, const Batch& bt = Batch());
 // wdinv = wj / diag of a level operator (set-up)
 hipError_t launch_wdinv_fine(const FineOp& op, double wj, cplx* wdinv, hipStream_t s);

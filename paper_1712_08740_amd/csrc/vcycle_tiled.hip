@@ -124,7 +124,7 @@ __device__ __forceinline__ bool in_grid(int z, int x, int nz, int nx) {
 template <class OP, class SC, int TCX, int TCZ>
 __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
                                              typename OP::C* __restrict__ x2out,
-                                             int hz, int hx, int nzc, int nxc,
+                                             int hz, int hx, CGrid cg,
                                              typename OP::C* __restrict__ bc, double rscale,
                                              const int* __restrict__ active, int ntx, int ntiles,
                                              int64_t bs) {
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
     // phase 4: b_c = R r for the tile's coarse nodes
     for (int t = threadIdx.x; t < TCX * TCZ; t += NT) {
         const int Iz = cz0 + t / TCX, Ix = cx0 + t % TCX;
-        if (Iz >= nzc || Ix >= nxc) continue;
+        if (Iz >= cg.nz || Ix >= cg.nx) continue;
         const int lz = (hz ? 2 * Iz : Iz) - oz, lx = (hx ? 2 * Ix : Ix) - ox;
         C acc = czero<C>();
 #pragma unroll
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
                 acc = cadd(acc, cscale(s1[(lz + dz) * wx + (lx + dx)], w));
             }
         }
-        bc[(int64_t)Iz * nxc + Ix] = cscale(acc, (T)rscale);
+        bc[cg.at(Iz, Ix)] = cscale(acc, (T)rscale);
     }
 }
 
@@ -246,7 +246,7 @@ template <class OP, class SB, int TX, int TZ>
 __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
                                            const SB* __restrict__ b,
                                            const typename OP::C* __restrict__ x2,
-                                           const typename OP::C* __restrict__ e, int nxc,
+                                           const typename OP::C* __restrict__ e, CGrid cg,
                                            typename OP::C* __restrict__ out,
                                            const int* __restrict__ active, int ntx, int ntiles,
                                            int64_t bs) {
@@ -284,8 +284,8 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
                 T wz0, wz1, wx0, wx1;
                 interp2(qz, hz, z0, z1, wz0, wz1);
                 interp2(qx, hx, x0, x1, wx0, wx1);
-                const C e00 = e[(int64_t)z0 * nxc + x0], e01 = e[(int64_t)z0 * nxc + x1];
-                const C e10 = e[(int64_t)z1 * nxc + x0], e11 = e[(int64_t)z1 * nxc + x1];
+                const C e00 = e[cg.at(z0, x0)], e01 = e[cg.at(z0, x1)];
+                const C e10 = e[cg.at(z1, x0)], e11 = e[cg.at(z1, x1)];
                 const C pe = cadd(cadd(cscale(e00, wz0 * wx0), cscale(e01, wz0 * wx1)),
                                   cadd(cscale(e10, wz1 * wx0), cscale(e11, wz1 * wx1)));
                 v = cadd(x2[(int64_t)qz * nx + qx], pe);
@@ -361,13 +361,13 @@ bool big_tiles(const OP& A) {
 }
 
 template <class OP, class SC, int TCX, int TCZ>
-hipError_t down_launch(const OP& A, const SC* src, typename OP::C* x2, int hz, int hx, int nzc,
-                       int nxc, typename OP::C* bc, const int* active, hipStream_t s,
+hipError_t down_launch(const OP& A, const SC* src, typename OP::C* x2, int hz, int hx, CGrid cg,
+                       typename OP::C* bc, const int* active, hipStream_t s,
                        const Batch& bt) {
-    const int ntx = (nxc + TCX - 1) / TCX, ntz = (nzc + TCZ - 1) / TCZ;
+    const int ntx = (cg.nx + TCX - 1) / TCX, ntz = (cg.nz + TCZ - 1) / TCZ;
     const int ntiles = ntx * ntz;
     HH_LAUNCH((k_down<OP, SC, TCX, TCZ>), dim3(ntiles, bt.n), dim3(NT), 0, s, A, src, x2, hz, hx,
-              nzc, nxc, bc, inv2dc(hz, hx), active, ntx, ntiles, bt.bs);
+              cg, bc, inv2dc(hz, hx), active, ntx, ntiles, bt.bs);
     return hipGetLastError();
 }
 
@@ -376,30 +376,30 @@ hipError_t down_launch(const OP& A, const SC* src, typename OP::C* x2, int hz, i
 // flight beat the extra halo work, and past that the down leg still gains
 // (measured on the 401 x 201 and 1201 x 401 hierarchies).
 template <class OP, class SC>
-hipError_t down_dispatch(const OP& A, const SC* src, typename OP::C* x2, int hz, int hx, int nzc,
-                         int nxc, typename OP::C* bc, const int* active, hipStream_t s,
+hipError_t down_dispatch(const OP& A, const SC* src, typename OP::C* x2, int hz, int hx, CGrid cg,
+                         typename OP::C* bc, const int* active, hipStream_t s,
                          const Batch& bt) {
-    return down_launch<OP, SC, 4, 4>(A, src, x2, hz, hx, nzc, nxc, bc, active, s, bt);
+    return down_launch<OP, SC, 4, 4>(A, src, x2, hz, hx, cg, bc, active, s, bt);
 }
 
 template <class OP, class SB, int TX, int TZ>
 hipError_t up_launch(const OP& A, int hz, int hx, const SB* b, const typename OP::C* x2,
-                     const typename OP::C* e, int nxc, typename OP::C* out, const int* active,
+                     const typename OP::C* e, CGrid cg, typename OP::C* out, const int* active,
                      hipStream_t s, const Batch& bt) {
     const int ntx = (A.nx() + TX - 1) / TX, ntz = (A.nz() + TZ - 1) / TZ;
     HH_LAUNCH((k_up<OP, SB, TX, TZ>), dim3(ntx * ntz, bt.n), dim3(NT), 0, s, A, hz, hx, b, x2, e,
-              nxc, out, active, ntx, ntx * ntz, bt.bs);
+              cg, out, active, ntx, ntx * ntz, bt.bs);
     return hipGetLastError();
 }
 
 // Up leg: 8 x 4-node tiles, and 32 x 8 (less halo work) on large 5-point grids.
 template <class OP, class SB>
 hipError_t up_dispatch(const OP& A, int hz, int hx, const SB* b, const typename OP::C* x2,
-                       const typename OP::C* e, int nxc, typename OP::C* out, const int* active,
+                       const typename OP::C* e, CGrid cg, typename OP::C* out, const int* active,
                        hipStream_t s, const Batch& bt) {
     if (big_tiles(A))
-        return up_launch<OP, SB, 32, 8>(A, hz, hx, b, x2, e, nxc, out, active, s, bt);
-    return up_launch<OP, SB, 8, 4>(A, hz, hx, b, x2, e, nxc, out, active, s, bt);
+        return up_launch<OP, SB, 32, 8>(A, hz, hx, b, x2, e, cg, out, active, s, bt);
+    return up_launch<OP, SB, 8, 4>(A, hz, hx, b, x2, e, cg, out, active, s, bt);
 }
 
 template <class T>
@@ -418,47 +418,47 @@ Coarse9<T> coarse9(const CoarseOpT<T>& op) {
 }  // namespace
 
 hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, cplx* x2, int hz, int hx,
-                               int nzc, int nxc, cplx* bc, const int* active, hipStream_t s,
+                               CGrid cg, cplx* bc, const int* active, hipStream_t s,
                                const Batch& bt) {
-    return down_dispatch(fine5(op), src, x2, hz, hx, nzc, nxc, bc, active, s, bt);
+    return down_dispatch(fine5(op), src, x2, hz, hx, cg, bc, active, s, bt);
 }
 hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, cplxf* x2, int hz,
-                               int hx, int nzc, int nxc, cplxf* bc, const int* active,
+                               int hx, CGrid cg, cplxf* bc, const int* active,
                                hipStream_t s, const Batch& bt) {
-    return down_dispatch(fine5(op), src, x2, hz, hx, nzc, nxc, bc, active, s, bt);
+    return down_dispatch(fine5(op), src, x2, hz, hx, cg, bc, active, s, bt);
 }
 
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz, int hx,
-                                 int nzc, int nxc, cplx* bc, const int* active, hipStream_t s,
+                                 CGrid cg, cplx* bc, const int* active, hipStream_t s,
                                  const Batch& bt) {
-    return down_dispatch(coarse9(op), b, x2, hz, hx, nzc, nxc, bc, active, s, bt);
+    return down_dispatch(coarse9(op), b, x2, hz, hx, cg, bc, active, s, bt);
 }
 hipError_t launch_vc_coarse_down(const CoarseOpT<float>& op, const cplxf* b, cplxf* x2, int hz,
-                                 int hx, int nzc, int nxc, cplxf* bc, const int* active,
+                                 int hx, CGrid cg, cplxf* bc, const int* active,
                                  hipStream_t s, const Batch& bt) {
-    return down_dispatch(coarse9(op), b, x2, hz, hx, nzc, nxc, bc, active, s, bt);
+    return down_dispatch(coarse9(op), b, x2, hz, hx, cg, bc, active, s, bt);
 }
 
 hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b, const cplx* x2,
-                             const cplx* e, int nxc, cplx* out, const int* active, hipStream_t s,
+                             const cplx* e, CGrid cg, cplx* out, const int* active, hipStream_t s,
                              const Batch& bt) {
-    return up_dispatch(fine5(op), hz, hx, b, x2, e, nxc, out, active, s, bt);
+    return up_dispatch(fine5(op), hz, hx, b, x2, e, cg, out, active, s, bt);
 }
 hipError_t launch_vc_fine_up(const FineOpT<float>& op, int hz, int hx, const cplx* b,
-                             const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
+                             const cplxf* x2, const cplxf* e, CGrid cg, cplxf* out,
                              const int* active, hipStream_t s, const Batch& bt) {
-    return up_dispatch(fine5(op), hz, hx, b, x2, e, nxc, out, active, s, bt);
+    return up_dispatch(fine5(op), hz, hx, b, x2, e, cg, out, active, s, bt);
 }
 
 hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b, const cplx* x2,
-                               const cplx* e, int nxc, cplx* out, const int* active,
+                               const cplx* e, CGrid cg, cplx* out, const int* active,
                                hipStream_t s, const Batch& bt) {
-    return up_dispatch(coarse9(op), hz, hx, b, x2, e, nxc, out, active, s, bt);
+    return up_dispatch(coarse9(op), hz, hx, b, x2, e, cg, out, active, s, bt);
 }
 hipError_t launch_vc_coarse_up(const CoarseOpT<float>& op, int hz, int hx, const cplxf* b,
-                               const cplxf* x2, const cplxf* e, int nxc, cplxf* out,
+                               const cplxf* x2, const cplxf* e, CGrid cg, cplxf* out,
                                const int* active, hipStream_t s, const Batch& bt) {
-    return up_dispatch(coarse9(op), hz, hx, b, x2, e, nxc, out, active, s, bt);
+    return up_dispatch(coarse9(op), hz, hx, b, x2, e, cg, out, active, s, bt);
 }
 
 namespace {

@@ -96,8 +96,7 @@ def test_footprint_plans_the_oracle_hierarchy(lib):
         nc = n[-1]
         bw = min(shapes[-1]) + 1                    # half-bandwidth of the coarsest stencil
         expect = (12 * n[0] + sum(216 * v for v in n[1:]) + sum(24 * v for v in n[:-1])
-                  + 24 * nc * nc + 16 * nc * (4 * bw + 2) + 16 * ((nc * nc + 255) // 256)
-                  + 16 * 4096)
+                  + 24 * nc * nc + 16 * nc * (4 * bw + 2) + 16 * 4096)
         pb, wb = lib.footprint_bytes(w.shape, w.omega, w.slowness.max(), w.h, max_coarse=mc)
         assert expect <= pb <= expect + 256 * (2 * len(n) + 16), (w.name, mc)
         _, wb2 = lib.footprint_bytes(w.shape, w.omega, w.slowness.max(), w.h, max_coarse=mc,
