@@ -94,172 +94,192 @@ __global__ void __launch_bounds__(256) k_band_split(const cplx* __restrict__ AB,
 
 // Columns c0 .. c0+C-1 of M^{-1} (M = L U, the transposed renumbered operator)
 // by forward substitution with the unit lower factor from e_c, then backward
-// substitution with U, both right-looking, by one wavefront. The rows that the
-// current row can still update (at most b below it, or above it going back)
-// stay in registers: rows are taken in blocks of 64, row base + 64 s + lane in
-// slot s of lane `lane`, and when a block is done its slot 0 is written out and
-// the slots shift by one. At each row the lane that owns it passes its C values
-// to the others through LDS; factor entries are loaded D rows ahead. The
-// forward result is kept in `out` and read back by the backward pass.
+// substitution with U, both right-looking, by one wavefront. The lanes form
+// 64/R groups of R; group g takes CG of the columns and lane r of a group the
+// rows r, r + R, ... of the current block of R rows and of the SLOTS - 1 blocks
+// after it (the rows the current row can still update: at most b away), in
+// registers. At each row the lanes that own it pass their values to their
+// group through LDS; when a block is done its slot is written out and the
+// slots shift by one. Factor entries are loaded D rows ahead. The forward
+// result is kept in `out` and read back by the backward pass.
 //
 // out receives row c0+c of A'^{-1} (A' = M^T): at (c0+c) n + q in the band
 // numbering, or at orig(c0+c) n + orig(q) (the natural numbering of A^{-1})
 // when `natural` is set. flag[0] |= 2 for a non-finite entry of the inverse.
-template <int SLOTS, int C, int D>
+// a -= l y with four fused multiply-adds
+__device__ __forceinline__ void msub(cplx& a, cplx l, cplx y) {
+    a.x = fma(-l.x, y.x, a.x);
+    a.x = fma(l.y, y.y, a.x);
+    a.y = fma(-l.x, y.y, a.y);
+    a.y = fma(-l.y, y.x, a.y);
+}
+
+template <int R, int SLOTS, int CG, int D>
 __global__ void __launch_bounds__(64) k_band_inv(const cplx* __restrict__ Lc,
                                                  const cplx* __restrict__ Uc,
                                                  const cplx* __restrict__ Ui, int n, int b,
                                                  Numbering num, int natural,
                                                  cplx* __restrict__ out, int* __restrict__ flag) {
-    static_assert(64 % D == 0, "D divides the block of 64 rows");
-    const int lane = threadIdx.x;
+    static_assert(64 % R == 0 && R % D == 0, "R divides the wavefront, D divides R");
+    constexpr int C = CG * (64 / R);
+    const int rl = threadIdx.x % R;                // row lane
+    const int cb = (threadIdx.x / R) * CG;         // first column of this lane's group
     const int c0 = blockIdx.x * C;
     const int nc = min(C, n - c0);
     __shared__ cplx ybuf[2][C];
     auto at = [&](int c, int64_t q) -> int64_t {
         return natural ? num.orig(c0 + c) * (int64_t)n + num.orig(q) : (int64_t)(c0 + c) * n + q;
     };
-    cplx acc[SLOTS][C];
+    cplx acc[SLOTS][CG];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s)
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            acc[s][c] = mk((s == 0 && lane == c && c < nc) ? 1.0 : 0.0, 0.0);
+        for (int k = 0; k < CG; ++k) {
+            const int c = cb + k;
+            acc[s][k] = mk((c < nc && s == c / R && rl == c % R) ? 1.0 : 0.0, 0.0);
+        }
 
     // ---- forward: y = L^{-1} e_c, rows c0 .. n-1 (the rows above c0 are zero)
     // L(row, i) = Lc[i][row - i - 1] for the row of slot s in the block at base
+    // Every load is issued (from entry 0 when out of range, a finite factor
+    // entry) and scaled by 0 or 1: a load under a branch makes the compiler wait
+    // for all outstanding loads before its first use, defeating the prefetch.
     auto lval = [&](int i, int base, int s) -> cplx {
-        const int row = base + 64 * s + lane;
+        const int row = base + R * s + rl;
         const int t = row - i - 1;
-        return (i < n && t >= 0 && t < b && row < n) ? Lc[(int64_t)i * b + t] : mk(0.0, 0.0);
+        const bool ok = i < n && t >= 0 && t < b && row < n;
+        return cscale(Lc[ok ? (int64_t)i * b + t : 0], ok ? 1.0 : 0.0);
     };
     cplx fv[D][SLOTS];
 #pragma unroll
     for (int d = 0; d < D; ++d)
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) fv[d][s] = lval(c0 + d, c0, s);
-    for (int base = c0; base < n; base += 64) {
-        for (int g = 0; g < 64 && base + g < n; g += D) {
+    for (int base = c0; base < n; base += R) {
+        for (int g = 0; g < R && base + g < n; g += D) {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 const int i = base + g + d;
                 if (i < n) {
-                    if (lane == g + d) {
+                    if (rl == g + d) {
 #pragma unroll
-                        for (int c = 0; c < C; ++c) ybuf[i & 1][c] = acc[0][c];
+                        for (int k = 0; k < CG; ++k) ybuf[i & 1][cb + k] = acc[0][k];
                     }
                     __syncthreads();
                     cplx l[SLOTS];
-                    const int bn = (g + d + D >= 64) ? base + 64 : base;   // block of row i + D
+                    const int bn = (g + d + D >= R) ? base + R : base;     // block of row i + D
 #pragma unroll
                     for (int s = 0; s < SLOTS; ++s) {
                         l[s] = fv[d][s];
                         fv[d][s] = lval(i + D, bn, s);
                     }
 #pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        const cplx y = ybuf[i & 1][c];
+                    for (int k = 0; k < CG; ++k) {
+                        const cplx y = ybuf[i & 1][cb + k];
 #pragma unroll
-                        for (int s = 0; s < SLOTS; ++s)
-                            if (64 * s <= g + d + b) acc[s][c] = csub(acc[s][c], cmul(l[s], y));
+                        for (int s = 0; s < SLOTS; ++s) msub(acc[s][k], l[s], y);
                     }
                 }
             }
         }
-        const int row = base + lane;
+        const int row = base + rl;
         if (row < n) {
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (c < nc) out[at(c, row)] = acc[0][c];
+            for (int k = 0; k < CG; ++k)
+                if (cb + k < nc) out[at(cb + k, row)] = acc[0][k];
         }
 #pragma unroll
         for (int s = 0; s + 1 < SLOTS; ++s)
 #pragma unroll
-            for (int c = 0; c < C; ++c) acc[s][c] = acc[s + 1][c];
+            for (int k = 0; k < CG; ++k) acc[s][k] = acc[s + 1][k];
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[SLOTS - 1][c] = mk(0.0, 0.0);
+        for (int k = 0; k < CG; ++k) acc[SLOTS - 1][k] = mk(0.0, 0.0);
     }
     // the forward results are read back by other lanes: complete the stores and
     // read them past the first-level cache
     __threadfence();
     __syncthreads();
-    auto yval = [&](int row, int c) -> cplx {
-        if (row < c0 || c >= nc) return mk(0.0, 0.0);
-        double* q = reinterpret_cast<double*>(out + at(c, row));
-        return mk(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                  __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    auto yval = [&](int row, int k) -> cplx {
+        const bool ok = row >= c0 && cb + k < nc;
+        double* q = reinterpret_cast<double*>(out + (ok ? at(cb + k, row) : 0));
+        const cplx v = mk(__hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                          __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        return ok ? v : mk(0.0, 0.0);
     };
 
-    // ---- backward: x = U^{-1} y, rows n-1 .. 0; row top - 64 s - lane in slot s
+    // ---- backward: x = U^{-1} y, rows n-1 .. 0; row top - R s - rl in slot s
     auto uval = [&](int i, int top, int s) -> cplx {
-        const int row = top - 64 * s - lane;
+        const int row = top - R * s - rl;
         const int t = i - 1 - row;
-        return (i >= 0 && t >= 0 && t < b && row >= 0) ? Uc[(int64_t)i * b + t] : mk(0.0, 0.0);
+        const bool ok = i >= 0 && t >= 0 && t < b && row >= 0;
+        return cscale(Uc[ok ? (int64_t)i * b + t : 0], ok ? 1.0 : 0.0);
+    };
+    auto uinv = [&](int row) -> cplx {
+        return cscale(Ui[row >= 0 ? row : 0], row >= 0 ? 1.0 : 0.0);
     };
     const int top0 = n - 1;
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s)
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[s][c] = yval(top0 - 64 * s - lane, c);
+        for (int k = 0; k < CG; ++k) acc[s][k] = yval(top0 - R * s - rl, k);
 #pragma unroll
     for (int d = 0; d < D; ++d)
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) fv[d][s] = uval(top0 - d, top0, s);
-    cplx dinv = top0 - lane >= 0 ? Ui[top0 - lane] : mk(0.0, 0.0);
+    cplx dinv = uinv(top0 - rl);
     bool bad = false;
-    for (int top = top0; top >= 0; top -= 64) {
+    for (int top = top0; top >= 0; top -= R) {
         // the slot entering after this block, and the diagonal of the next block
-        cplx ynext[C];
-        const int rn = top - 64 * SLOTS - lane;
+        cplx ynext[CG];
+        const int rn = top - R * SLOTS - rl;
 #pragma unroll
-        for (int c = 0; c < C; ++c) ynext[c] = yval(rn, c);
-        const cplx dnext = top - 64 - lane >= 0 ? Ui[top - 64 - lane] : mk(0.0, 0.0);
-        for (int g = 0; g < 64 && top - g >= 0; g += D) {
+        for (int k = 0; k < CG; ++k) ynext[k] = yval(rn, k);
+        const cplx dnext = uinv(top - R - rl);
+        for (int g = 0; g < R && top - g >= 0; g += D) {
 #pragma unroll
             for (int d = 0; d < D; ++d) {
                 const int i = top - g - d;
                 if (i >= 0) {
-                    if (lane == g + d) {
+                    if (rl == g + d) {
 #pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            acc[0][c] = cmul(acc[0][c], dinv);
-                            ybuf[i & 1][c] = acc[0][c];
+                        for (int k = 0; k < CG; ++k) {
+                            acc[0][k] = cmul(acc[0][k], dinv);
+                            ybuf[i & 1][cb + k] = acc[0][k];
                         }
                     }
                     __syncthreads();
                     cplx u[SLOTS];
-                    const int tn = (g + d + D >= 64) ? top - 64 : top;     // block of row i - D
+                    const int tn = (g + d + D >= R) ? top - R : top;       // block of row i - D
 #pragma unroll
                     for (int s = 0; s < SLOTS; ++s) {
                         u[s] = fv[d][s];
                         fv[d][s] = uval(i - D, tn, s);
                     }
 #pragma unroll
-                    for (int c = 0; c < C; ++c) {
-                        const cplx x = ybuf[i & 1][c];
+                    for (int k = 0; k < CG; ++k) {
+                        const cplx x = ybuf[i & 1][cb + k];
 #pragma unroll
-                        for (int s = 0; s < SLOTS; ++s)
-                            if (64 * s <= g + d + b) acc[s][c] = csub(acc[s][c], cmul(u[s], x));
+                        for (int s = 0; s < SLOTS; ++s) msub(acc[s][k], u[s], x);
                     }
                 }
             }
         }
-        const int row = top - lane;
+        const int row = top - rl;
         if (row >= 0) {
 #pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (c < nc) {
-                    const cplx v = acc[0][c];
+            for (int k = 0; k < CG; ++k)
+                if (cb + k < nc) {
+                    const cplx v = acc[0][k];
                     bad = bad || !(isfinite(v.x) && isfinite(v.y));
-                    out[at(c, row)] = v;
+                    out[at(cb + k, row)] = v;
                 }
         }
 #pragma unroll
         for (int s = 0; s + 1 < SLOTS; ++s)
 #pragma unroll
-            for (int c = 0; c < C; ++c) acc[s][c] = acc[s + 1][c];
+            for (int k = 0; k < CG; ++k) acc[s][k] = acc[s + 1][k];
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[SLOTS - 1][c] = ynext[c];
+        for (int k = 0; k < CG; ++k) acc[SLOTS - 1][k] = ynext[k];
         dinv = dnext;
     }
     if (bad) atomicOr(flag, 2);
@@ -277,11 +297,12 @@ size_t band_scratch_bytes(int nz, int nx) {
     return (size_t)(n * (2 * b + 1) + 2 * n * b + n) * sizeof(cplx);
 }
 
-template <int SLOTS, int C, int D>
+template <int R, int SLOTS, int CG, int D>
 static void inv_launch(const cplx* Lc, const cplx* Uc, const cplx* Ui, int n, int b, Numbering num,
                        int natural, cplx* A, int* flag, hipStream_t s) {
-    HH_LAUNCH((k_band_inv<SLOTS, C, D>), dim3((unsigned)((n + C - 1) / C)), dim3(64), 0, s, Lc, Uc,
-              Ui, n, b, num, natural, A, flag);
+    constexpr int C = CG * (64 / R);
+    HH_LAUNCH((k_band_inv<R, SLOTS, CG, D>), dim3((unsigned)((n + C - 1) / C)), dim3(64), 0, s, Lc,
+              Uc, Ui, n, b, num, natural, A, flag);
 }
 
 hipError_t band_invert(int nz, int nx, cplx* A, void* scratch, int* flag, bool natural,
@@ -299,16 +320,20 @@ hipError_t band_invert(int nz, int nx, cplx* A, void* scratch, int* flag, bool n
     HH_LAUNCH(k_band_lu, dim3(1), dim3(LU_THREADS), 0, s, AB, (int)n, b, flag);
     HH_LAUNCH(k_band_split, dim3((unsigned)((n * b + 255) / 256)), dim3(256), 0, s, AB, n, b, Lc,
               Uc, Ui);
-    // the window of a block of 64 rows reaches b rows further: 1 + ceil(b / 64) slots
+    // the window of a block of R rows reaches b rows further: 1 + ceil(b / R) slots
     const int nat = natural || !num.zfast ? 1 : 0;
-    if (b <= 64)
-        inv_launch<2, 16, 8>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
+    if (b <= 16)
+        inv_launch<16, 2, 4, 8>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
+    else if (b <= 32)
+        inv_launch<16, 3, 4, 8>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
+    else if (b <= 64)
+        inv_launch<16, 5, 4, 4>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
+    else if (b <= 96)
+        inv_launch<16, 7, 4, 2>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
     else if (b <= 128)
-        inv_launch<3, 16, 8>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
-    else if (b <= 192)
-        inv_launch<4, 8, 4>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
+        inv_launch<16, 9, 4, 2>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
     else
-        inv_launch<5, 8, 4>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
+        inv_launch<64, 5, 4, 4>(Lc, Uc, Ui, (int)n, b, num, nat, A, flag, s);
     return hipGetLastError();
 }
 
