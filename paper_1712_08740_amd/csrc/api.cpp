@@ -249,7 +249,7 @@ int kt_harvest(hh_problem_s* p, const std::vector<std::vector<int>>& executed) {
 // workspace layout
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t V, Z, b, w, partial, h1, h2, R, cs, sn, g, y, st, total;
+    size_t V, Z, b, w, partial, h1, h2, R, cs, sn, g, y, zs, st, total;
     std::vector<size_t> t, bc, ec;   // per level
     int nbA, nbN, nbS, nbmax;   // partials of apply_dot, node kernels, the norm
 };
@@ -296,6 +296,7 @@ Layout layout(const hh_problem_s* p, int m, size_t es = sizeof(cplx)) {
     L.sn = take((size_t)m * c);
     L.g = take((size_t)(m + 1) * c);
     L.y = take((size_t)m * c);
+    L.zs = take((size_t)m * sizeof(double));
     L.st = take(sizeof(SolveState));
     L.total = off;
     return L;
@@ -989,6 +990,7 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
     cplx* sn = at<cplx>(ws, L.sn);
     cplx* g = at<cplx>(ws, L.g);
     cplx* y = at<cplx>(ws, L.y);
+    double* zs = at<double>(ws, L.zs);
     SolveState* st = at<SolveState>(ws, L.st);
     const int* active = &st->active;
     const FineOp H = op_H(p);
@@ -1014,7 +1016,7 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
     // needs step j's reorthogonalisation coefficients). A full cycle ends with
     // the projections of u_m and the Givens step of column m - 1.
     const GivensArgs giv{st, h1, h2, R, cs, sn, g, drec, dhist, (int64_t)L.total,
-                         p->hist_stride};
+                         p->hist_stride, zs};
     cplx* red = h1;
 
     std::vector<std::vector<int>> executed;   // Arnoldi steps that did work, per cycle and RHS
@@ -1095,9 +1097,9 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
         executed.push_back(ex);
         if (!any_stopped) break;                    // every right-hand side finished at the start
         if (f32)
-            HIPCHK(launch_cycle_finish(st, R, g, y, Zf, N, u, s, bt));
+            HIPCHK(launch_cycle_finish(st, R, g, zs, y, Zf, N, u, s, bt));
         else
-            HIPCHK(launch_cycle_finish(st, R, g, y, Z, N, u, s, bt));
+            HIPCHK(launch_cycle_finish(st, R, g, zs, y, Z, N, u, s, bt));
         if (all_done) break;                        // non-finite values inside the cycle
     }
     HIPCHK(hipStreamSynchronize(s));

@@ -20,6 +20,7 @@ struct GivensArgs {
     double* hist;             // residual estimates, pinned host memory
     int64_t bs;               // bytes between the workspaces of consecutive right-hand sides
     int64_t hist_stride;      // entries between the histories of consecutive right-hand sides
+    double* zs;               // 1 / nu_j: the update coefficient of z_j is y_j / nu_j
 };
 
 // Sum over i < n of f(i) by the 64 lanes of wavefront 0 in a fixed order
@@ -92,6 +93,7 @@ __device__ inline void givens_dcgs(const GivensArgs& ga, int rb, bool tail, cplx
     a.cs = rhs_nn(ga.cs, rb, ga.bs);
     a.sn = rhs_nn(ga.sn, rb, ga.bs);
     a.g = rhs_nn(ga.g, rb, ga.bs);
+    a.zs = rhs_nn(ga.zs, rb, ga.bs);
     a.rec = ga.rec + rb;
     a.hist = ga.hist + (int64_t)rb * ga.hist_stride;
     SolveState* st = a.st;
@@ -123,15 +125,19 @@ __device__ inline void givens_dcgs(const GivensArgs& ga, int rb, bool tail, cplx
     __syncthreads();
     cplx* ssn = sc;
     if (!tail) {
-        // keep this step's w-projections and h_jj for the next column
-        for (int i = tid; i < j; i += nt) a.hprev[i] = a.red[j + 1 + i];
+        // keep this step's w-projections and h_jj for the next column, divided
+        // by nu (u_{j+1} is stored divided by nu: see k_axpy_dcgs)
+        for (int i = tid; i < j; i += nt) a.hprev[i] = cscale(a.red[j + 1 + i], s_inv_nu);
     }
     __syncthreads();
     for (int i = tid; i + 1 < j; i += nt) ssn[i] = a.sn[i];
     __syncthreads();
     if (tid != 0) return;
     const double hn = s_nu;
-    if (!tail) a.hprev[j] = s_h;
+    if (!tail) {
+        a.hprev[j] = cscale(s_h, s_inv_nu);
+        a.zs[j] = s_inv_nu;
+    }
     if (j == 0) {                      // first step of the cycle: no column yet
         a.g[0] = mk(hn, 0.0);
         st->j = 1;

@@ -276,7 +276,12 @@ __global__ void __launch_bounds__(256) k_axpy_dot(const cplx* __restrict__ V, in
 // V_j, 2(j+1) values) every block derives (dcgs_coeffs) nu = ||u - V a||, the
 // new Hessenberg entry h_jj = v_j^H w and c = b - a h_jj / nu, then
 //   V_j     <- (u - sum_i a_i V_i) / nu          (the reorthogonalised v_j)
-//   V_{j+1} <- w - sum_i c_i V_i - (h_jj / nu) u  (w projected once: the next u)
+//   V_{j+1} <- (w - sum_i c_i V_i - (h_jj / nu) u) / nu
+// (w projected once: the next u). The division by nu keeps the scale of the
+// stored u (and of z = M^{-1} u) that of one Hessenberg column: without it
+// the scales of consecutive steps multiply over a cycle and overflow complex64
+// within a few tens of steps. The Hessenberg entries carried to the next
+// column are divided by nu as well, and z_j enters the update as z_j / nu.
 // With giv.st set, one extra workgroup performs the Givens step of column j-1
 // (which needed this step's reorthogonalisation coefficients).
 // LDS (dynamic): 3 (j + 2) complex + (j + 2) doubles.
@@ -343,7 +348,7 @@ __global__ void __launch_bounds__(256) k_axpy_dcgs(cplx* __restrict__ V, int64_t
         }
     }
     V[(int64_t)j * n + p] = cscale(acc_v, inv_nu);
-    V[(int64_t)(j + 1) * n + p] = acc_u;
+    V[(int64_t)(j + 1) * n + p] = cscale(acc_u, inv_nu);
 }
 
 // w -= V h, then ||w||^2 per block. At most kNormBlocks blocks (grid-stride
@@ -512,11 +517,13 @@ __global__ void __launch_bounds__(256) k_givens_tail(GivensArgs a) {
 __global__ void __launch_bounds__(256) k_backsub_pred(const SolveState* st,
                                                       const cplx* __restrict__ R,
                                                       const cplx* __restrict__ g,
+                                                      const double* __restrict__ zs,
                                                       cplx* __restrict__ y, int64_t bs) {
     const int rb = blockIdx.x;
     st = rhs_nn(st, rb, bs);
     R = rhs_nn(R, rb, bs);
     g = rhs_nn(g, rb, bs);
+    zs = rhs_nn(zs, rb, bs);
     y = rhs_nn(y, rb, bs);
     const int k = st->k;
     if (k == 0) return;
@@ -529,7 +536,7 @@ __global__ void __launch_bounds__(256) k_backsub_pred(const SolveState* st,
         __syncthreads();
         for (int l = threadIdx.x; l < i; l += 256)
             gs[l] = csub(gs[l], cmul(R[l + (int64_t)i * ld], yi));
-        if (threadIdx.x == 0) y[i] = yi;
+        if (threadIdx.x == 0) y[i] = cscale(yi, zs[i]);
         __syncthreads();
     }
 }
@@ -742,23 +749,23 @@ hipError_t launch_axpy_dcgs(cplx* V, int64_t n, int j, const cplx* red, const cp
     return hipGetLastError();
 }
 template <class ZC>
-hipError_t cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y, const ZC* Z,
-                        int64_t n, cplx* x, hipStream_t s, const Batch& bt) {
-    HH_LAUNCH(k_backsub_pred, dim3(bt.n), dim3(256), 0, s, st, R, g, y, bt.bs);
+hipError_t cycle_finish(SolveState* st, const cplx* R, const cplx* g, const double* zs, cplx* y,
+                        const ZC* Z, int64_t n, cplx* x, hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_backsub_pred, dim3(bt.n), dim3(256), 0, s, st, R, g, zs, y, bt.bs);
     HH_LAUNCH(k_update_pred<ZC>, dim3(node_blocks(n), bt.n), dim3(256), 0, s, st, Z, n, y, x,
               bt.bs, bt.fs);
     HH_LAUNCH(k_cycle_end, dim3(bt.n), dim3(64), 0, s, st, bt.bs);
     return hipGetLastError();
 }
-hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
-                               const cplx* Z, int64_t n, cplx* x, hipStream_t s,
+hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, const double* zs,
+                               cplx* y, const cplx* Z, int64_t n, cplx* x, hipStream_t s,
                                const Batch& bt) {
-    return cycle_finish(st, R, g, y, Z, n, x, s, bt);
+    return cycle_finish(st, R, g, zs, y, Z, n, x, s, bt);
 }
-hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, cplx* y,
-                               const cplxf* Z, int64_t n, cplx* x, hipStream_t s,
+hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, const double* zs,
+                               cplx* y, const cplxf* Z, int64_t n, cplx* x, hipStream_t s,
                                const Batch& bt) {
-    return cycle_finish(st, R, g, y, Z, n, x, s, bt);
+    return cycle_finish(st, R, g, zs, y, Z, n, x, s, bt);
 }
 hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
                              double tol, HostRecord* rec, double* hist, int64_t hist_stride,

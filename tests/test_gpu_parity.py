@@ -449,6 +449,25 @@ def test_solve_f32_precond_1201x401_15hz(hh):
     assert np.linalg.norm(u - _np(r64.u).ravel()) <= 1e-6 * np.linalg.norm(u)
 
 
+@pytest.mark.gpu
+def test_stagnating_cycles_keep_the_basis_in_range(hh):
+    """Regression: the Arnoldi step preconditions the stored vector before it
+    is normalised, so that vector must be rescaled every step. On a grid whose
+    hierarchy stalls FGMRES (1601 x 601 at 10 Hz with the 4096-node dense limit:
+    the residual stays near 0.11), unscaled vectors grow by the product of the
+    subdiagonal entries and overflowed complex64 within one 30-step cycle. Both
+    precisions must stay finite and give the same residual history."""
+    w = wl.random_field_2d(1601, 601, 10.0, seed=1001, freq_hz=10.0, src=(800, 5))
+    P = hh.Problem(_t(w.slowness), w.omega, 0.01, 10.0, max_coarse=4096)
+    r64 = P.solve(_t(w.source), tol=1e-6, restart=30, max_iters=90)
+    r32 = P.solve(_t(w.source), tol=1e-6, restart=30, max_iters=90, precond_f32=True)
+    P.close()
+    for r in (r64, r32):
+        assert r.status == hh.HH_NOT_CONVERGED and r.iterations == 90
+        assert np.all(np.isfinite(r.history)) and 0.05 < r.true_rel_res < 0.5
+    np.testing.assert_allclose(r32.history, r64.history, rtol=1e-3)
+
+
 def test_f32_flag_validation(hh):
     w = wl.layered_1d_well()
     P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
