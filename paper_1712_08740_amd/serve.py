@@ -72,18 +72,16 @@ class Result:
 
 def coarsest_limit(req: Request) -> Optional[int]:
     """Dense limit of the coarsest grid for a request (2D). A larger limit stops
-    the coarsening before under-resolved levels, trading a larger LU at set-up
-    for far fewer iterations. Measured on MI355X (set-up + solve, complex64
-    preconditioner): 801 x 401 at 20 Hz: 4096 -> 1249 iterations (187 ms),
-    8192 -> 154 (136 ms); 1601 x 601 at 10 Hz: 8192 -> 309 (391 ms), 16384 -> 94
-    (1035 ms); 1601 x 601 at 20 Hz: 8192 does not converge in 2000, 16384 ->
-    220 (1118 ms). Hence 8192, and 16384 for grids of 500k nodes or more
-    sampled at 12 nodes per shortest wavelength or fewer (omega max(m) h >=
-    0.52)."""
+    the coarsening before under-resolved levels, trading a larger LU and inverse
+    at set-up for far fewer iterations. Measured on MI355X (set-up + solve,
+    complex64 preconditioner): 801 x 401 at 20 Hz: 4096 -> 1250 iterations
+    (146 ms), 8192 -> 154 (43 ms); 1601 x 601 at 10 Hz: 8192 -> 309 (141 ms),
+    16384 -> 94 (131 ms); 1601 x 601 at 20 Hz: 8192 does not converge in 2000,
+    16384 -> 220 (206 ms). Hence 8192, and 16384 for grids of 500k nodes or
+    more."""
     if req.max_coarse is not None or req.slowness.ndim != 2:
         return req.max_coarse
-    kh = 2 * np.pi * req.freq_hz * float(req.slowness.max()) * req.h
-    return 16384 if (req.slowness.size >= 500_000 and kh >= 0.52) else 8192
+    return 16384 if req.slowness.size >= 500_000 else 8192
 
 
 def footprint(req: Request) -> int:

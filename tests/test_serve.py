@@ -161,3 +161,15 @@ def test_footprint_covers_device_allocation():
     # the runtime rounds allocations up; the library's own buffers are all counted
     assert used_problem <= pb + (256 << 20)    # + the LU library's own scratch
     P.close()
+
+
+def test_coarsest_limit_rule():
+    """The serving dense limit: 8192, 16384 from 500k grid nodes, the
+    request's own limit when it gives one, none in 1D."""
+    def req(shape, **kw):
+        return serve.Request(id=0, slowness=np.full(shape, 1 / 2000.0), h=10.0, freq_hz=10.0,
+                             source=np.zeros(shape, complex), **kw)
+    assert serve.coarsest_limit(req((401, 801))) == 8192
+    assert serve.coarsest_limit(req((601, 1601))) == 16384
+    assert serve.coarsest_limit(req((601, 1601), max_coarse=4096)) == 4096
+    assert serve.coarsest_limit(req((1001,))) is None
