@@ -13,6 +13,7 @@
 
 #include <immintrin.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -251,7 +252,7 @@ int kt_harvest(hh_problem_s* p, const std::vector<std::vector<int>>& executed) {
 struct Layout {
     size_t V, Z, b, w, partial, h1, h2, R, cs, sn, g, y, zs, st, total;
     std::vector<size_t> t, bc, ec;   // per level
-    int nbA, nbN, nbS, nbmax;   // partials of apply_dot, node kernels, the norm
+    int nbA, nbN, nbR, nbmax;   // partials of apply_dot, node kernels, the residual norm
 };
 
 // es: bytes per complex value of Z and the V-cycle vectors (16, or 8 when
@@ -286,8 +287,8 @@ Layout layout(const hh_problem_s* p, int m, size_t es = sizeof(cplx)) {
     }
     L.nbA = apply_blocks(op_H(p));
     L.nbN = node_blocks(p->N);
-    L.nbS = norm_blocks(p->N);
-    L.nbmax = L.nbA > L.nbN ? L.nbA : L.nbN;
+    L.nbR = residual_blocks(op_H(p));
+    L.nbmax = std::max(std::max(L.nbA, L.nbN), L.nbR);
     L.partial = take((size_t)L.nbmax * 2 * (m + 1) * c);
     L.h1 = take((size_t)2 * (m + 1) * c);
     L.h2 = take((size_t)(m + 1) * c);
@@ -1025,7 +1026,7 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
     for (int cycle = 1;; ++cycle) {
         p->kt.cycle = cycle;
         HIPCHK(launch_residual_norm(H, b, u, V, partial, &st->done, s, bt));   // u_0 = r
-        HIPCHK(launch_cycle_start(st, partial, L.nbA, g, drec, s, bt));
+        HIPCHK(launch_cycle_start(st, partial, L.nbR, g, drec, s, bt));
         // close to convergence: learn whether this cycle opens before enqueuing it
         if (min_est <= tol)
             CHK(wait_for(p, nrhs, s,

@@ -307,6 +307,8 @@ hipError_t launch_apply_dot(const FineOp& op, const cplxf* z, cplx* w, const cpl
                             cplx* partial, const int* active, hipStream_t s,
                             const Batch& bt = Batch());
 int apply_blocks(const FineOp& op);
+// partials of launch_residual_norm (one per 64 x 4 tile in 2D)
+int residual_blocks(const FineOp& op);
 int node_blocks(int64_t n);
 // blocks of the norm kernel (its partial sums are re-read by each consumer)
 constexpr int kNormBlocks = 512;

@@ -108,83 +108,187 @@ __device__ __forceinline__ void block_dots(const cplx* V, int64_t n, int k, bool
 
 __device__ __forceinline__ bool off(const int* active) { return active && *active == 0; }
 
+// One recursive-halving step over lane bit 4H (H = 2, 1): each lane keeps
+// the lower (bit clear) or upper half of its 2H values, sends the other half
+// to the partner lane and adds what it receives.
+template <int H>
+__device__ __forceinline__ void halve(cplx (&v)[16], int lane) {
+    const bool hi = (lane & (4 * H)) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const cplx keep = hi ? v[H + i] : v[i];
+        const cplx send = hi ? v[i] : v[H + i];
+        v[i] = cadd(keep, mk(__shfl_xor(send.x, 4 * H, 64), __shfl_xor(send.y, 4 * H, 64)));
+    }
+}
+
+// The same step over lane bits 5 and 4 with the gfx950 lane swaps (no
+// selects, no LDS crossbar): v_permlane32_swap exchanges the upper half of a
+// with the lower half of b, so afterwards a + b holds a_l + a_{l+32} in lanes
+// below 32 and b_{l-32} + b_l above; v_permlane16_swap does the same for the
+// odd 16-lane rows of a and the even rows of b.
+template <bool ROWS16>
+__device__ __forceinline__ double swap_add(double a, double b) {
+    const unsigned long long ua = __double_as_longlong(a), ub = __double_as_longlong(b);
+    const unsigned alo = (unsigned)ua, ahi = (unsigned)(ua >> 32);
+    const unsigned blo = (unsigned)ub, bhi = (unsigned)(ub >> 32);
+    unsigned xlo, ylo, xhi, yhi;
+    if (ROWS16) {
+        const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+        xlo = l[0]; ylo = l[1]; xhi = h[0]; yhi = h[1];
+    } else {
+        const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+        xlo = l[0]; ylo = l[1]; xhi = h[0]; yhi = h[1];
+    }
+    return __longlong_as_double((long long)(((unsigned long long)xhi << 32) | xlo)) +
+           __longlong_as_double((long long)(((unsigned long long)yhi << 32) | ylo));
+}
+
+// Sum over the 64 lanes of a wavefront of 16 complex values per lane:
+// recursive halving over lane bits 5..2, then a butterfly over bits 1..0.
+// Every lane returns the total of value (lane >> 2) & 15; the order of the
+// additions is fixed.
+__device__ __forceinline__ cplx wave_sum16(cplx (&v)[16], int lane) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        v[i] = mk(swap_add<false>(v[i].x, v[8 + i].x), swap_add<false>(v[i].y, v[8 + i].y));
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        v[i] = mk(swap_add<true>(v[i].x, v[4 + i].x), swap_add<true>(v[i].y, v[4 + i].y));
+    halve<2>(v, lane);
+    halve<1>(v, lane);
+    cplx a = v[0];
+    a = cadd(a, mk(__shfl_xor(a.x, 1, 64), __shfl_xor(a.y, 1, 64)));
+    a = cadd(a, mk(__shfl_xor(a.x, 2, 64), __shfl_xor(a.y, 2, 64)));
+    return a;
+}
+
 // w = H z (fine operator) and the projections of the Arnoldi step with
 // delayed reorthogonalisation: with u = V_{k-1} (the new, not yet
 // reorthogonalised vector), partial[i] = block sums of conj(V_i) u and
-// partial[k + i] = block sums of conj(V_i) w, i < k. For k <= KMAX the basis
-// values are loaded up front (all in flight together).
+// partial[k + i] = block sums of conj(V_i) w, i < k. A block of 256 threads
+// takes AD_NPT runs of 256 consecutive nodes; each thread sums its nodes'
+// products, then the sums are reduced over each wavefront (wave_sum16) and
+// over the four wavefronts in LDS. For k <= KMAX the basis values of a node
+// are loaded up front (all in flight together); beyond, in chunks of 8.
+constexpr int AD_NPT = 2;
+
 template <int NDIM, int KMAX, class ZC>
 __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const ZC* __restrict__ z,
                                                    cplx* __restrict__ w,
                                                    const cplx* __restrict__ V, int k,
                                                    cplx* __restrict__ partial,
                                                    const int* __restrict__ active, int64_t bs) {
-    const int rb = blockIdx.z;
+    const int rb = blockIdx.y;
     active = rhs_at(active, rb, bs);
     if (off(active)) return;
     z = rhs_nn(z, rb, bs);
     w = rhs_nn(w, rb, bs);
     V = rhs_nn(V, rb, bs);
     partial = rhs_nn(partial, rb, bs);
-    __shared__ cplx lds[KC * 256];
-    int ix, iz, tid;
-    if (NDIM == 2) {
-        ix = blockIdx.x * 64 + threadIdx.x;
-        iz = blockIdx.y * 4 + threadIdx.y;
-        tid = threadIdx.y * 64 + threadIdx.x;
-    } else {
-        ix = blockIdx.x * 256 + threadIdx.x;
-        iz = 0;
-        tid = threadIdx.x;
-    }
-    const int nb = gridDim.x * gridDim.y;
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-    const bool valid = ix < op.nx && iz < op.nz;
+    constexpr int NS = (KMAX > 0 ? KMAX : 8) * 2;          // staged sums per wavefront
+    __shared__ cplx wsum[4 * NS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nb = gridDim.x, blk = blockIdx.x;
     const int64_t n = (int64_t)op.nz * op.nx;
-    const int64_t p = valid ? (int64_t)iz * op.nx + ix : 0;
-    cplx v[KMAX > 0 ? KMAX : 1];
-    if (KMAX > 0) {
+    int64_t pr[AD_NPT];
+    bool ok[AD_NPT];
+    cplx ur[AD_NPT], wr[AD_NPT];
+    // w = H z on the block's nodes
 #pragma unroll
-        for (int i = 0; i < KMAX; ++i)
-            v[i] = (valid && i < k) ? V[(int64_t)i * n + p] : mk(0.0, 0.0);
-    }
-    const cplx up = valid ? V[(int64_t)(k - 1) * n + p] : mk(0.0, 0.0);
-    cplx wp = mk(0.0, 0.0);
-    if (valid) {
-        const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
-        const cplx zW = cconv<cplx>(z[ix > 0 ? p - 1 : p]);
-        const cplx zE = cconv<cplx>(z[ix < op.nx - 1 ? p + 1 : p]);
-        const cplx zp = cconv<cplx>(z[p]);
-        cplx sx = cadd(ix > 0 ? zW : mk(0.0, 0.0), ix < op.nx - 1 ? zE : mk(0.0, 0.0));
-        wp = csub(cmul(c.diag, zp), cscale(sx, c.cx));
-        if (NDIM == 2) {
-            const cplx zN = cconv<cplx>(z[iz > 0 ? p - op.nx : p]);
-            const cplx zS = cconv<cplx>(z[iz < op.nz - 1 ? p + op.nx : p]);
-            cplx sz = cadd(iz > 0 ? zN : mk(0.0, 0.0), iz < op.nz - 1 ? zS : mk(0.0, 0.0));
-            wp = csub(wp, cscale(sz, c.cz));
+    for (int r = 0; r < AD_NPT; ++r) {
+        const int64_t p0 = ((int64_t)blk * AD_NPT + r) * 256 + tid;
+        ok[r] = p0 < n;
+        const int64_t p = ok[r] ? p0 : 0;
+        pr[r] = p;
+        ur[r] = ok[r] ? V[(int64_t)(k - 1) * n + p] : mk(0.0, 0.0);
+        cplx wp = mk(0.0, 0.0);
+        if (ok[r]) {
+            const int iz = NDIM == 2 ? (int)(p / op.nx) : 0;
+            const int ix = NDIM == 2 ? (int)(p - (int64_t)iz * op.nx) : (int)p;
+            const Coef5 c = fine_coefs(op, iz, ix, op.m2[p]);
+            const cplx zW = cconv<cplx>(z[ix > 0 ? p - 1 : p]);
+            const cplx zE = cconv<cplx>(z[ix < op.nx - 1 ? p + 1 : p]);
+            const cplx zp = cconv<cplx>(z[p]);
+            const cplx sx = cadd(ix > 0 ? zW : mk(0.0, 0.0), ix < op.nx - 1 ? zE : mk(0.0, 0.0));
+            wp = csub(cmul(c.diag, zp), cscale(sx, c.cx));
+            if (NDIM == 2) {
+                const cplx zN = cconv<cplx>(z[iz > 0 ? p - op.nx : p]);
+                const cplx zS = cconv<cplx>(z[iz < op.nz - 1 ? p + op.nx : p]);
+                const cplx sz = cadd(iz > 0 ? zN : mk(0.0, 0.0), iz < op.nz - 1 ? zS : mk(0.0, 0.0));
+                wp = csub(wp, cscale(sz, c.cz));
+            }
+            w[p] = wp;
         }
-        w[p] = wp;
+        wr[r] = wp;
     }
     if (KMAX > 0) {
+        cplx acc[2][KMAX > 0 ? KMAX : 1];
 #pragma unroll
-        for (int set = 0; set < 2; ++set) {
-            const cplx x = set == 0 ? up : wp;
+        for (int i = 0; i < KMAX; ++i) acc[0][i] = acc[1][i] = mk(0.0, 0.0);
 #pragma unroll
-            for (int c0 = 0; c0 < KMAX; c0 += KC) {
-                if (c0 >= k) break;
-                cplx d[KC];
+        for (int r = 0; r < AD_NPT; ++r) {
+            cplx v[KMAX > 0 ? KMAX : 1];
 #pragma unroll
-                for (int c = 0; c < KC; ++c) d[c] = cmulc(v[c0 + c], x);
-                cplx sum;
-                int idx;
-                block_multi_sum(d, lds, tid, &sum, &idx);
-                if (idx >= 0 && c0 + idx < k)
-                    partial[(int64_t)(set * k + c0 + idx) * nb + blk] = sum;
+            for (int i = 0; i < KMAX; ++i)
+                v[i] = (ok[r] && i < k) ? V[(int64_t)i * n + pr[r]] : mk(0.0, 0.0);
+#pragma unroll
+            for (int i = 0; i < KMAX; ++i) {
+                acc[0][i] = cadd(acc[0][i], cmulc(v[i], ur[r]));
+                acc[1][i] = cadd(acc[1][i], cmulc(v[i], wr[r]));
             }
         }
+        // chunks of 8 basis vectors: values 0..7 against u, 8..15 against w
+#pragma unroll
+        for (int c0 = 0; c0 < KMAX; c0 += 8) {
+            if (c0 >= k) break;
+            cplx d[16];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                d[c] = acc[0][c0 + c];
+                d[8 + c] = acc[1][c0 + c];
+            }
+            const cplx t = wave_sum16(d, lane);
+            if ((lane & 3) == 0) wsum[wave * NS + c0 * 2 + (lane >> 2)] = t;
+        }
+        __syncthreads();
+        for (int t = tid; t < 2 * k; t += 256) {
+            const int set = t >= k, i = t - set * k;
+            const int slot = (i & ~7) * 2 + set * 8 + (i & 7);
+            cplx a = wsum[slot];
+#pragma unroll
+            for (int q = 1; q < 4; ++q) a = cadd(a, wsum[q * NS + slot]);
+            partial[(int64_t)t * nb + blk] = a;
+        }
     } else {
-        block_dots(V, n, k, valid, p, up, partial, nb, blk, lds, tid);
-        block_dots(V, n, k, valid, p, wp, partial + (int64_t)k * nb, nb, blk, lds, tid);
+        for (int c0 = 0; c0 < k; c0 += 8) {
+            cplx d[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) d[c] = mk(0.0, 0.0);
+#pragma unroll
+            for (int r = 0; r < AD_NPT; ++r) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const cplx v = (ok[r] && c0 + c < k) ? V[(int64_t)(c0 + c) * n + pr[r]]
+                                                         : mk(0.0, 0.0);
+                    d[c] = cadd(d[c], cmulc(v, ur[r]));
+                    d[8 + c] = cadd(d[8 + c], cmulc(v, wr[r]));
+                }
+            }
+            const cplx t = wave_sum16(d, lane);
+            if ((lane & 3) == 0) wsum[wave * NS + (lane >> 2)] = t;
+            __syncthreads();
+            if (tid < 16) {
+                const int set = tid >= 8, i = c0 + (tid & 7);
+                cplx a = wsum[tid];
+#pragma unroll
+                for (int q = 1; q < 4; ++q) a = cadd(a, wsum[q * NS + tid]);
+                if (i < k) partial[(int64_t)(set * k + i) * nb + blk] = a;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -653,12 +757,11 @@ static void apply_dot_dispatch(dim3 g, dim3 b, const FineOp& op, const ZC* z, cp
 template <class ZC>
 hipError_t apply_dot(const FineOp& op, const ZC* z, cplx* w, const cplx* V, int k, cplx* partial,
                      const int* active, hipStream_t s, const Batch& bt) {
+    const dim3 g(apply_blocks(op), bt.n), b(256);
     if (op.ndim == 2)
-        apply_dot_dispatch<2>(dim3((op.nx + 63) / 64, (op.nz + 3) / 4, bt.n), dim3(64, 4), op, z,
-                              w, V, k, partial, active, bt.bs, s);
+        apply_dot_dispatch<2>(g, b, op, z, w, V, k, partial, active, bt.bs, s);
     else
-        apply_dot_dispatch<1>(dim3((op.nx + 255) / 256, 1, bt.n), dim3(256), op, z, w, V, k,
-                              partial, active, bt.bs, s);
+        apply_dot_dispatch<1>(g, b, op, z, w, V, k, partial, active, bt.bs, s);
     return hipGetLastError();
 }
 
@@ -671,8 +774,12 @@ hipError_t launch_apply_dot(const FineOp& op, const cplxf* z, cplx* w, const cpl
     return apply_dot(op, z, w, V, k, partial, active, s, bt);
 }
 
-int apply_blocks(const FineOp& op) {
+int residual_blocks(const FineOp& op) {
     return op.ndim == 2 ? ((op.nx + 63) / 64) * ((op.nz + 3) / 4) : (op.nx + 255) / 256;
+}
+int apply_blocks(const FineOp& op) {
+    const int64_t n = (int64_t)op.nz * op.nx;
+    return (int)((n + 256 * AD_NPT - 1) / (256 * AD_NPT));
 }
 int node_blocks(int64_t n) { return (int)((n + 255) / 256); }
 int norm_blocks(int64_t n) { return node_blocks(n) < kNormBlocks ? node_blocks(n) : kNormBlocks; }
