@@ -144,19 +144,24 @@ __device__ inline void givens_dcgs(const GivensArgs& ga, int rb, bool tail, cplx
         st->k = 0;
         HostRecord* rec = a.rec;
         rec->jstep = 1;
-        __threadfence_system();
         rec->seq += 1;
         return;
     }
     const int col = j - 1;             // the column completed at this step
     const int ld = st->m + 1;
     scol[j] = mk(hn, 0.0);
+    // previous rotations; the entry carried from one rotation to the next stays
+    // in registers, so only the carry is a dependent chain (the other operands
+    // are loaded ahead)
+    cplx carry = scol[0];
     for (int i = 0; i < col; ++i) {
-        const cplx p = scol[i], q = scol[i + 1];
-        scol[i] = cadd(cscale(p, scs[i]), cmul(ssn[i], q));
-        scol[i + 1] = csub(cscale(q, scs[i]), cmulc(ssn[i], p));
+        const cplx q = scol[i + 1];
+        const double c = scs[i];
+        const cplx sn = ssn[i];
+        scol[i] = cadd(cscale(carry, c), cmul(sn, q));
+        carry = csub(cscale(q, c), cmulc(sn, carry));
     }
-    const cplx av = scol[col];
+    const cplx av = carry;
     double c;
     cplx s;
     if (hn == 0.0) {
@@ -198,9 +203,13 @@ __device__ inline void givens_dcgs(const GivensArgs& ga, int rb, bool tail, cplx
     rec->est = est;
     rec->jstep = tail ? j : j + 1;
     rec->status = st->status;
-    __threadfence_system();          // the fields above are visible before the flags
-    if (stop) rec->stops += 1;
-    rec->done = st->done;
+    if (stop) {
+        // the host reads the fields above once it sees the cycle stopped: make
+        // them visible first (a step that goes on needs no ordering)
+        __threadfence_system();
+        rec->stops += 1;
+        rec->done = st->done;
+    }
     rec->seq += 1;
 }
 
