@@ -173,9 +173,12 @@ __device__ __forceinline__ cplx wave_sum16(cplx (&v)[16], int lane) {
 // products, then the sums are reduced over each wavefront (wave_sum16) and
 // over the four wavefronts in LDS. For k <= KMAX the basis values of a node
 // are loaded up front (all in flight together); beyond, in chunks of 8.
-constexpr int AD_NPT = 2;
+// Two nodes per thread halve the reductions where the grid is small enough
+// for them to matter; on large grids one node per thread keeps two
+// wavefronts per SIMD in flight (ad_npt).
+inline int ad_npt(int64_t n) { return n < 262144 ? 2 : 1; }
 
-template <int NDIM, int KMAX, class ZC>
+template <int NDIM, int KMAX, class ZC, int AD_NPT>
 __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const ZC* __restrict__ z,
                                                    cplx* __restrict__ w,
                                                    const cplx* __restrict__ V, int k,
@@ -493,8 +496,19 @@ __global__ void __launch_bounds__(64) k_reduce_pred(const cplx* __restrict__ par
     out = rhs_nn(out, rb, bs);
     const int i = blockIdx.x;
     const cplx* pi = partial + (int64_t)i * nb;
+    // eight loads in flight per lane (issued from a clamped index and masked,
+    // so that no load waits behind a branch), summed in a fixed order
     cplx acc = mk(0.0, 0.0);
-    for (int t = threadIdx.x; t < nb; t += 64) acc = cadd(acc, pi[t]);
+    for (int t0 = threadIdx.x; t0 < nb; t0 += 64 * 8) {
+        cplx v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + 64 * u;
+            v[u] = cscale(pi[t < nb ? t : 0], t < nb ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = cadd(acc, v[u]);
+    }
     for (int o = 32; o > 0; o >>= 1) {
         acc.x += __shfl_down(acc.x, o, 64);
         acc.y += __shfl_down(acc.y, o, 64);
@@ -738,30 +752,36 @@ hipError_t launch_check_slowness(const double* m, int64_t n, double* m2, int* fl
     return hipGetLastError();
 }
 
-template <int NDIM, class ZC>
+template <int NDIM, class ZC, int NPT>
 static void apply_dot_dispatch(dim3 g, dim3 b, const FineOp& op, const ZC* z, cplx* w,
                                const cplx* V, int k, cplx* partial, const int* active,
                                int64_t bs, hipStream_t s) {
     if (k <= 8)
-        HH_LAUNCH((k_apply_dot<NDIM, 8, ZC>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
+        HH_LAUNCH((k_apply_dot<NDIM, 8, ZC, NPT>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
     else if (k <= 16)
-        HH_LAUNCH((k_apply_dot<NDIM, 16, ZC>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
+        HH_LAUNCH((k_apply_dot<NDIM, 16, ZC, NPT>), g, b, 0, s, op, z, w, V, k, partial, active,
+                  bs);
     else if (k <= 32)
-        HH_LAUNCH((k_apply_dot<NDIM, 32, ZC>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
+        HH_LAUNCH((k_apply_dot<NDIM, 32, ZC, NPT>), g, b, 0, s, op, z, w, V, k, partial, active,
+                  bs);
     else if (k <= 48)
-        HH_LAUNCH((k_apply_dot<NDIM, 48, ZC>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
+        HH_LAUNCH((k_apply_dot<NDIM, 48, ZC, NPT>), g, b, 0, s, op, z, w, V, k, partial, active,
+                  bs);
     else
-        HH_LAUNCH((k_apply_dot<NDIM, 0, ZC>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
+        HH_LAUNCH((k_apply_dot<NDIM, 0, ZC, NPT>), g, b, 0, s, op, z, w, V, k, partial, active, bs);
 }
 
 template <class ZC>
 hipError_t apply_dot(const FineOp& op, const ZC* z, cplx* w, const cplx* V, int k, cplx* partial,
                      const int* active, hipStream_t s, const Batch& bt) {
     const dim3 g(apply_blocks(op), bt.n), b(256);
-    if (op.ndim == 2)
-        apply_dot_dispatch<2>(g, b, op, z, w, V, k, partial, active, bt.bs, s);
+    const bool two = ad_npt((int64_t)op.nz * op.nx) == 2;
+    if (op.ndim == 2 && two)
+        apply_dot_dispatch<2, ZC, 2>(g, b, op, z, w, V, k, partial, active, bt.bs, s);
+    else if (op.ndim == 2)
+        apply_dot_dispatch<2, ZC, 1>(g, b, op, z, w, V, k, partial, active, bt.bs, s);
     else
-        apply_dot_dispatch<1>(g, b, op, z, w, V, k, partial, active, bt.bs, s);
+        apply_dot_dispatch<1, ZC, 2>(g, b, op, z, w, V, k, partial, active, bt.bs, s);
     return hipGetLastError();
 }
 
@@ -779,7 +799,8 @@ int residual_blocks(const FineOp& op) {
 }
 int apply_blocks(const FineOp& op) {
     const int64_t n = (int64_t)op.nz * op.nx;
-    return (int)((n + 256 * AD_NPT - 1) / (256 * AD_NPT));
+    const int npt = ad_npt(n);
+    return (int)((n + 256 * npt - 1) / (256 * npt));
 }
 int node_blocks(int64_t n) { return (int)((n + 255) / 256); }
 int norm_blocks(int64_t n) { return node_blocks(n) < kNormBlocks ? node_blocks(n) : kNormBlocks; }
