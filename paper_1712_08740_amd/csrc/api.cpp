@@ -368,7 +368,7 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const i
     if (p->ndim == 1) {
         // v in, z out; m^2 shared
         TIMED2(HH_KERNEL_PCR, (16.0 + es) * N, rs * N,
-               launch_pcr_norm(M, src, nullptr, nullptr, z, active, s, bt));
+               launch_pcr(M, src, z, active, s, bt));
         return HH_OK;
     }
     const int nl = (int)p->levels.size();

@@ -278,7 +278,6 @@ struct SolveState {
     double tol;
     double beta0;    // ||W f||
     double rel;      // last recomputed relative residual
-    double scale;    // 1/||w|| for the vector the next step normalises
 };
 
 // Progress record in pinned host memory, written by the device, polled by the
@@ -409,12 +408,11 @@ hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b
 // wdinv = wj / diag of a level operator (set-up)
 hipError_t launch_wdinv_fine(const FineOp& op, double wj, cplx* wdinv, hipStream_t s);
 hipError_t launch_wdinv_coarse(const CoarseOp& op, double wj, cplx* wdinv, hipStream_t s);
-// PCR with the normalisation of the Arnoldi vector folded in (vout = s*src, x = M^{-1} vout)
-hipError_t launch_pcr_norm(const FineOp& op, const cplx* src, const double* scale, cplx* vout,
-                           cplx* x, const int* active, hipStream_t s, const Batch& bt = Batch());
-hipError_t launch_pcr_norm(const FineOpT<float>& op, const cplx* src, const double* scale,
-                           cplx* vout, cplxf* x, const int* active, hipStream_t s,
-                           const Batch& bt = Batch());
+// 1D preconditioner x = M^{-1} src (PCR), predicated on *active
+hipError_t launch_pcr(const FineOp& op, const cplx* src, cplx* x, const int* active,
+                      hipStream_t s, const Batch& bt = Batch());
+hipError_t launch_pcr(const FineOpT<float>& op, const cplx* src, cplxf* x, const int* active,
+                      hipStream_t s, const Batch& bt = Batch());
 
 // precision conversions (set-up of the single-precision preconditioner), RNE
 hipError_t launch_to_f32(const double* a, float* b, int64_t n, hipStream_t s);

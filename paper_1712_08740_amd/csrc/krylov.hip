@@ -607,7 +607,6 @@ __global__ void __launch_bounds__(256) k_cycle_start(SolveState* st, const cplx*
         st->status = status;
     } else {
         st->active = 1;
-        st->scale = 1.0 / beta;
         g[0] = mk(beta, 0.0);
         for (int i = 1; i <= st->m; ++i) g[i] = mk(0.0, 0.0);
     }
@@ -714,7 +713,6 @@ __global__ void __launch_bounds__(256) k_solve_init(SolveState* st, const cplx* 
     st->j = 0;
     st->k = 0;
     st->active = 0;
-    st->scale = 0.0;
     st->rel = 0.0;
     st->done = 0;
     st->status = 0;

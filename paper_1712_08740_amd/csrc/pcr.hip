@@ -19,13 +19,10 @@ namespace {
 constexpr int PCR_THREADS = 1024;
 constexpr int PCR_MAXN = 1024;
 
-// d = s * src (s = *scale, or 1); vout = d when vout != nullptr (the normalised
-// Arnoldi vector, complex128); x = M^{-1} d in the operator's precision T.
+// x = M^{-1} src in the operator's precision T (src stays complex128).
 // Returns at once when *active == 0.
 template <class T>
 __global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOpT<T> op, const cplx* __restrict__ src,
-                                                     const double* __restrict__ scale,
-                                                     cplx* __restrict__ vout,
                                                      typename Cx<T>::type* __restrict__ x_out,
                                                      const int* __restrict__ active, int64_t bs) {
     typedef typename Cx<T>::type C;
@@ -33,13 +30,10 @@ __global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOpT<T> op, const cplx* 
     active = rhs_at(active, rb, bs);
     if (active && *active == 0) return;
     src = rhs_nn(src, rb, bs);
-    scale = rhs_at(scale, rb, bs);
-    vout = rhs_at(vout, rb, bs);
     x_out = rhs_nn(x_out, rb, bs);
     __shared__ C sa[PCR_MAXN], sb[PCR_MAXN], sc[PCR_MAXN], sd[PCR_MAXN];
     const int n = op.nx;
     const int i = threadIdx.x;
-    const double sv = scale ? scale[0] : 1.0;
     const C zero = czero<C>();
     if (i < n) {
         const Coef5T<T> c = fine_coefs(op, 0, i, op.m2[i]);
@@ -49,9 +43,7 @@ __global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOpT<T> op, const cplx* 
         sa[i] = lo;
         sc[i] = up;
         sb[i] = c.diag;
-        const cplx d = cscale(src[i], sv);
-        sd[i] = cconv<C>(d);
-        if (vout) vout[i] = d;
+        sd[i] = cconv<C>(src[i]);
     }
     __syncthreads();
     for (int s = 1; s < n; s <<= 1) {
@@ -86,28 +78,26 @@ __global__ void __launch_bounds__(PCR_THREADS) k_pcr(FineOpT<T> op, const cplx* 
 }
 
 template <class T>
-hipError_t pcr(const FineOpT<T>& op, const cplx* src, const double* scale, cplx* vout,
-               typename Cx<T>::type* x, const int* active, hipStream_t s, const Batch& bt) {
+hipError_t pcr(const FineOpT<T>& op, const cplx* src, typename Cx<T>::type* x, const int* active,
+               hipStream_t s, const Batch& bt) {
     if (op.ndim != 1 || op.nx > PCR_MAXN) return hipErrorInvalidValue;
-    HH_LAUNCH((k_pcr<T>), dim3(bt.n), dim3(PCR_THREADS), 0, s, op, src, scale, vout, x, active,
-              bt.bs);
+    HH_LAUNCH((k_pcr<T>), dim3(bt.n), dim3(PCR_THREADS), 0, s, op, src, x, active, bt.bs);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_pcr_solve(const FineOp& op, const cplx* d, cplx* x, hipStream_t s) {
-    return launch_pcr_norm(op, d, nullptr, nullptr, x, nullptr, s);
+    return launch_pcr(op, d, x, nullptr, s);
 }
 
-hipError_t launch_pcr_norm(const FineOp& op, const cplx* src, const double* scale, cplx* vout,
-                           cplx* x, const int* active, hipStream_t s, const Batch& bt) {
-    return pcr(op, src, scale, vout, x, active, s, bt);
+hipError_t launch_pcr(const FineOp& op, const cplx* src, cplx* x, const int* active,
+                      hipStream_t s, const Batch& bt) {
+    return pcr(op, src, x, active, s, bt);
 }
-hipError_t launch_pcr_norm(const FineOpT<float>& op, const cplx* src, const double* scale,
-                           cplx* vout, cplxf* x, const int* active, hipStream_t s,
-                           const Batch& bt) {
-    return pcr(op, src, scale, vout, x, active, s, bt);
+hipError_t launch_pcr(const FineOpT<float>& op, const cplx* src, cplxf* x, const int* active,
+                      hipStream_t s, const Batch& bt) {
+    return pcr(op, src, x, active, s, bt);
 }
 
 }  // namespace hh

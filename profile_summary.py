@@ -28,9 +28,9 @@ CSRC = os.path.join(ROOT, "paper_1712_08740_amd", "csrc")
 
 # kernel class of the solve's kernel timer -> (kernel-name prefix, source files)
 CLASSES = {
-    "vc_down": ("k_down<Fine5", ["vcycle_tiled.hip", "hh_internal.h", "givens.h"]),
+    "vc_down": ("k_down<Fine5", ["vcycle_tiled.hip", "hh_internal.h"]),
     "vc_up": ("k_up<Fine5", ["vcycle_tiled.hip", "hh_internal.h"]),
-    "vc_down_coarse": ("k_down<Coarse9", ["vcycle_tiled.hip", "hh_internal.h", "givens.h"]),
+    "vc_down_coarse": ("k_down<Coarse9", ["vcycle_tiled.hip", "hh_internal.h"]),
     "vc_up_coarse": ("k_up<Coarse9", ["vcycle_tiled.hip", "hh_internal.h"]),
     "gemv": ("k_gemv_pred", ["coarsest.hip", "hh_internal.h"]),
     "apply_dot": ("k_apply_dot", ["krylov.hip", "hh_internal.h", "givens.h"]),
@@ -63,8 +63,8 @@ def kernels(db: str, title: str, cmd: str) -> str:
     out = [f"# {title}", "", "Command (on the MI355X, from the repository root):", "",
            f"    {cmd}", "",
            "Kernel durations from `rocprofv3 --kernel-trace --stats` (top_kernels); "
-           "times in microseconds. Set-up kernels (Galerkin products, Gauss-Jordan "
-           "inversion) run once per problem.", "",
+           "times in microseconds. Set-up kernels (Galerkin products, banded LU and "
+           "inverse of the coarsest operator) run once per problem.", "",
            "| kernel | calls | total us | avg us | % |", "|---|---:|---:|---:|---:|"]
     for n, c, t, a, p in rows:
         out.append(f"| {_short(n)} | {c} | {t:.1f} | {a:.3f} | {p:.1f} |")
