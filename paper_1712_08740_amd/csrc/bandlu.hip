@@ -77,6 +77,150 @@ __global__ void __launch_bounds__(LU_THREADS) k_band_lu(cplx* __restrict__ AB, i
     }
 }
 
+// 1 / z as conj(z) / |z|^2, the real reciprocal from the hardware estimate
+// refined by two Newton steps (exact division when |z|^2 is not a normal
+// number well inside the range)
+__device__ __forceinline__ cplx crecip(cplx z) {
+    const double d = z.x * z.x + z.y * z.y;
+    if (!(d > 1e-290 && d < 1e290)) return cdiv(mk(1.0, 0.0), z);
+    double r = __builtin_amdgcn_rcp(d);
+    r = r * (2.0 - d * r);
+    r = r * (2.0 - d * r);
+    return mk(z.x * r, -z.y * r);
+}
+
+// a -= l y with four fused multiply-adds
+__device__ __forceinline__ void msub4(cplx& a, cplx l, cplx y) {
+    a.x = fma(-l.x, y.x, a.x);
+    a.x = fma(l.y, y.y, a.x);
+    a.y = fma(-l.x, y.y, a.y);
+    a.y = fma(-l.y, y.x, a.y);
+}
+
+// Blocked right-looking LU without pivoting of the band (one workgroup of
+// LU_T threads). Columns are taken LU_P at a time. The panel (rows k0 ..
+// k0+kp+b-1 of those columns) and the block U12 of U to its right (rows k0 ..
+// k0+kp-1, the b columns after the panel) are factored in registers: thread i
+// holds panel row i, thread nr + j column j of U12. At each column the pivot
+// row and the column below the pivot are published in LDS (double buffered:
+// one barrier per column), every panel row scales its entry and updates the
+// rest of its row, every U12 column updates its entries below the pivot.
+// Then the trailing b x b block takes the rank-kp update L21 U12 from global
+// memory, each thread a 4 x 4 tile in registers. Entries outside the band are
+// zero and stay zero. flag[0] = 1 on a zero or non-finite pivot.
+// LDS: 2 b LU_P + 4 LU_P complex.
+constexpr int LU_P = 16;
+constexpr int LU_T = 512;
+
+__host__ __device__ inline size_t lu_blk_lds(int b) {
+    return (size_t)(2 * b * LU_P + 4 * LU_P) * sizeof(cplx);
+}
+
+__global__ void __launch_bounds__(LU_T) k_band_lu_blk(cplx* __restrict__ AB, int n, int b,
+                                                      int* __restrict__ flag) {
+    extern __shared__ cplx lds[];
+    const int w = 2 * b + 1;
+    const int tid = threadIdx.x;
+    cplx* l21 = lds;                             // [b][LU_P]: panel rows below the top block
+    cplx* u12 = lds + b * LU_P;                  // [LU_P][b]
+    cplx* brow = u12 + LU_P * b;                 // [2][LU_P]: pivot row
+    cplx* bcol = brow + 2 * LU_P;                // [2][LU_P]: column below the pivot, top block
+    auto at = [&](int r, int c) -> cplx* { return AB + (int64_t)r * w + (c - r + b); };
+    for (int k0 = 0; k0 < n; k0 += LU_P) {
+        const int kp = min(LU_P, n - k0);
+        const int nr = min(kp + b, n - k0);          // panel rows
+        const int nc = min(b, n - k0 - kp);          // columns of U12 and of the trailing block
+        const bool isrow = tid < nr, iscol = !isrow && tid < nr + nc;
+        const int j = tid - nr;
+        // every load is issued (from entry 0 when out of range) and masked: loads
+        // under branches would each be waited for before the next is issued
+        cplx v[LU_P];
+#pragma unroll
+        for (int t = 0; t < LU_P; ++t) {
+            const bool okr = isrow && t < kp && tid - t <= b && t - tid <= b;
+            const bool okc = iscol && t < kp && kp + j - t <= b;
+            const cplx* q = okr ? at(k0 + tid, k0 + t) : okc ? at(k0 + t, k0 + kp + j) : AB;
+            v[t] = cscale(*q, (okr || okc) ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int c = 0; c < LU_P; ++c) {
+            if (c < kp) {                        // uniform: kp < LU_P only for the last panel
+            const int par = c & 1;
+            if (isrow && tid == c) {
+#pragma unroll
+                for (int t = c; t < LU_P; ++t) brow[par * LU_P + t] = v[t];
+            }
+            if (isrow && tid > c && tid < kp) bcol[par * LU_P + tid] = v[c];
+            __syncthreads();
+            const cplx piv = brow[par * LU_P + c];
+            if (tid == 0 && !(isfinite(piv.x) && isfinite(piv.y) && (piv.x != 0.0 || piv.y != 0.0)))
+                *flag = 1;
+            const cplx ip = crecip(piv);
+            if (isrow && tid > c) {
+                const cplx l = cmul(v[c], ip);
+                v[c] = l;
+#pragma unroll
+                for (int t = c + 1; t < LU_P; ++t) msub4(v[t], l, brow[par * LU_P + t]);
+            }
+            if (iscol) {
+                const cplx uc = v[c];
+#pragma unroll
+                for (int i = c + 1; i < LU_P; ++i)
+                    if (i < kp) msub4(v[i], cmul(bcol[par * LU_P + i], ip), uc);
+            }
+            }
+        }
+        // factors out; L21 and U12 into LDS for the trailing update
+        if (isrow) {
+#pragma unroll
+            for (int t = 0; t < LU_P; ++t) {
+                if (t < kp && tid - t <= b && t - tid <= b) *at(k0 + tid, k0 + t) = v[t];
+                if (tid >= kp) l21[(tid - kp) * LU_P + t] = v[t];
+            }
+        }
+        if (iscol) {
+#pragma unroll
+            for (int t = 0; t < LU_P; ++t) {
+                if (t < kp && kp + j - t <= b) *at(k0 + t, k0 + kp + j) = v[t];
+                u12[t * b + j] = v[t];
+            }
+        }
+        __syncthreads();
+        // trailing block: rows and columns k0+kp .. (nr - kp rows, nc columns)
+        const int r22 = nr - kp;
+        const int tr = (r22 + 3) / 4, tc = (nc + 3) / 4;
+        for (int e = tid; e < tr * tc; e += LU_T) {
+            const int r0 = 4 * (e / tc), c0 = 4 * (e % tc);
+            cplx acc[4][4];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool ok = r0 + a < r22 && c0 + q < nc;
+                    acc[a][q] = cscale(*(ok ? at(k0 + kp + r0 + a, k0 + kp + c0 + q) : AB),
+                                       ok ? 1.0 : 0.0);
+                }
+            for (int t = 0; t < kp; ++t) {
+                cplx l[4], u[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) l[a] = r0 + a < r22 ? l21[(r0 + a) * LU_P + t] : mk(0.0, 0.0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) u[q] = c0 + q < nc ? u12[t * b + c0 + q] : mk(0.0, 0.0);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) msub4(acc[a][q], l[a], u[q]);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (r0 + a < r22 && c0 + q < nc) *at(k0 + kp + r0 + a, k0 + kp + c0 + q) = acc[a][q];
+        }
+        __syncthreads();
+    }
+}
+
 // Lc[i][t] = L(i+1+t, i), Uc[i][t] = U(i-1-t, i) (0 outside), Ui[i] = 1 / U(i, i)
 __global__ void __launch_bounds__(256) k_band_split(const cplx* __restrict__ AB, int64_t n, int b,
                                                     cplx* __restrict__ Lc, cplx* __restrict__ Uc,
@@ -317,7 +461,11 @@ hipError_t band_invert(int nz, int nx, cplx* A, void* scratch, int* flag, bool n
     cplx* Ui = Uc + n * b;
     HH_LAUNCH(k_band_extract, dim3((unsigned)((n * (2 * b + 1) + 255) / 256)), dim3(256), 0, s, A,
               n, b, num, AB);
-    HH_LAUNCH(k_band_lu, dim3(1), dim3(LU_THREADS), 0, s, AB, (int)n, b, flag);
+    const size_t lu_lds = lu_blk_lds(b);
+    if (lu_lds <= 65536)                          // b <= 125
+        HH_LAUNCH(k_band_lu_blk, dim3(1), dim3(LU_T), lu_lds, s, AB, (int)n, b, flag);
+    else
+        HH_LAUNCH(k_band_lu, dim3(1), dim3(LU_THREADS), 0, s, AB, (int)n, b, flag);
     HH_LAUNCH(k_band_split, dim3((unsigned)((n * b + 255) / 256)), dim3(256), 0, s, AB, n, b, Lc,
               Uc, Ui);
     // the window of a block of R rows reaches b rows further: 1 + ceil(b / R) slots
