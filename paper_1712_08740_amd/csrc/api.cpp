@@ -90,6 +90,8 @@ struct hh_problem_s {
     std::vector<LevelData> levels;
     cplx* cinv = nullptr;           // explicit inverse of the coarsest operator
     cplxf* cinvf = nullptr;         // ... rounded to complex64
+    cplx* pcr = nullptr;            // 1D: reduction multipliers of M (pcr_factor_elems)
+    cplxf* pcrf = nullptr;          // ... of the complex64 operator
     int nc = 0;
     int max_coarse = HH_MAX_COARSE; // largest coarsest grid inverted densely
     void* band = nullptr;           // banded LU scratch of the coarsest inverse
@@ -185,11 +187,13 @@ template <> struct Prec<double> {
     static FineOp fine(const hh_problem_s* p) { return op_M(p); }
     static CoarseOp coarse(const LevelData& L) { return coarse_op(L); }
     static const cplx* cinv(const hh_problem_s* p) { return p->cinv; }
+    static const cplx* pcr(const hh_problem_s* p) { return p->pcr; }
 };
 template <> struct Prec<float> {
     static FineOpT<float> fine(const hh_problem_s* p) { return op_Mf(p); }
     static CoarseOpT<float> coarse(const LevelData& L) { return coarse_opf(L); }
     static const cplxf* cinv(const hh_problem_s* p) { return p->cinvf; }
+    static const cplxf* pcr(const hh_problem_s* p) { return p->pcrf; }
 };
 
 // ---------------------------------------------------------------------------
@@ -368,7 +372,7 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const i
     if (p->ndim == 1) {
         // v in, z out; m^2 shared
         TIMED2(HH_KERNEL_PCR, (16.0 + es) * N, rs * N,
-               launch_pcr(M, src, z, active, s, bt));
+               launch_pcr((int)p->N, Prec<T>::pcr(p), src, z, active, s, bt));
         return HH_OK;
     }
     const int nl = (int)p->levels.size();
@@ -413,9 +417,13 @@ void free_levels(hh_problem_s* p) {
     p->levels.clear();
     if (p->cinv) (void)hipFree(p->cinv);
     if (p->cinvf) (void)hipFree(p->cinvf);
+    if (p->pcr) (void)hipFree(p->pcr);
+    if (p->pcrf) (void)hipFree(p->pcrf);
     if (p->band) (void)hipFree(p->band);
     p->cinv = nullptr;
     p->cinvf = nullptr;
+    p->pcr = nullptr;
+    p->pcrf = nullptr;
     p->band = nullptr;
 }
 
@@ -482,6 +490,9 @@ size_t problem_bytes(const hh_problem_s* p) {
         const LevelData& lc = p->levels.back();
         b += align_up(nc * nc * sizeof(cplx)) + align_up(nc * nc * sizeof(cplxf)) +
              align_up(band_scratch_bytes(lc.nz, lc.nx));
+    } else {
+        const size_t e = pcr_factor_elems((int)p->N);
+        b += align_up(e * sizeof(cplx)) + align_up(e * sizeof(cplxf));
     }
     return b;
 }
@@ -490,7 +501,12 @@ int build_hierarchy(hh_problem_s* p) {
     free_levels(p);
     CHK(plan_levels(p));
     const int64_t nc = p->nc;
-    if (p->ndim == 1) return HH_OK;
+    if (p->ndim == 1) {
+        const size_t e = pcr_factor_elems((int)p->N);
+        HIPCHK(hipMalloc(&p->pcr, e * sizeof(cplx)));
+        HIPCHK(hipMalloc(&p->pcrf, e * sizeof(cplxf)));
+        return HH_OK;
+    }
     for (size_t l = 1; l < p->levels.size(); ++l) {
         HIPCHK(hipMalloc(&p->levels[l].C, 9 * (size_t)p->levels[l].size() * sizeof(cplx)));
         HIPCHK(hipMalloc(&p->levels[l].Cf, 9 * (size_t)p->levels[l].size() * sizeof(cplxf)));
@@ -507,8 +523,13 @@ int build_hierarchy(hh_problem_s* p) {
 }
 
 int apply_shift(hh_problem_s* p) {
-    if (p->ndim == 1) return HH_OK;
     hipStream_t s = p->stream;
+    if (p->ndim == 1) {                 // the reduction multipliers of M in both precisions
+        HIPCHK(launch_pcr_factor(op_M(p), p->pcr, s));
+        HIPCHK(launch_pcr_factor(op_Mf(p), p->pcrf, s));
+        HIPCHK(hipStreamSynchronize(s));
+        return HH_OK;
+    }
     const int nl = (int)p->levels.size();
     const FineOp M = op_M(p);
     for (int l = 1; l < nl; ++l) {

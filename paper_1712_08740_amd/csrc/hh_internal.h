@@ -253,9 +253,8 @@ hipError_t band_invert(int nz, int nx, cplx* A, void* scratch, int* flag, bool n
                        hipStream_t s);
 
 // ---------------------------------------------------------------------------
-// launchers (pcr.hip): exact solve of the 1D tridiagonal shifted Laplacian
+// launchers (krylov.hip): right-hand side, Arnoldi steps, solve control
 // ---------------------------------------------------------------------------
-hipError_t launch_pcr_solve(const FineOp& op, const cplx* d, cplx* x, hipStream_t s);
 
 // b = W f
 hipError_t launch_weight_rhs(const FineOp& op, const cplx* f, cplx* b, hipStream_t s,
@@ -408,10 +407,17 @@ hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b
 // wdinv = wj / diag of a level operator (set-up)
 hipError_t launch_wdinv_fine(const FineOp& op, double wj, cplx* wdinv, hipStream_t s);
 hipError_t launch_wdinv_coarse(const CoarseOp& op, double wj, cplx* wdinv, hipStream_t s);
-// 1D preconditioner x = M^{-1} src (PCR), predicated on *active
-hipError_t launch_pcr(const FineOp& op, const cplx* src, cplx* x, const int* active,
+// 1D preconditioner x = M^{-1} src by parallel cyclic reduction (pcr.hip):
+// the multipliers of every step and the final diagonal of M (op), computed
+// once per shift into f (pcr_factor_elems(n) values), then applied per
+// right-hand side, predicated on *active
+int pcr_levels(int n);
+size_t pcr_factor_elems(int n);
+hipError_t launch_pcr_factor(const FineOp& op, cplx* f, hipStream_t s);
+hipError_t launch_pcr_factor(const FineOpT<float>& op, cplxf* f, hipStream_t s);
+hipError_t launch_pcr(int n, const cplx* f, const cplx* src, cplx* x, const int* active,
                       hipStream_t s, const Batch& bt = Batch());
-hipError_t launch_pcr(const FineOpT<float>& op, const cplx* src, cplxf* x, const int* active,
+hipError_t launch_pcr(int n, const cplxf* f, const cplx* src, cplxf* x, const int* active,
                       hipStream_t s, const Batch& bt = Batch());
 
 // precision conversions (set-up of the single-precision preconditioner), RNE

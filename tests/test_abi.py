@@ -106,8 +106,14 @@ def test_footprint_plans_the_oracle_hierarchy(lib):
         N = w.slowness.size
         assert wb2 - wb >= 2 * 30 * N * 16          # 30 more V and Z columns
         assert wb3 >= 3 * wb
+    # 1D: m^2 in both precisions, the fixed scratch, and the cyclic-reduction
+    # multipliers of M (two per step, ten steps for 1001 nodes, plus the final
+    # diagonal) in complex128 and complex64
     pb, wb = lib.footprint_bytes((1001,), 2 * np.pi * 10, 1 / 1500, 5.0, restart=50)
-    assert pb < 100_000 and wb >= (51 + 50) * 1001 * 16
+    e = (2 * 10 + 1) * 1001
+    expect = 12 * 1001 + 16 * 4096 + 24 * e
+    assert expect <= pb <= expect + 256 * 8
+    assert wb >= (51 + 50) * 1001 * 16
 
 
 def test_footprint_rejects_bad_arguments(lib):

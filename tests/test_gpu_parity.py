@@ -223,6 +223,22 @@ def test_solve_small_and_ragged(hh, shape, freq, restart):
     _check_solve(res, ref, 1e-8)
 
 
+def test_restart_one_matches_oracle(hh):
+    """GMRES(1): every cycle is one Arnoldi step closed by the end-of-cycle
+    projections (no step hosts a Givens update), so status, iteration count and
+    residual history must follow the oracle step by step."""
+    m = _model((37,), 10.0, seed=4)
+    omega = 2 * np.pi * 5.0
+    f = wl.random_complex((37,), 8)
+    P = _problem(hh, m, omega, 0.01, 10.0)
+    res = P.solve(_t(f), tol=1e-8, restart=1, max_iters=40)
+    ref = solver.solve(m, omega, 0.01, 10.0, f, tol=1e-8, restart=1, maxiter=40)
+    assert res.status == ref.status and res.iterations == ref.iterations
+    n = min(len(res.history), len(ref.history))
+    r = np.asarray(ref.history[:n])
+    assert np.all(np.abs(res.history[:n] - r) <= 1e-6 * r)
+
+
 def test_unpreconditioned_matches_oracle(hh):
     w = wl.layered_1d(301, 5.0, 10.0, src=50)
     P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
