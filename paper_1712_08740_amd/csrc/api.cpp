@@ -1119,9 +1119,9 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
         executed.push_back(ex);
         if (!any_stopped) break;                    // every right-hand side finished at the start
         if (f32)
-            HIPCHK(launch_cycle_finish(st, R, g, zs, y, Zf, N, u, s, bt));
+            HIPCHK(launch_cycle_finish(st, m, R, g, zs, y, Zf, N, u, s, bt));
         else
-            HIPCHK(launch_cycle_finish(st, R, g, zs, y, Z, N, u, s, bt));
+            HIPCHK(launch_cycle_finish(st, m, R, g, zs, y, Z, N, u, s, bt));
         if (all_done) break;                        // non-finite values inside the cycle
     }
     HIPCHK(hipStreamSynchronize(s));

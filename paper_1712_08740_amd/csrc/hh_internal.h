@@ -338,12 +338,13 @@ hipError_t launch_axpy_dcgs(cplx* V, int64_t n, int j, const cplx* red, const cp
 // the Givens step closing a full cycle (red = [V_{0..m-1}^H V_m, V_m^H V_m])
 hipError_t launch_givens_tail(const GivensArgs& a, hipStream_t s, const Batch& bt = Batch());
 // y = R^{-1} g, x += Z y for the st->k columns of the cycle, then st->k = 0
-hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, const double* zs,
-                               cplx* y, const cplx* Z, int64_t n, cplx* x, hipStream_t s,
-                               const Batch& bt = Batch());
-hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, const double* zs,
-                               cplx* y, const cplxf* Z, int64_t n, cplx* x, hipStream_t s,
-                               const Batch& bt = Batch());
+// (m: the restart length, an upper bound of the columns st->k)
+hipError_t launch_cycle_finish(SolveState* st, int m, const cplx* R, const cplx* g,
+                               const double* zs, cplx* y, const cplx* Z, int64_t n, cplx* x,
+                               hipStream_t s, const Batch& bt = Batch());
+hipError_t launch_cycle_finish(SolveState* st, int m, const cplx* R, const cplx* g,
+                               const double* zs, cplx* y, const cplxf* Z, int64_t n, cplx* x,
+                               hipStream_t s, const Batch& bt = Batch());
 hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
                              double tol, HostRecord* rec, double* hist, int64_t hist_stride,
                              hipStream_t s, const Batch& bt = Batch());

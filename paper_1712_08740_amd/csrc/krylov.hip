@@ -658,6 +658,53 @@ __global__ void __launch_bounds__(256) k_backsub_pred(const SolveState* st,
     }
 }
 
+// The same for k <= 32 columns by one wavefront: lane l holds g_l and the
+// entries R[l, i] of every column (loaded up front, off the recurrence) and
+// forms 1 / R[l, l] before it starts; column i then costs two broadcasts and
+// one multiply-add per lane, with no barrier.
+constexpr int BS_MAX = 32;
+
+__device__ __forceinline__ cplx bcast(cplx v, int src) {
+    return mk(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+}
+
+__global__ void __launch_bounds__(64) k_backsub_wave(const SolveState* st,
+                                                     const cplx* __restrict__ R,
+                                                     const cplx* __restrict__ g,
+                                                     const double* __restrict__ zs,
+                                                     cplx* __restrict__ y, int64_t bs) {
+    const int rb = blockIdx.x;
+    st = rhs_nn(st, rb, bs);
+    R = rhs_nn(R, rb, bs);
+    g = rhs_nn(g, rb, bs);
+    zs = rhs_nn(zs, rb, bs);
+    y = rhs_nn(y, rb, bs);
+    const int k = st->k;
+    if (k == 0) return;
+    const int ld = st->m + 1;
+    const int lane = threadIdx.x;
+    const bool mine = lane < k;
+    const int lc = mine ? lane : 0;
+    cplx r[BS_MAX];
+#pragma unroll
+    for (int i = 0; i < BS_MAX; ++i) {
+        const bool ok = i < k && lane < i;
+        r[i] = cscale(R[ok ? lane + (int64_t)i * ld : 0], ok ? 1.0 : 0.0);
+    }
+    cplx gl = cscale(g[lc], mine ? 1.0 : 0.0);
+    const cplx dl = R[lc + (int64_t)lc * ld];
+    const cplx rinv = cdiv(mk(1.0, 0.0), dl);
+    const double zl = zs[lc];
+#pragma unroll
+    for (int i = BS_MAX - 1; i >= 0; --i) {
+        if (i < k) {
+            const cplx yi = cmul(bcast(gl, i), bcast(rinv, i));
+            gl = csub(gl, cmul(r[i], yi));
+            if (lane == i) y[i] = cscale(yi, zl);
+        }
+    }
+}
+
 template <class ZC>
 __global__ void __launch_bounds__(256) k_update_pred(const SolveState* st,
                                                      const ZC* __restrict__ Z, int64_t n,
@@ -875,23 +922,28 @@ hipError_t launch_axpy_dcgs(cplx* V, int64_t n, int j, const cplx* red, const cp
     return hipGetLastError();
 }
 template <class ZC>
-hipError_t cycle_finish(SolveState* st, const cplx* R, const cplx* g, const double* zs, cplx* y,
-                        const ZC* Z, int64_t n, cplx* x, hipStream_t s, const Batch& bt) {
-    HH_LAUNCH(k_backsub_pred, dim3(bt.n), dim3(256), 0, s, st, R, g, zs, y, bt.bs);
+hipError_t cycle_finish(SolveState* st, int m, const cplx* R, const cplx* g, const double* zs,
+                        cplx* y, const ZC* Z, int64_t n, cplx* x, hipStream_t s,
+                        const Batch& bt) {
+    // k <= restart: one wavefront when the restart length allows it
+    if (m <= BS_MAX)
+        HH_LAUNCH(k_backsub_wave, dim3(bt.n), dim3(64), 0, s, st, R, g, zs, y, bt.bs);
+    else
+        HH_LAUNCH(k_backsub_pred, dim3(bt.n), dim3(256), 0, s, st, R, g, zs, y, bt.bs);
     HH_LAUNCH(k_update_pred<ZC>, dim3(node_blocks(n), bt.n), dim3(256), 0, s, st, Z, n, y, x,
               bt.bs, bt.fs);
     HH_LAUNCH(k_cycle_end, dim3(bt.n), dim3(64), 0, s, st, bt.bs);
     return hipGetLastError();
 }
-hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, const double* zs,
-                               cplx* y, const cplx* Z, int64_t n, cplx* x, hipStream_t s,
-                               const Batch& bt) {
-    return cycle_finish(st, R, g, zs, y, Z, n, x, s, bt);
+hipError_t launch_cycle_finish(SolveState* st, int m, const cplx* R, const cplx* g,
+                               const double* zs, cplx* y, const cplx* Z, int64_t n, cplx* x,
+                               hipStream_t s, const Batch& bt) {
+    return cycle_finish(st, m, R, g, zs, y, Z, n, x, s, bt);
 }
-hipError_t launch_cycle_finish(SolveState* st, const cplx* R, const cplx* g, const double* zs,
-                               cplx* y, const cplxf* Z, int64_t n, cplx* x, hipStream_t s,
-                               const Batch& bt) {
-    return cycle_finish(st, R, g, zs, y, Z, n, x, s, bt);
+hipError_t launch_cycle_finish(SolveState* st, int m, const cplx* R, const cplx* g,
+                               const double* zs, cplx* y, const cplxf* Z, int64_t n, cplx* x,
+                               hipStream_t s, const Batch& bt) {
+    return cycle_finish(st, m, R, g, zs, y, Z, n, x, s, bt);
 }
 hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
                              double tol, HostRecord* rec, double* hist, int64_t hist_stride,

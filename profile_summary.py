@@ -38,7 +38,7 @@ CLASSES = {
     "axpy_norm": ("k_dot_blocks", ["krylov.hip", "hh_internal.h", "givens.h"]),
     "givens": ("k_givens_tail", ["krylov.hip", "hh_internal.h", "givens.h"]),
     "reduce": ("k_reduce_pred", ["krylov.hip", "hh_internal.h", "givens.h"]),
-    "pcr": ("k_pcr", ["pcr.hip", "hh_internal.h"]),
+    "pcr": ("k_pcr_apply", ["pcr.hip", "hh_internal.h"]),
 }
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 COPY_KIB = 256 * 1024
