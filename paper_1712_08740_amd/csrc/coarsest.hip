@@ -81,83 +81,163 @@ __global__ void __launch_bounds__(256) k_gemv_batch(int n, const C* __restrict__
 }
 
 // Y = A X for a batch of right-hand sides (the coarsest solve of every source
-// at once): A row-major n x n, column b of X and Y in right-hand side b's
-// workspace (bs bytes after column b - 1).
+// at once) on the matrix cores: A row-major n x n, column b of X and Y in
+// right-hand side b's workspace (bs bytes after column b - 1).
 //
-// k_coarsest_gemm: a block owns 64 rows, 32 right-hand sides (group
-// blockIdx.y) and one of KS contiguous ranges of k (blockIdx.z), streamed
-// through LDS in chunks of 32 (the next chunk's loads are issued before the
-// current chunk is consumed). Thread (r, g) owns row r and right-hand sides
-// 8g..8g+7 and sums its k range in increasing order into part[z][col][row].
-// k_coarsest_sum adds the KS partial sums in order: every result depends only
-// on A and its own column, in a fixed order. A is read once per group of 32
-// right-hand sides; X once per 64 rows.
-constexpr int GM_TM = 64, GM_TK = 32, GM_TN = 32;
+// With A's complex entries stored as interleaved (re, im) pairs, A is a real
+// n x 2n matrix A_r, and for x = X(:, b)
+//   Re Y(:, b) = A_r [Re x_0, -Im x_0, Re x_1, -Im x_1, ...]^T,
+//   Im Y(:, b) = A_r [Im x_0,  Re x_0, Im x_1,  Re x_1, ...]^T,
+// so one real product with 2n terms gives both parts of every output.
+//
+// k_coarsest_mfma: a block of four waves owns 128 rows (32 per wave: two
+// 16-row tiles), 32 right-hand sides (group blockIdx.y: two 16-column tiles,
+// each for the real and the imaginary part) and one of KS contiguous ranges of
+// k (blockIdx.z), stepping 16 complex k at a time. A is loaded once, straight
+// into registers, the next step's loads in flight while the current one is
+// multiplied; X comes from the L2 (it is read by every row block).
+// MFMA 16x16x4 (f32 or f64): lane l supplies A(l%16, l/16) and B(l/16, l%16)
+// and receives in accumulator r the entry of column l%16 and row 4(l/16)+r
+// (f32) or l/16+4r (f64). Lane (i, q) of a tile holds
+// complex entries 4u + q (u = 0..3) of its row (or column) in the step, so one
+// load instruction reads 4 consecutive entries per row; each u is fed as two
+// k-slices (real parts, then imaginary parts). The order of the terms is fixed:
+// every result depends only on A and its own column.
+// k_coarsest_sum adds the KS partial sums in order.
+constexpr int MF_TM = 128, MF_TN = 32, MF_KC = 16;
 
-template <class C>
-__global__ void __launch_bounds__(256) k_coarsest_gemm(int n, const C* __restrict__ A,
-                                                       const C* __restrict__ X, int nrhs,
-                                                       int64_t bs, int chunks_per_split,
-                                                       C* __restrict__ part) {
-    constexpr int TM = GM_TM, TK = GM_TK, TN = GM_TN;
-    constexpr int CPT = TN / (256 / TM);      // 8 right-hand sides per thread
-    constexpr int LA = TM * TK / 256, LX = TK * TN / 256;
-    __shared__ C As[TM][TK + 1];
-    __shared__ C Xs[TK][TN];
-    const int tid = threadIdx.x;
-    const int r = tid % TM, g = tid / TM;
-    const int r0 = blockIdx.x * TM, c0 = blockIdx.y * TN;
-    const int nchunks = (n + TK - 1) / TK;
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+template <class R> struct Mfma;
+template <> struct Mfma<float> {
+    typedef mfma_f4 acc;
+    // row of D held by lane group q (= lane / 16) in accumulator r
+    static __device__ __forceinline__ int row(int q, int r) { return 4 * q + r; }
+    static __device__ __forceinline__ acc fma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct Mfma<double> {
+    typedef mfma_d4 acc;
+    static __device__ __forceinline__ int row(int q, int r) { return q + 4 * r; }
+    static __device__ __forceinline__ acc fma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <class R>
+__global__ void __launch_bounds__(256) k_coarsest_mfma(int n, const typename Cx<R>::type* __restrict__ A,
+                                                       const typename Cx<R>::type* __restrict__ X,
+                                                       int nrhs, int64_t bs, int chunks_per_split,
+                                                       typename Cx<R>::type* __restrict__ part) {
+    typedef typename Cx<R>::type C;
+    typedef typename Mfma<R>::acc Acc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, q = lane >> 4;
+    const int row0 = blockIdx.x * MF_TM + wave * 32;
+    const int col0 = blockIdx.y * MF_TN;
+    const int nchunks = (n + MF_KC - 1) / MF_KC;
     const int kc0 = blockIdx.z * chunks_per_split;
     const int kc1 = min(nchunks, kc0 + chunks_per_split);
-    C acc[CPT];
+    // rows and columns past the end read row/column 0; their results are not stored
+    const C* pa[2];
+    const C* px[2];
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) acc[c] = czero<C>();
-    C ra[LA], rx[LX];
-    auto load = [&](int kc) {
-        const int k0 = kc * TK;
+    for (int t = 0; t < 2; ++t) {
+        const int row = row0 + 16 * t + li, col = col0 + 16 * t + li;
+        pa[t] = A + (int64_t)(row < n ? row : 0) * n;
+        px[t] = rhs_nn(X, col < nrhs ? col : 0, bs);
+    }
+    Acc acc[2][2][2];                       // [row tile][column tile][re, im]
 #pragma unroll
-        for (int i = 0; i < LA; ++i) {            // A tile, coalesced along k
-            const int e = tid + 256 * i;
-            const int row = r0 + e / TK, k = k0 + e % TK;
-            ra[i] = (row < n && k < n) ? A[(int64_t)row * n + k] : czero<C>();
-        }
+    for (int t = 0; t < 2; ++t)
 #pragma unroll
-        for (int i = 0; i < LX; ++i) {            // X tile, coalesced along k
-            const int e = tid + 256 * i;
-            const int col = c0 + e / TK, k = k0 + e % TK;
-            rx[i] = (col < nrhs && k < n) ? rhs_nn(X, col, bs)[k] : czero<C>();
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[t][c][p][r] = (R)0;
+    // Steps below n / MF_KC lie inside the matrix and load without a mask; the
+    // one partial step at the end loads entry 0 in place of entries k >= n and
+    // zeroes their A values (A is finite). No load sits under a branch, so the
+    // next step's loads stay in flight during the current products.
+    auto load = [&](int kc, C (&ra)[2][4], C (&rx)[2][4]) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = kc * MF_KC + 4 * u + q;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                ra[t][u] = pa[t][k];
+                rx[t][u] = px[t][k];
+            }
         }
     };
-    if (kc0 < kc1) load(kc0);
-    for (int kc = kc0; kc < kc1; ++kc) {
+    auto step = [&](const C (&ra)[2][4], const C (&rx)[2][4]) {
 #pragma unroll
-        for (int i = 0; i < LA; ++i) {
-            const int e = tid + 256 * i;
-            As[e / TK][e % TK] = ra[i];
-        }
+        for (int u = 0; u < 4; ++u) {
 #pragma unroll
-        for (int i = 0; i < LX; ++i) {
-            const int e = tid + 256 * i;
-            Xs[e % TK][e / TK] = rx[i];
-        }
-        __syncthreads();
-        if (kc + 1 < kc1) load(kc + 1);          // in flight while this chunk is consumed
-#pragma unroll 8
-        for (int kk = 0; kk < TK; ++kk) {
-            const C a = As[r][kk];
+            for (int c = 0; c < 2; ++c) {
+                const R xr = rx[c][u].x, xi = rx[c][u].y;
 #pragma unroll
-            for (int c = 0; c < CPT; ++c) acc[c] = cadd(acc[c], cmul(a, Xs[kk][g * CPT + c]));
+                for (int t = 0; t < 2; ++t) {
+                    acc[t][c][0] = Mfma<R>::fma(ra[t][u].x, xr, acc[t][c][0]);
+                    acc[t][c][1] = Mfma<R>::fma(ra[t][u].x, xi, acc[t][c][1]);
+                    acc[t][c][0] = Mfma<R>::fma(ra[t][u].y, -xi, acc[t][c][0]);
+                    acc[t][c][1] = Mfma<R>::fma(ra[t][u].y, xr, acc[t][c][1]);
+                }
+            }
         }
-        __syncthreads();
+    };
+    // two register buffers in turn: step kc is multiplied while kc + 1 loads
+    const int nfull = n / MF_KC;              // steps that lie inside the matrix
+    const int kf = max(kc0, min(kc1, nfull)); // this range's unmasked steps: [kc0, kf)
+    C a0[2][4], x0[2][4], a1[2][4], x1[2][4];
+    if (kc0 < kf) load(kc0, a0, x0);
+    // (the scheduling barriers keep the compiler from sinking the loads of the
+    // next step down to their uses)
+    for (int kc = kc0; kc < kf; kc += 2) {
+        load(kc + 1 < kf ? kc + 1 : kf - 1, a1, x1);
+        __builtin_amdgcn_sched_barrier(0);
+        step(a0, x0);
+        if (kc + 1 >= kf) break;
+        load(kc + 2 < kf ? kc + 2 : kf - 1, a0, x0);
+        __builtin_amdgcn_sched_barrier(0);
+        step(a1, x1);
     }
-    const int ncol = gridDim.y * TN;
+    if (nfull >= kc0 && nfull < kc1) {        // the partial last step, in this range
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int col = c0 + g * CPT + c;
-        if (r0 + r < n)
-            part[((int64_t)blockIdx.z * ncol + col) * n + r0 + r] = acc[c];
+        for (int u = 0; u < 4; ++u) {
+            const int k = nfull * MF_KC + 4 * u + q;
+            const int kk = k < n ? k : 0;
+            const R m = k < n ? (R)1 : (R)0;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                const C va = pa[t][kk];
+                a0[t][u].x = va.x * m;
+                a0[t][u].y = va.y * m;
+                x0[t][u] = px[t][kk];
+            }
+        }
+        step(a0, x0);
     }
+    const int ncol = gridDim.y * MF_TN;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int col = col0 + 16 * c + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = row0 + 16 * t + Mfma<R>::row(q, r);
+                if (row < n) {
+                    C v;
+                    v.x = acc[t][c][0][r];
+                    v.y = acc[t][c][1][r];
+                    part[((int64_t)blockIdx.z * ncol + col) * n + row] = v;
+                }
+            }
+        }
 }
 
 template <class C>
@@ -172,26 +252,29 @@ __global__ void __launch_bounds__(256) k_coarsest_sum(int n, int nrhs, int64_t b
     rhs_nn(Y, col, bs)[row] = acc;
 }
 
-// split of k: enough blocks to give every CU a few, at least 4 chunks per split
+// split of k: enough blocks to give every CU a few, at least 4 steps per split
 int gemm_splits(int n, int nrhs) {
-    const int nchunks = (n + GM_TK - 1) / GM_TK;
-    const int blocks = ((n + GM_TM - 1) / GM_TM) * ((nrhs + GM_TN - 1) / GM_TN);
+    const int nchunks = (n + MF_KC - 1) / MF_KC;
+    const int blocks = ((n + MF_TM - 1) / MF_TM) * ((nrhs + MF_TN - 1) / MF_TN);
     int ks = (1024 + blocks - 1) / blocks;
     if (ks > nchunks / 4) ks = nchunks / 4;
     return ks < 1 ? 1 : ks;
 }
 
-template <class C>
-hipError_t gemm(int n, const C* A, const C* x, C* y, C* part, hipStream_t s, const Batch& bt) {
+template <class R>
+hipError_t gemm(int n, const typename Cx<R>::type* A, const typename Cx<R>::type* x,
+                typename Cx<R>::type* y, typename Cx<R>::type* part, hipStream_t s,
+                const Batch& bt) {
+    typedef typename Cx<R>::type C;
     if (n > HH_MAX_COARSE_LIMIT) return hipErrorInvalidValue;
-    const int groups = (bt.n + GM_TN - 1) / GM_TN;
+    const int groups = (bt.n + MF_TN - 1) / MF_TN;
     const int ks = gemm_splits(n, bt.n);
-    const int nchunks = (n + GM_TK - 1) / GM_TK;
+    const int nchunks = (n + MF_KC - 1) / MF_KC;
     const int cps = (nchunks + ks - 1) / ks;
-    HH_LAUNCH((k_coarsest_gemm<C>), dim3((n + GM_TM - 1) / GM_TM, groups, ks), dim3(256), 0, s, n,
-              A, x, bt.n, bt.bs, cps, part);
+    HH_LAUNCH((k_coarsest_mfma<R>), dim3((n + MF_TM - 1) / MF_TM, groups, ks), dim3(256), 0, s,
+              n, A, x, bt.n, bt.bs, cps, part);
     HH_LAUNCH((k_coarsest_sum<C>), dim3((n + 255) / 256, bt.n), dim3(256), 0, s, n, bt.n, bt.bs,
-              ks, groups * GM_TN, (const C*)part, y);
+              ks, groups * MF_TN, (const C*)part, y);
     return hipGetLastError();
 }
 
@@ -223,16 +306,16 @@ hipError_t launch_vc_gemv(int n, const cplxf* A, const cplx* x, cplxf* y, const 
     return gemv(n, A, x, y, active, s, bt);
 }
 size_t vc_gemm_scratch_bytes(int n, int nrhs) {
-    const int groups = (nrhs + GM_TN - 1) / GM_TN;
-    return (size_t)gemm_splits(n, nrhs) * groups * GM_TN * n * sizeof(cplx);
+    const int groups = (nrhs + MF_TN - 1) / MF_TN;
+    return (size_t)gemm_splits(n, nrhs) * groups * MF_TN * n * sizeof(cplx);
 }
 hipError_t launch_vc_gemm(int n, const cplx* A, const cplx* x, cplx* y, void* scratch,
                           hipStream_t s, const Batch& bt) {
-    return gemm(n, A, x, y, static_cast<cplx*>(scratch), s, bt);
+    return gemm<double>(n, A, x, y, static_cast<cplx*>(scratch), s, bt);
 }
 hipError_t launch_vc_gemm(int n, const cplxf* A, const cplxf* x, cplxf* y, void* scratch,
                           hipStream_t s, const Batch& bt) {
-    return gemm(n, A, x, y, static_cast<cplxf*>(scratch), s, bt);
+    return gemm<float>(n, A, x, y, static_cast<cplxf*>(scratch), s, bt);
 }
 
 }  // namespace hh

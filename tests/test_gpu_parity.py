@@ -571,6 +571,25 @@ def test_batch_equals_single_small_grid(hh, kw):
             assert r <= kw["tol"] * (1 + 1e-6)
 
 
+@pytest.mark.parametrize("kw", [dict(restart=10, tol=1e-8),
+                                dict(restart=10, tol=1e-7, precond_f32=True)],
+                         ids=["f64", "f32"])
+def test_batch_two_source_groups_ragged_coarsest(hh, kw):
+    """37 sources: the batched coarsest product runs a full group of 32 and a
+    partial one of 5; the grid makes every level (and the coarsest size) ragged
+    against the product's 16-entry steps and 128-row blocks."""
+    shape, h, freq = (45, 97), 10.0, 5.0
+    m = _model(shape, h, seed=8)
+    P = _problem(hh, m, 2 * np.pi * freq, 0.01, h)
+    nc = int(np.prod(P.level_info(P.num_levels - 1)[0]))
+    assert P.num_levels >= 3 and nc % 16 != 0
+    rng = np.random.default_rng(37)
+    pos = [(int(rng.integers(0, shape[0])), int(rng.integers(0, shape[1]))) for _ in range(37)]
+    F = _batch_sources(shape, pos)
+    res = _assert_batch_equals_single(P, F, **kw)
+    assert np.all(res.status == 0)
+
+
 @pytest.mark.parametrize("shape", [(1001,), (3, 3)], ids=str)
 def test_batch_1d_and_single_level(hh, shape):
     if len(shape) == 1:
