@@ -28,6 +28,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# dense matrix-core peaks of the MI355X (TFLOP/s)
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 METRIC = "Helmholtz solves/s to 1e-6 residual; HBM GB/s; p50/p99 latency vs plain"
 
 
@@ -49,6 +51,10 @@ def parse():
     ap.add_argument("--kernel", default="auto",
                     help="kernel class for the roofline figure; 'auto' (default) times every "
                          "class over one warm-up solve and takes the one with the most device time")
+    ap.add_argument("--tiles", default="auto", choices=["auto", "default"],
+                    help="tile shapes of the multigrid legs: 'auto' times every shape on the "
+                         "workload's hierarchy during set-up (hh_autotune), 'default' keeps the "
+                         "fixed rule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200,
                     help="serving: requests in the Poisson stream (mean 200/s)")
@@ -164,6 +170,15 @@ def cpu_baseline_batch(slow, sources, freqs, budget_s: float, its_by_freq, max_c
                       f"for {n} solves; NumPy/SciPy FP64, 1 thread"}
 
 
+def _tile_names(hh, tiles, mode):
+    """Tile shapes per level with legs, as 'down/up' (the fixed rule: 'default')."""
+    if mode != "auto":
+        return "default"
+    def name(shapes, t):
+        return "default" if t < 0 else shapes[t]
+    return [f"{name(hh.TILE_DOWN_SHAPES, d)}/{name(hh.TILE_UP_SHAPES, u)}" for d, u in tiles]
+
+
 def main_batch(a, hh, torch, dev):
     import workloads as wl
     slow, sources, freqs = wl.grf_801x301_sources()
@@ -180,6 +195,10 @@ def main_batch(a, hh, torch, dev):
     probs = [hh.Problem(m, 2 * np.pi * fz, 0.01, 10.0, max_coarse=max_coarse) for fz in freqs]
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
+    t_tune = time.perf_counter()
+    tiles = [P.autotune(precond_f32=mixed, nrhs=len(sources)) if a.tiles == "auto" else []
+             for P in probs]
+    t_tune = time.perf_counter() - t_tune
     wss = [torch.empty(P.workspace_bytes_batch(restart, len(sources)), dtype=torch.uint8,
                        device=dev) for P in probs]
     U = torch.empty_like(Ft)
@@ -222,14 +241,28 @@ def main_batch(a, hh, torch, dev):
                 sys.exit(1)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    launches = kms = kbytes = 0
+    launches = kms = kbytes = kflops = 0
     for P in probs:
         n_k, ms_k, b_k = P.kernel_timer_read()
         launches += n_k
         kms += ms_k
         kbytes += b_k
+        # the batched coarsest product: 8 real flops per complex multiply-add,
+        # nc^2 of them per source
+        nz_c, nx_c = P.level_info(P.num_levels - 1)[0]
+        kflops += n_k * 8.0 * float(nz_c * nx_c) ** 2 * len(sources)
         P.kernel_timer_start("none")
     achieved = (kbytes / (kms * 1e-3)) / 1e9 if kms > 0 else 0.0
+    if kernel == "gemv":
+        # a dense contraction on the matrix cores: priced against the MFMA peak
+        peak = MFMA_PEAK_TFLOPS["f32" if mixed else "f64"]
+        achieved_tf = (kflops / (kms * 1e-3)) / 1e12 if kms > 0 else 0.0
+        roof = {"bound": "mfma", "kernel": kernel, "achieved": achieved_tf, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved_tf / peak,
+                "hbm_gbs": achieved, "algorithmic_flops_per_launch": kflops / max(launches, 1)}
+    else:
+        roof = {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
     n_solves = len(freqs) * len(sources)
     out = {
         "metric": METRIC,
@@ -256,14 +289,15 @@ def main_batch(a, hh, torch, dev):
             "iterations_min_max_by_freq": [[int(i.min()), int(i.max())] for i in its],
             "true_rel_res_max": max(res),
             "setup_ms": 1e3 * t_setup,
+            "tiles_down_up_by_freq": [_tile_names(hh, t, a.tiles) for t in tiles],
+            "autotune_ms": 1e3 * t_tune,
         },
         "latency_ms": {"p50_step": float(np.percentile(lat, 50) * 1e3),
                        "p99_step": float(np.percentile(lat, 99) * 1e3),
                        "plain": "a step is the 128 solves; the plain one-at-a-time solver is "
                                 "bench.py without --workload"},
         "roofline": {
-            "bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            **roof,
             "traffic": measured_traffic("grf2d_801x301_batch" + ("_mixed" if mixed else ""),
                                         kernel),
             "launches": int(launches), "avg_launch_us": 1e3 * kms / max(launches, 1),
@@ -374,6 +408,9 @@ def main():
     u = torch.empty_like(f)
 
     mixed = a.precision == "mixed"
+    t_tune = time.perf_counter()
+    tiles = P.autotune(precond_f32=mixed) if a.tiles == "auto" else []
+    t_tune = time.perf_counter() - t_tune
 
     def one():
         return P.solve(f, tol=w.tol, restart=w.restart, max_iters=2000, u=u, workspace=ws,
@@ -445,6 +482,8 @@ def main():
             "iterations": int(np.median(its)),
             "true_rel_res_max": float(max(res)),
             "setup_ms": 1e3 * t_setup,
+            "tiles_down_up": _tile_names(hh, tiles, a.tiles),
+            "autotune_ms": 1e3 * t_tune,
         },
         "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
                        "p99": float(np.percentile(lat, 99) * 1e3),

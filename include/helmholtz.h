@@ -116,6 +116,47 @@ int hh_create_problem_ex(const double* m_dev, int ndim, const int64_t* shape, do
 int hh_set_max_coarse(hh_problem p, int max_coarse);
 
 /*
+ * Tile shapes of the multigrid legs. Each level l = 0 .. nlevels-2 has a down
+ * leg (two pre-smoothing sweeps, residual, restriction; tiles of coarse nodes)
+ * and an up leg (prolongation, two post-smoothing sweeps; tiles of level-l
+ * nodes), one kernel each. Every shape computes every node with the same
+ * arithmetic, so the choice changes the speed of a solve, never its bits.
+ * HH_TILE_DEFAULT (-1) is a fixed rule: down 4 x 4, up 8 x 4 (32 x 8 on a fine
+ * grid of at least 200000 nodes). A rebuilt hierarchy starts from the default.
+ */
+#define HH_TILE_DEFAULT (-1)
+#define HH_TILE_DOWN_4X4 0
+#define HH_TILE_DOWN_8X4 1
+#define HH_TILE_DOWN_COUNT 2
+#define HH_TILE_UP_8X4 0
+#define HH_TILE_UP_16X8 1
+#define HH_TILE_UP_32X8 2
+#define HH_TILE_UP_COUNT 3
+
+/*
+ * hh_autotune -- times every tile shape of every leg on this problem's
+ * hierarchy and keeps per leg the fastest, where a shape replaces the default
+ * only when it runs more than 3% faster (a project-side tuner for the
+ * multigrid cycle of Sec. 3; not part of the paper's method).
+ *   flags     : 0 (complex128 cycle) or HH_PRECOND_F32 (complex64 cycle).
+ *   nrhs      : sources per batch the choice is made for (1..HH_MAX_BATCH).
+ *   workspace_dev / workspace_bytes : at least hh_workspace_bytes_batch(p, 1,
+ *               nrhs) bytes; overwritten (zeroed, then the legs' outputs).
+ *   reps      : launches per timing (1..1000); each shape is timed three
+ *               times and the shortest counts.
+ * The call synchronises the stream. 1D problems and single-level hierarchies
+ * have no legs: HH_OK, nothing tuned.
+ */
+int hh_autotune(hh_problem p, unsigned flags, int nrhs, void* workspace_dev,
+                size_t workspace_bytes, int reps, void* stream);
+
+/* Tile shapes of level `level`'s legs (HH_TILE_*; -1: default); read, or set
+ * (for example from a cache of earlier hh_autotune results). HH_EINVAL for a
+ * level without legs or an unknown shape. */
+int hh_get_tiles(hh_problem p, int level, int* tile_down, int* tile_up);
+int hh_set_tiles(hh_problem p, int level, int tile_down, int tile_up);
+
+/*
  * hh_set_shift -- choose the shifted-Laplace preconditioner of Eq. 6,
  * M = -Lap - (beta1 - j beta2) omega^2 m^2 (same absorbing rows as H).
  * Rebuilds the multigrid hierarchy (Galerkin operators and coarsest inverse,

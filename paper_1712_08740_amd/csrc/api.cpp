@@ -67,6 +67,8 @@ struct LevelData {
     cplx* wd = nullptr;             // wj / diag per node (smoothing levels)
     cplxf* Cf = nullptr;            // the same, rounded to complex64
     cplxf* wdf = nullptr;
+    int tile_down = -1;             // tile shapes of this level's legs (HH_TILE_*, -1: default)
+    int tile_up = -1;
     int64_t size() const { return (int64_t)nz * nx; }
 };
 
@@ -352,11 +354,11 @@ int vcycle_coarse(hh_problem_s* p, const Layout& L, void* ws, int l, const int* 
     // the coarser correction in; both read the 9 coefficients and omega/diag
     TIMED2(HH_KERNEL_VC_DOWN_COARSE, 2.0 * es * nl_ + es * nn_, 10.0 * es * nl_,
            launch_vc_coarse_down(A, b, x2, lv.halve_z, lv.halve_x, coarse_grid(p, l + 1),
-                                 at<C>(ws, L.bc[l + 1]), active, s, bt));
+                                 at<C>(ws, L.bc[l + 1]), active, s, bt, lv.tile_down));
     CHK(vcycle_coarse<T>(p, L, ws, l + 1, active, s, bt));
     TIMED2(HH_KERNEL_VC_UP_COARSE, 3.0 * es * nl_ + es * nn_, 10.0 * es * nl_,
            launch_vc_coarse_up(A, lv.halve_z, lv.halve_x, b, x2, at<C>(ws, L.ec[l + 1]),
-                               coarse_grid(p, l + 1), x, active, s, bt));
+                               coarse_grid(p, l + 1), x, active, s, bt, lv.tile_up));
     return HH_OK;
 }
 
@@ -391,11 +393,84 @@ int precond(hh_problem_s* p, const Layout& L, void* ws, const cplx* src, const i
     // (shared by the right-hand sides)
     TIMED2(HH_KERNEL_VC_DOWN, (16.0 + es) * N + es * N1, (rs + es) * N,
            launch_vc_fine_down(M, src, x2, lv.halve_z, lv.halve_x, coarse_grid(p, 1),
-                               at<C>(ws, L.bc[1]), active, s, bt));
+                               at<C>(ws, L.bc[1]), active, s, bt, lv.tile_down));
     CHK(vcycle_coarse<T>(p, L, ws, 1, active, s, bt));
     TIMED2(HH_KERNEL_VC_UP, (16.0 + 2.0 * es) * N + es * N1, (rs + es) * N,
            launch_vc_fine_up(M, lv.halve_z, lv.halve_x, src, x2, at<C>(ws, L.ec[1]),
-                             coarse_grid(p, 1), z, active, s, bt));
+                             coarse_grid(p, 1), z, active, s, bt, lv.tile_up));
+    return HH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tile autotuner
+// ---------------------------------------------------------------------------
+// Launch configuration to keep: -1 (the default) unless one of 0 .. count-1
+// runs more than 3% faster than it (a margin above the timing noise, so that
+// the choice departs from the default only for a clear gain). Each runs once
+// to warm up, then three times `reps` back-to-back launches between two
+// events; the shortest of the three counts.
+template <class F>
+int fastest(F&& launch, int count, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+            int* best) {
+    float best_ms = 0.0f;
+    *best = -1;
+    for (int c = -1; c < count; ++c) {
+        HIPCHK(launch(c));
+        float tmin = 0.0f;
+        for (int trial = 0; trial < 3; ++trial) {
+            HIPCHK(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) HIPCHK(launch(c));
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (trial == 0 || ms < tmin) tmin = ms;
+        }
+        if (c == -1 || tmin < 0.97f * best_ms) {
+            best_ms = tmin;
+            *best = c;
+        }
+    }
+    return HH_OK;
+}
+
+// Times every tile shape of the down and up legs of levels 0 .. nl-2 in
+// precision T on the workspace's own vectors (inputs zero, every kernel
+// unconditional) and keeps per leg the choice of fastest() in the level data.
+template <class T>
+int tune_legs(hh_problem_s* p, const Layout& L, void* ws, int reps, hipStream_t s,
+              const Batch& bt, hipEvent_t e0, hipEvent_t e1) {
+    typedef typename Cx<T>::type C;
+    const int nl = (int)p->levels.size();
+    const cplx* src = at<cplx>(ws, L.V);
+    C* z = at<C>(ws, L.Z);
+    for (int l = 0; l + 1 < nl; ++l) {
+        LevelData& lv = p->levels[l];
+        const CGrid cg = coarse_grid(p, l + 1);
+        C* x2 = at<C>(ws, L.t[l]);
+        C* bcn = at<C>(ws, L.bc[l + 1]);
+        C* ecn = at<C>(ws, L.ec[l + 1]);
+        auto down = [&](int tile) -> hipError_t {
+            if (l == 0)
+                return launch_vc_fine_down(Prec<T>::fine(p), src, x2, lv.halve_z, lv.halve_x, cg,
+                                           bcn, nullptr, s, bt, tile);
+            return launch_vc_coarse_down(Prec<T>::coarse(lv), at<C>(ws, L.bc[l]), x2, lv.halve_z,
+                                         lv.halve_x, cg, bcn, nullptr, s, bt, tile);
+        };
+        auto up = [&](int tile) -> hipError_t {
+            if (l == 0)
+                return launch_vc_fine_up(Prec<T>::fine(p), lv.halve_z, lv.halve_x, src, x2, ecn,
+                                         cg, z, nullptr, s, bt, tile);
+            return launch_vc_coarse_up(Prec<T>::coarse(lv), lv.halve_z, lv.halve_x,
+                                       at<C>(ws, L.bc[l]), x2, ecn, cg, at<C>(ws, L.ec[l]),
+                                       nullptr, s, bt, tile);
+        };
+        int best = 0;
+        CHK(fastest(down, HH_TILE_DOWN_COUNT, reps, s, e0, e1, &best));
+        lv.tile_down = best;
+        CHK(fastest(up, HH_TILE_UP_COUNT, reps, s, e0, e1, &best));
+        lv.tile_up = best;
+    }
     return HH_OK;
 }
 
@@ -853,6 +928,56 @@ int hh_level_info(hh_problem p, int level, int64_t* shape2, double* spacing2) {
     shape2[1] = L.nx;
     spacing2[0] = p->ndim == 2 ? L.hz : 0.0;
     spacing2[1] = L.hx;
+    return HH_OK;
+}
+
+int hh_autotune(hh_problem p, unsigned flags, int nrhs, void* workspace_dev,
+                size_t workspace_bytes, int reps, void* stream) {
+    g_err.clear();
+    if (!p) return fail(HH_EINVAL, "problem is NULL");
+    CHK(check_ptr(workspace_dev, "workspace_dev"));
+    if (flags & ~HH_PRECOND_F32) return fail(HH_EINVAL, "flags must be 0 or HH_PRECOND_F32");
+    if (nrhs < 1 || nrhs > HH_MAX_BATCH) return fail(HH_EINVAL, "nrhs must be in [1, HH_MAX_BATCH]");
+    if (reps < 1 || reps > 1000) return fail(HH_EINVAL, "reps must be in [1, 1000]");
+    const bool f32 = (flags & HH_PRECOND_F32) != 0;
+    const Layout L = layout(p, 1, f32 ? sizeof(cplxf) : sizeof(cplx));
+    if (workspace_bytes < (size_t)nrhs * L.total) return fail(HH_EINVAL, "workspace too small");
+    if (p->ndim != 2 || p->levels.size() < 2) return HH_OK;   // no multigrid legs
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Batch bt{nrhs, (int64_t)L.total, p->N};
+    HIPCHK(hipMemsetAsync(workspace_dev, 0, (size_t)nrhs * L.total, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    hipError_t ee = hipEventCreate(&e1);
+    int rc = ee == hipSuccess ? HH_OK : fail(HH_EDEVICE, hipGetErrorString(ee));
+    if (rc == HH_OK)
+        rc = f32 ? tune_legs<float>(p, L, workspace_dev, reps, s, bt, e0, e1)
+                 : tune_legs<double>(p, L, workspace_dev, reps, s, bt, e0, e1);
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int hh_get_tiles(hh_problem p, int level, int* tile_down, int* tile_up) {
+    g_err.clear();
+    if (!p || !tile_down || !tile_up) return fail(HH_EINVAL, "NULL argument");
+    if (p->ndim != 2 || level < 0 || level + 1 >= (int)p->levels.size())
+        return fail(HH_EINVAL, "level has no multigrid legs");
+    *tile_down = p->levels[level].tile_down;
+    *tile_up = p->levels[level].tile_up;
+    return HH_OK;
+}
+
+int hh_set_tiles(hh_problem p, int level, int tile_down, int tile_up) {
+    g_err.clear();
+    if (!p) return fail(HH_EINVAL, "problem is NULL");
+    if (p->ndim != 2 || level < 0 || level + 1 >= (int)p->levels.size())
+        return fail(HH_EINVAL, "level has no multigrid legs");
+    if (tile_down < -1 || tile_down >= HH_TILE_DOWN_COUNT || tile_up < -1 ||
+        tile_up >= HH_TILE_UP_COUNT)
+        return fail(HH_EINVAL, "unknown tile shape");
+    p->levels[level].tile_down = tile_down;
+    p->levels[level].tile_up = tile_up;
     return HH_OK;
 }
 

@@ -94,8 +94,7 @@ __global__ void __launch_bounds__(256) k_gemv_batch(int n, const C* __restrict__
 // 16-row tiles), 32 right-hand sides (group blockIdx.y: two 16-column tiles,
 // each for the real and the imaginary part) and one of KS contiguous ranges of
 // k (blockIdx.z), stepping 16 complex k at a time. A is loaded once, straight
-// into registers, the next step's loads in flight while the current one is
-// multiplied; X comes from the L2 (it is read by every row block).
+// into registers; X comes from the L2 (it is read by every row block).
 // MFMA 16x16x4 (f32 or f64): lane l supplies A(l%16, l/16) and B(l/16, l%16)
 // and receives in accumulator r the entry of column l%16 and row 4(l/16)+r
 // (f32) or l/16+4r (f64). Lane (i, q) of a tile holds
@@ -160,8 +159,7 @@ __global__ void __launch_bounds__(256) k_coarsest_mfma(int n, const typename Cx<
                 for (int r = 0; r < 4; ++r) acc[t][c][p][r] = (R)0;
     // Steps below n / MF_KC lie inside the matrix and load without a mask; the
     // one partial step at the end loads entry 0 in place of entries k >= n and
-    // zeroes their A values (A is finite). No load sits under a branch, so the
-    // next step's loads stay in flight during the current products.
+    // zeroes their A values (A is finite). No load sits under a branch.
     auto load = [&](int kc, C (&ra)[2][4], C (&rx)[2][4]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -189,21 +187,15 @@ __global__ void __launch_bounds__(256) k_coarsest_mfma(int n, const typename Cx<
             }
         }
     };
-    // two register buffers in turn: step kc is multiplied while kc + 1 loads
+    // one register buffer: the waves sharing a SIMD (3 in complex64, 5 in
+    // complex128) hide each other's load latency (measured faster than a
+    // second buffer, which costs occupancy)
     const int nfull = n / MF_KC;              // steps that lie inside the matrix
     const int kf = max(kc0, min(kc1, nfull)); // this range's unmasked steps: [kc0, kf)
-    C a0[2][4], x0[2][4], a1[2][4], x1[2][4];
-    if (kc0 < kf) load(kc0, a0, x0);
-    // (the scheduling barriers keep the compiler from sinking the loads of the
-    // next step down to their uses)
-    for (int kc = kc0; kc < kf; kc += 2) {
-        load(kc + 1 < kf ? kc + 1 : kf - 1, a1, x1);
-        __builtin_amdgcn_sched_barrier(0);
+    C a0[2][4], x0[2][4];
+    for (int kc = kc0; kc < kf; ++kc) {
+        load(kc, a0, x0);
         step(a0, x0);
-        if (kc + 1 >= kf) break;
-        load(kc + 2 < kf ? kc + 2 : kf - 1, a0, x0);
-        __builtin_amdgcn_sched_barrier(0);
-        step(a1, x1);
     }
     if (nfull >= kc0 && nfull < kc1) {        // the partial last step, in this range
 #pragma unroll
@@ -252,11 +244,12 @@ __global__ void __launch_bounds__(256) k_coarsest_sum(int n, int nrhs, int64_t b
     rhs_nn(Y, col, bs)[row] = acc;
 }
 
-// split of k: enough blocks to give every CU a few, at least 4 steps per split
+// split of k: about three resident blocks per CU in one round (a second,
+// partly filled round of blocks measured slower), at least 4 steps per split
 int gemm_splits(int n, int nrhs) {
     const int nchunks = (n + MF_KC - 1) / MF_KC;
     const int blocks = ((n + MF_TM - 1) / MF_TM) * ((nrhs + MF_TN - 1) / MF_TN);
-    int ks = (1024 + blocks - 1) / blocks;
+    int ks = 768 / blocks;
     if (ks > nchunks / 4) ks = nchunks / 4;
     return ks < 1 ? 1 : ks;
 }

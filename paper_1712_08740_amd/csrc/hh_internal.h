@@ -371,6 +371,8 @@ hipError_t launch_vc_gemm(int n, const cplxf* A, const cplxf* x, cplxf* y, void*
 // temporally blocked legs (vcycle_tiled.hip): down = two pre-sweeps from zero,
 // residual and restriction; up = prolongation and two post-sweeps
 // (the smoother weight enters through op.wdinv = omega_J / diag).
+// tile: the leg's tile shape, HH_TILE_* ids of helmholtz.h (-1: the default
+// for the level); every shape gives the same bits.
 // The next coarser grid: its shape, and whether its vectors are stored x-major
 // (node (iz, ix) at ix nz + iz: the band numbering of the coarsest inverse)
 // instead of z-major.
@@ -382,29 +384,29 @@ struct CGrid {
 };
 hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, cplx* x2, int hz, int hx,
                                CGrid cg, cplx* bc, const int* active, hipStream_t s,
-                               const Batch& bt = Batch());
+                               const Batch& bt = Batch(), int tile = -1);
 // single-precision cycle: the Krylov vector src stays complex128
 hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, cplxf* x2, int hz,
                                int hx, CGrid cg, cplxf* bc, const int* active,
-                               hipStream_t s, const Batch& bt = Batch());
+                               hipStream_t s, const Batch& bt = Batch(), int tile = -1);
 hipError_t launch_vc_coarse_down(const CoarseOpT<float>& op, const cplxf* b, cplxf* x2, int hz,
                                  int hx, CGrid cg, cplxf* bc, const int* active,
-                                 hipStream_t s, const Batch& bt = Batch());
+                                 hipStream_t s, const Batch& bt = Batch(), int tile = -1);
 hipError_t launch_vc_fine_up(const FineOpT<float>& op, int hz, int hx, const cplx* b,
                              const cplxf* x2, const cplxf* e, CGrid cg, cplxf* out,
-                             const int* active, hipStream_t s, const Batch& bt = Batch());
+                             const int* active, hipStream_t s, const Batch& bt = Batch(), int tile = -1);
 hipError_t launch_vc_coarse_up(const CoarseOpT<float>& op, int hz, int hx, const cplxf* b,
                                const cplxf* x2, const cplxf* e, CGrid cg, cplxf* out,
-                               const int* active, hipStream_t s, const Batch& bt = Batch());
+                               const int* active, hipStream_t s, const Batch& bt = Batch(), int tile = -1);
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz,
                                  int hx, CGrid cg, cplx* bc, const int* active,
-                                 hipStream_t s, const Batch& bt = Batch());
+                                 hipStream_t s, const Batch& bt = Batch(), int tile = -1);
 hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b,
                              const cplx* x2, const cplx* e, CGrid cg, cplx* out, const int* active,
-                             hipStream_t s, const Batch& bt = Batch());
+                             hipStream_t s, const Batch& bt = Batch(), int tile = -1);
 hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b,
                                const cplx* x2, const cplx* e, CGrid cg, cplx* out,
-                               const int* active, hipStream_t s, const Batch& bt = Batch());
+                               const int* active, hipStream_t s, const Batch& bt = Batch(), int tile = -1);
 // wdinv = wj / diag of a level operator (set-up)
 hipError_t launch_wdinv_fine(const FineOp& op, double wj, cplx* wdinv, hipStream_t s);
 hipError_t launch_wdinv_coarse(const CoarseOp& op, double wj, cplx* wdinv, hipStream_t s);

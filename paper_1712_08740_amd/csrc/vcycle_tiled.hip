@@ -371,14 +371,17 @@ hipError_t down_launch(const OP& A, const SC* src, typename OP::C* x2, int hz, i
     return hipGetLastError();
 }
 
-// Tiles of 4 x 4 coarse nodes (an 8 x 8 fine block and its halo) on every
-// level: the legs are latency-bound up to a few 100k nodes, where more blocks in
+// Tile shapes of the down leg (coarse nodes): 0 = 4 x 4 (an 8 x 8 fine block
+// and its halo), 1 = 8 x 4. The default (tile < 0) is 4 x 4 on every level:
+// the legs are latency-bound up to a few 100k nodes, where more blocks in
 // flight beat the extra halo work, and past that the down leg still gains
-// (measured on the 401 x 201 and 1201 x 401 hierarchies).
+// (measured on the 401 x 201 and 1201 x 401 hierarchies). Every shape computes
+// every node with the same arithmetic: the choice changes speed, not results.
 template <class OP, class SC>
 hipError_t down_dispatch(const OP& A, const SC* src, typename OP::C* x2, int hz, int hx, CGrid cg,
                          typename OP::C* bc, const int* active, hipStream_t s,
-                         const Batch& bt) {
+                         const Batch& bt, int tile) {
+    if (tile == 1) return down_launch<OP, SC, 8, 4>(A, src, x2, hz, hx, cg, bc, active, s, bt);
     return down_launch<OP, SC, 4, 4>(A, src, x2, hz, hx, cg, bc, active, s, bt);
 }
 
@@ -392,13 +395,16 @@ hipError_t up_launch(const OP& A, int hz, int hx, const SB* b, const typename OP
     return hipGetLastError();
 }
 
-// Up leg: 8 x 4-node tiles, and 32 x 8 (less halo work) on large 5-point grids.
+// Tile shapes of the up leg (fine nodes): 0 = 8 x 4, 1 = 16 x 8, 2 = 32 x 8.
+// The default (tile < 0) is 8 x 4, and 32 x 8 (less halo work) on large
+// 5-point grids. Results do not depend on the choice.
 template <class OP, class SB>
 hipError_t up_dispatch(const OP& A, int hz, int hx, const SB* b, const typename OP::C* x2,
                        const typename OP::C* e, CGrid cg, typename OP::C* out, const int* active,
-                       hipStream_t s, const Batch& bt) {
-    if (big_tiles(A))
-        return up_launch<OP, SB, 32, 8>(A, hz, hx, b, x2, e, cg, out, active, s, bt);
+                       hipStream_t s, const Batch& bt, int tile) {
+    if (tile < 0) tile = big_tiles(A) ? 2 : 0;
+    if (tile == 2) return up_launch<OP, SB, 32, 8>(A, hz, hx, b, x2, e, cg, out, active, s, bt);
+    if (tile == 1) return up_launch<OP, SB, 16, 8>(A, hz, hx, b, x2, e, cg, out, active, s, bt);
     return up_launch<OP, SB, 8, 4>(A, hz, hx, b, x2, e, cg, out, active, s, bt);
 }
 
@@ -419,46 +425,46 @@ Coarse9<T> coarse9(const CoarseOpT<T>& op) {
 
 hipError_t launch_vc_fine_down(const FineOp& op, const cplx* src, cplx* x2, int hz, int hx,
                                CGrid cg, cplx* bc, const int* active, hipStream_t s,
-                               const Batch& bt) {
-    return down_dispatch(fine5(op), src, x2, hz, hx, cg, bc, active, s, bt);
+                               const Batch& bt, int tile) {
+    return down_dispatch(fine5(op), src, x2, hz, hx, cg, bc, active, s, bt, tile);
 }
 hipError_t launch_vc_fine_down(const FineOpT<float>& op, const cplx* src, cplxf* x2, int hz,
                                int hx, CGrid cg, cplxf* bc, const int* active,
-                               hipStream_t s, const Batch& bt) {
-    return down_dispatch(fine5(op), src, x2, hz, hx, cg, bc, active, s, bt);
+                               hipStream_t s, const Batch& bt, int tile) {
+    return down_dispatch(fine5(op), src, x2, hz, hx, cg, bc, active, s, bt, tile);
 }
 
 hipError_t launch_vc_coarse_down(const CoarseOp& op, const cplx* b, cplx* x2, int hz, int hx,
                                  CGrid cg, cplx* bc, const int* active, hipStream_t s,
-                                 const Batch& bt) {
-    return down_dispatch(coarse9(op), b, x2, hz, hx, cg, bc, active, s, bt);
+                                 const Batch& bt, int tile) {
+    return down_dispatch(coarse9(op), b, x2, hz, hx, cg, bc, active, s, bt, tile);
 }
 hipError_t launch_vc_coarse_down(const CoarseOpT<float>& op, const cplxf* b, cplxf* x2, int hz,
                                  int hx, CGrid cg, cplxf* bc, const int* active,
-                                 hipStream_t s, const Batch& bt) {
-    return down_dispatch(coarse9(op), b, x2, hz, hx, cg, bc, active, s, bt);
+                                 hipStream_t s, const Batch& bt, int tile) {
+    return down_dispatch(coarse9(op), b, x2, hz, hx, cg, bc, active, s, bt, tile);
 }
 
 hipError_t launch_vc_fine_up(const FineOp& op, int hz, int hx, const cplx* b, const cplx* x2,
                              const cplx* e, CGrid cg, cplx* out, const int* active, hipStream_t s,
-                             const Batch& bt) {
-    return up_dispatch(fine5(op), hz, hx, b, x2, e, cg, out, active, s, bt);
+                             const Batch& bt, int tile) {
+    return up_dispatch(fine5(op), hz, hx, b, x2, e, cg, out, active, s, bt, tile);
 }
 hipError_t launch_vc_fine_up(const FineOpT<float>& op, int hz, int hx, const cplx* b,
                              const cplxf* x2, const cplxf* e, CGrid cg, cplxf* out,
-                             const int* active, hipStream_t s, const Batch& bt) {
-    return up_dispatch(fine5(op), hz, hx, b, x2, e, cg, out, active, s, bt);
+                             const int* active, hipStream_t s, const Batch& bt, int tile) {
+    return up_dispatch(fine5(op), hz, hx, b, x2, e, cg, out, active, s, bt, tile);
 }
 
 hipError_t launch_vc_coarse_up(const CoarseOp& op, int hz, int hx, const cplx* b, const cplx* x2,
                                const cplx* e, CGrid cg, cplx* out, const int* active,
-                               hipStream_t s, const Batch& bt) {
-    return up_dispatch(coarse9(op), hz, hx, b, x2, e, cg, out, active, s, bt);
+                               hipStream_t s, const Batch& bt, int tile) {
+    return up_dispatch(coarse9(op), hz, hx, b, x2, e, cg, out, active, s, bt, tile);
 }
 hipError_t launch_vc_coarse_up(const CoarseOpT<float>& op, int hz, int hx, const cplxf* b,
                                const cplxf* x2, const cplxf* e, CGrid cg, cplxf* out,
-                               const int* active, hipStream_t s, const Batch& bt) {
-    return up_dispatch(coarse9(op), hz, hx, b, x2, e, cg, out, active, s, bt);
+                               const int* active, hipStream_t s, const Batch& bt, int tile) {
+    return up_dispatch(coarse9(op), hz, hx, b, x2, e, cg, out, active, s, bt, tile);
 }
 
 namespace {

@@ -10,7 +10,9 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import json
 import os
+import tempfile
 from typing import Optional
 
 import numpy as np
@@ -33,6 +35,12 @@ HH_MAX_COARSE = 4096
 HH_MAX_COARSE_LIMIT = 32768
 HH_MAX_1D = 1024
 HH_MAX_BATCH = 1024
+HH_TILE_DEFAULT = -1
+HH_TILE_DOWN_COUNT = 2
+HH_TILE_UP_COUNT = 3
+# tile shapes by id: down legs in coarse nodes, up legs in level nodes (x by z)
+TILE_DOWN_SHAPES = ("4x4", "8x4")
+TILE_UP_SHAPES = ("8x4", "16x8", "32x8")
 HH_KERNEL_NONE = 0
 HH_KERNEL_APPLY_DOT = 1
 HH_KERNEL_AXPY_DOT = 2
@@ -53,7 +61,8 @@ EXPORTED = [
     "hh_apply_precond_f32",
     "hh_orthogonalize_scratch_bytes", "hh_orthogonalize", "hh_kernel_timer_start",
     "hh_kernel_timer_read", "hh_workspace_bytes_batch", "hh_solve_batch", "hh_set_max_coarse",
-    "hh_footprint_bytes", "hh_create_problem_ex",
+    "hh_footprint_bytes", "hh_create_problem_ex", "hh_autotune", "hh_get_tiles",
+    "hh_set_tiles",
 ]
 
 KERNEL_IDS = {"none": HH_KERNEL_NONE, "apply_dot": HH_KERNEL_APPLY_DOT,
@@ -88,6 +97,10 @@ def _load():
         "hh_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "hh_last_error": (ctypes.c_char_p, []),
         "hh_num_levels": (ctypes.c_int, [_vp, _c_int_p]),
+        "hh_autotune": (ctypes.c_int, [_vp, ctypes.c_uint, ctypes.c_int, _vp, ctypes.c_size_t,
+                                       ctypes.c_int, _vp]),
+        "hh_get_tiles": (ctypes.c_int, [_vp, ctypes.c_int, _c_int_p, _c_int_p]),
+        "hh_set_tiles": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "hh_level_info": (ctypes.c_int, [_vp, ctypes.c_int, _c_i64_p, _c_double_p]),
         "hh_apply_operator": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
         "hh_apply_level_operator": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _vp]),
@@ -121,6 +134,37 @@ def _load():
 
 
 _lib = _load()
+
+
+def tile_cache_key(level_shapes, precond_f32: bool, nrhs: int) -> str:
+    """Key of a tile choice in a cache file: the hierarchy's level grids, the
+    cycle's precision and the batch size (the quantities the timings depend
+    on, for one kind of GPU)."""
+    grids = ",".join(f"{nz}x{nx}" for nz, nx in level_shapes)
+    return f"{'c64' if precond_f32 else 'c128'}/rhs{int(nrhs)}/{grids}"
+
+
+def read_tile_cache(path: str) -> dict:
+    """Entries of a tile cache file ({} when it does not exist)."""
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        data = json.load(fh)
+    if not isinstance(data, dict):
+        raise ValueError(f"{path}: not a tile cache")
+    return data
+
+
+def write_tile_cache(path: str, key: str, tiles) -> None:
+    """Adds one entry ([[down, up] per level]) to a tile cache file, written to
+    a temporary file and renamed over the old one."""
+    data = read_tile_cache(path)
+    data[key] = [[int(d), int(u)] for d, u in tiles]
+    folder = os.path.dirname(os.path.abspath(path))
+    fd, tmp = tempfile.mkstemp(dir=folder, suffix=".tmp")
+    with os.fdopen(fd, "w") as fh:
+        json.dump(data, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
 
 
 def footprint_bytes(shape, omega: float, max_slowness: float, h: float,
@@ -303,6 +347,44 @@ class Problem:
         n = ctypes.c_int()
         _check(_lib.hh_num_levels(self._handle, ctypes.byref(n)), "hh_num_levels")
         return n.value
+
+    def get_tiles(self, level: int):
+        """``(down, up)`` tile shape ids of level ``level``'s legs (-1: default)."""
+        d, u = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.hh_get_tiles(self._handle, int(level), ctypes.byref(d), ctypes.byref(u)),
+               "hh_get_tiles")
+        return d.value, u.value
+
+    def set_tiles(self, level: int, down: int, up: int):
+        _check(_lib.hh_set_tiles(self._handle, int(level), int(down), int(up)), "hh_set_tiles")
+
+    def autotune(self, precond_f32: bool = False, nrhs: int = 1, cache: Optional[str] = None,
+                 reps: int = 10, stream=None):
+        """Tile shapes of the multigrid legs chosen by timing (``hh_autotune``),
+        for the complex64 or complex128 cycle and batches of ``nrhs`` sources.
+        With ``cache`` (a JSON file) a choice stored for the same hierarchy,
+        precision and batch size is reused instead of timed, and a new one is
+        stored. Returns ``[(down, up)]`` per level with legs."""
+        nlegs = self.num_levels - 1 if self.ndim == 2 else 0
+        if nlegs < 1:
+            return []
+        key = tile_cache_key([self.level_info(l)[0] for l in range(self.num_levels)],
+                             precond_f32, nrhs)
+        if cache is not None:
+            hit = read_tile_cache(cache).get(key)
+            if hit is not None and len(hit) == nlegs:
+                for l, (d, u) in enumerate(hit):
+                    self.set_tiles(l, d, u)
+                return [tuple(t) for t in hit]
+        ws = torch.empty(self.workspace_bytes_batch(1, nrhs), dtype=torch.uint8,
+                         device=self.device)
+        _check(_lib.hh_autotune(self._handle, HH_PRECOND_F32 if precond_f32 else 0, int(nrhs),
+                                _vp(ws.data_ptr()), ws.numel(), int(reps),
+                                _vp(_stream_ptr(stream))), "hh_autotune")
+        tiles = [self.get_tiles(l) for l in range(nlegs)]
+        if cache is not None:
+            write_tile_cache(cache, key, tiles)
+        return tiles
 
     def level_info(self, level: int):
         shape = (ctypes.c_int64 * 2)()

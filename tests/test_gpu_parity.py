@@ -709,3 +709,96 @@ def test_max_coarse_argument_checks(hh):
     P1 = _problem(hh, w1.slowness, w1.omega, w1.alpha, w1.h)
     with pytest.raises(hh.HHError):
         P1.set_max_coarse(8192)
+
+
+# ---------------------------------------------------------------------------
+# tile shapes of the multigrid legs and their autotuner
+# ---------------------------------------------------------------------------
+def test_every_tile_shape_gives_the_same_bits(hh):
+    """Each leg's tile shape changes only how nodes are grouped into blocks:
+    the preconditioner output is the same to the bit for every shape of every
+    leg (complex128 and complex64 cycles), and for all levels changed at once."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    nlegs = P.num_levels - 1
+    assert nlegs >= 3
+    v = _t(wl.random_complex(w.shape, 21))
+    for f32 in (False, True):
+        z0 = _np(P.apply_precond(v, f32=f32))
+        for l in range(nlegs):
+            for d in range(hh.HH_TILE_DOWN_COUNT):
+                for u in range(hh.HH_TILE_UP_COUNT):
+                    P.set_tiles(l, d, u)
+                    assert np.array_equal(_np(P.apply_precond(v, f32=f32)), z0), (f32, l, d, u)
+            P.set_tiles(l, -1, -1)
+        for d, u in ((1, 1), (0, 2), (1, 0)):
+            for l in range(nlegs):
+                P.set_tiles(l, d, u)
+            assert np.array_equal(_np(P.apply_precond(v, f32=f32)), z0), (f32, d, u)
+        for l in range(nlegs):
+            P.set_tiles(l, -1, -1)
+
+
+def test_autotune_keeps_results_and_caches_choices(hh, tmp_path):
+    """The tuner picks a valid shape per leg (or keeps the default); a solve with the tuned shapes
+    gives the bits of the default ones; a second handle on the same hierarchy
+    takes the choice from the cache file."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    ref = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    u_ref = _np(ref.u).copy()
+    cache = str(tmp_path / "tiles.json")
+    tiles = P.autotune(cache=cache)
+    assert len(tiles) == P.num_levels - 1
+    for l, (d, u) in enumerate(tiles):
+        assert -1 <= d < hh.HH_TILE_DOWN_COUNT and -1 <= u < hh.HH_TILE_UP_COUNT
+        assert P.get_tiles(l) == (d, u)
+    res = P.solve(_t(w.source), tol=w.tol, restart=w.restart)
+    assert res.iterations == ref.iterations
+    assert np.array_equal(_np(res.u), u_ref)
+    key = hh.tile_cache_key([P.level_info(l)[0] for l in range(P.num_levels)], False, 1)
+    assert hh.read_tile_cache(cache)[key] == [list(t) for t in tiles]
+    Q = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    # a planted entry shows that the cache is read, not re-timed
+    planted = [(1, 1)] * len(tiles)
+    hh.write_tile_cache(cache, key, planted)
+    assert Q.autotune(cache=cache) == planted
+    assert all(Q.get_tiles(l) == (1, 1) for l in range(len(tiles)))
+    # the complex64 cycle for batches of 4 is another entry
+    tiles4 = Q.autotune(precond_f32=True, nrhs=4, cache=cache)
+    assert len(hh.read_tile_cache(cache)) == 2 and len(tiles4) == len(tiles)
+
+
+def test_autotuned_batch_gives_the_same_bits(hh):
+    shape, h, freq = (65, 129), 10.0, 8.0
+    m = wl.smooth_slowness_2d(*shape, h, 5)
+    P = _problem(hh, m, 2 * np.pi * freq, 0.01, h)
+    F = _t(_batch_sources(shape, [(3, 64), (32, 5), (60, 120)]))
+    kw = dict(tol=1e-7, restart=9, precond_f32=True)
+    a = P.solve_batch(F, **kw)
+    ua = _np(a.u).copy()
+    P.autotune(precond_f32=True, nrhs=3, reps=3)
+    b = P.solve_batch(F, **kw)
+    assert np.array_equal(b.iterations, a.iterations)
+    assert np.array_equal(_np(b.u), ua)
+
+
+def test_tile_argument_checks(hh):
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    nl = P.num_levels
+    for bad in ((nl - 1, 0, 0), (-1, 0, 0), (0, hh.HH_TILE_DOWN_COUNT, 0),
+                (0, 0, hh.HH_TILE_UP_COUNT), (0, -2, 0)):
+        with pytest.raises(hh.HHError):
+            P.set_tiles(*bad)
+    with pytest.raises(hh.HHError):
+        P.get_tiles(nl - 1)
+    ws = torch.empty(16, dtype=torch.uint8, device=DEV)
+    with pytest.raises(hh.HHError):
+        hh._check(hh._lib.hh_autotune(P._handle, 0, 1, hh._vp(ws.data_ptr()), 16, 10, None),
+                  "hh_autotune")
+    g = wl.layered_1d_well()
+    Q = _problem(hh, g.slowness, g.omega, g.alpha, g.h)
+    assert Q.autotune() == []
+    with pytest.raises(hh.HHError):
+        Q.get_tiles(0)
