@@ -125,7 +125,12 @@ template <> struct Mfma<double> {
     }
 };
 
-template <class R>
+// WIDE (complex64 with n even, so every row of A starts on 16 bytes): each
+// load instruction takes two consecutive entries per lane, entries 8v + 2q and
+// 8v + 2q + 1 of the step (v = 0, 1) standing in the places u = 2v, 2v + 1 of
+// the k order (half the load instructions: measured 72 -> 88 TFLOP/s at
+// n = 7676).
+template <class R, bool WIDE>
 __global__ void __launch_bounds__(256) k_coarsest_mfma(int n, const typename Cx<R>::type* __restrict__ A,
                                                        const typename Cx<R>::type* __restrict__ X,
                                                        int nrhs, int64_t bs, int chunks_per_split,
@@ -161,13 +166,33 @@ __global__ void __launch_bounds__(256) k_coarsest_mfma(int n, const typename Cx<
     // one partial step at the end loads entry 0 in place of entries k >= n and
     // zeroes their A values (A is finite). No load sits under a branch.
     auto load = [&](int kc, C (&ra)[2][4], C (&rx)[2][4]) {
+        if constexpr (WIDE) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = kc * MF_KC + 4 * u + q;
+            for (int v = 0; v < 2; ++v) {
+                const int k = kc * MF_KC + 8 * v + 2 * q;
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                ra[t][u] = pa[t][k];
-                rx[t][u] = px[t][k];
+                for (int t = 0; t < 2; ++t) {
+                    const float4 a4 = *reinterpret_cast<const float4*>(pa[t] + k);
+                    const float4 x4 = *reinterpret_cast<const float4*>(px[t] + k);
+                    ra[t][2 * v].x = a4.x;
+                    ra[t][2 * v].y = a4.y;
+                    ra[t][2 * v + 1].x = a4.z;
+                    ra[t][2 * v + 1].y = a4.w;
+                    rx[t][2 * v].x = x4.x;
+                    rx[t][2 * v].y = x4.y;
+                    rx[t][2 * v + 1].x = x4.z;
+                    rx[t][2 * v + 1].y = x4.w;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = kc * MF_KC + 4 * u + q;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    ra[t][u] = pa[t][k];
+                    rx[t][u] = px[t][k];
+                }
             }
         }
     };
@@ -200,7 +225,7 @@ __global__ void __launch_bounds__(256) k_coarsest_mfma(int n, const typename Cx<
     if (nfull >= kc0 && nfull < kc1) {        // the partial last step, in this range
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int k = nfull * MF_KC + 4 * u + q;
+            const int k = nfull * MF_KC + (WIDE ? 8 * (u >> 1) + 2 * q + (u & 1) : 4 * u + q);
             const int kk = k < n ? k : 0;
             const R m = k < n ? (R)1 : (R)0;
 #pragma unroll
@@ -264,8 +289,17 @@ hipError_t gemm(int n, const typename Cx<R>::type* A, const typename Cx<R>::type
     const int ks = gemm_splits(n, bt.n);
     const int nchunks = (n + MF_KC - 1) / MF_KC;
     const int cps = (nchunks + ks - 1) / ks;
-    HH_LAUNCH((k_coarsest_mfma<R>), dim3((n + MF_TM - 1) / MF_TM, groups, ks), dim3(256), 0, s,
-              n, A, x, bt.n, bt.bs, cps, part);
+    const dim3 grid((n + MF_TM - 1) / MF_TM, groups, ks);
+    // with n even, A and X on 16 bytes and a per-source stride that is a
+    // multiple of 16 (the workspace layout keeps 256), every row of A and every
+    // X entry pair 2i, 2i + 1 is 16-byte aligned
+    if (sizeof(C) == 8 && n % 2 == 0 && bt.bs % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(x) % 16 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0)
+        HH_LAUNCH((k_coarsest_mfma<R, sizeof(C) == 8>), grid, dim3(256), 0, s, n, A, x, bt.n,
+                  bt.bs, cps, part);
+    else
+        HH_LAUNCH((k_coarsest_mfma<R, false>), grid, dim3(256), 0, s, n, A, x, bt.n, bt.bs, cps,
+                  part);
     HH_LAUNCH((k_coarsest_sum<C>), dim3((n + 255) / 256, bt.n), dim3(256), 0, s, n, bt.n, bt.bs,
               ks, groups * MF_TN, (const C*)part, y);
     return hipGetLastError();

@@ -574,11 +574,14 @@ def test_batch_equals_single_small_grid(hh, kw):
 @pytest.mark.parametrize("kw", [dict(restart=10, tol=1e-8),
                                 dict(restart=10, tol=1e-7, precond_f32=True)],
                          ids=["f64", "f32"])
-def test_batch_two_source_groups_ragged_coarsest(hh, kw):
+@pytest.mark.parametrize("shape", [(45, 97), (49, 97)], ids=["nc156", "nc91"])
+def test_batch_two_source_groups_ragged_coarsest(hh, kw, shape):
     """37 sources: the batched coarsest product runs a full group of 32 and a
     partial one of 5; the grid makes every level (and the coarsest size) ragged
-    against the product's 16-entry steps and 128-row blocks."""
-    shape, h, freq = (45, 97), 10.0, 5.0
+    against the product's 16-entry steps and 128-row blocks; an even and an odd
+    coarsest size (the complex64 product loads entry pairs only when rows are
+    16-byte aligned)."""
+    h, freq = 10.0, 5.0
     m = _model(shape, h, seed=8)
     P = _problem(hh, m, 2 * np.pi * freq, 0.01, h)
     nc = int(np.prod(P.level_info(P.num_levels - 1)[0]))
