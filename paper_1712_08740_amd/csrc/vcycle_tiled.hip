@@ -55,6 +55,18 @@ struct Fine5 {
     __device__ __forceinline__ C wd(int iz, int ix) const {
         return op.wdinv[(int64_t)iz * op.nx + ix];
     }
+    // the stored data of row p (m^2), and the row built from it
+    typedef T Raw;
+    __device__ __forceinline__ Raw load_raw(int64_t p) const { return op.m2[p]; }
+    __device__ __forceinline__ Row make_row(const Raw& m2p, int iz, int ix) const {
+        const Coef5T<T> c = fine_coefs(op, iz, ix, m2p);
+        Row r;
+        r.diag = c.diag;
+        r.cx = c.cx;
+        r.cz = c.cz;
+        return r;
+    }
+    __device__ __forceinline__ C wd_at(int64_t p) const { return op.wdinv[p]; }
     __device__ __forceinline__ static Row zero_row() {
         Row r;
         r.diag = cconv<C>(mk(1.0, 0.0));
@@ -94,6 +106,17 @@ struct Coarse9 {
     __device__ __forceinline__ C wd(int iz, int ix) const {
         return op.wdinv[(int64_t)iz * op.nx + ix];
     }
+    // the stored data of row p (its 9 coefficients) is the row
+    typedef Row Raw;
+    __device__ __forceinline__ Raw load_raw(int64_t p) const {
+        const int64_t N = (int64_t)op.nz * op.nx;
+        Row r;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) r.a[t] = op.C[t * N + p];
+        return r;
+    }
+    __device__ __forceinline__ Row make_row(const Raw& raw, int, int) const { return raw; }
+    __device__ __forceinline__ C wd_at(int64_t p) const { return op.wdinv[p]; }
     __device__ __forceinline__ static Row zero_row() {
         Row r;
 #pragma unroll
@@ -131,11 +154,12 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
     typedef typename OP::C C;
     typedef typename OP::real T;
     constexpr int W1X = 2 * TCX + 5, W1Z = 2 * TCZ + 5;   // largest x1 region
-    __shared__ C sb[W1X * W1Z];
-    __shared__ C sw[W1X * W1Z];                             // omega_J / diag
-    __shared__ C s1[W1X * W1Z];
+    constexpr int TRASH = W1X * W1Z;                        // slot for stores past the region
+    __shared__ C sb[W1X * W1Z + 1];
+    __shared__ C sw[W1X * W1Z + 1];                         // omega_J / diag
+    __shared__ C s1[W1X * W1Z + 1];
     __shared__ C s2[W1X * W1Z];
-    __shared__ typename OP::Row srow[W1X * W1Z];           // rows of the x1 region
+    __shared__ typename OP::Row srow[W1X * W1Z + 1];       // rows of the x1 region
     const int rb = blockIdx.y;                             // right-hand side
     active = rhs_at(active, rb, bs);
     if (inactive(active)) return;
@@ -153,26 +177,38 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
     const int olz = hz ? 2 * cz0 : cz0, ohz = hz ? 2 * (cz0 + TCZ) - 1 : cz0 + TCZ - 1;
     const int n1 = wx * wz;
     constexpr int SL1 = (W1X * W1Z + NT - 1) / NT;
-    // phase 1: b, the operator rows and x1 on the x1 region (the only global reads)
+    // phase 1: b, the operator rows and x1 on the x1 region (the only global
+    // reads). Every load of the thread is issued before any value is used:
+    // nodes outside the grid or the region read node 0 and take zero values by
+    // selection, and stores past the region go to a spare slot, so no load or
+    // use sits under a branch (which made the loads of each node wait for the
+    // previous node's).
+    SC lb[SL1];
+    C lw[SL1];
+    typename OP::Raw lr[SL1];
 #pragma unroll
     for (int k = 0; k < SL1; ++k) {
         const int i = threadIdx.x + k * NT;
-        if (i < n1) {
-            const int qz = oz + i / wx, qx = ox + i % wx;
-            C bq = czero<C>(), x1 = czero<C>(), wq = czero<C>();
-            typename OP::Row r = OP::zero_row();
-            if (in_grid(qz, qx, nz, nx)) {
-                const int64_t q = (int64_t)qz * nx + qx;
-                bq = cconv<C>(src[q]);
-                r = A.row(qz, qx);
-                wq = A.wd(qz, qx);
-                x1 = cmul(bq, wq);
-            }
-            sb[i] = bq;
-            sw[i] = wq;
-            srow[i] = r;
-            s1[i] = x1;
-        }
+        const int qz = oz + i / wx, qx = ox + i % wx;
+        const bool ok = i < n1 && in_grid(qz, qx, nz, nx);
+        const int64_t q = ok ? (int64_t)qz * nx + qx : 0;
+        lb[k] = src[q];
+        lw[k] = A.wd_at(q);
+        lr[k] = A.load_raw(q);
+    }
+#pragma unroll
+    for (int k = 0; k < SL1; ++k) {
+        const int i = threadIdx.x + k * NT;
+        const int qz = oz + i / wx, qx = ox + i % wx;
+        const bool ok = i < n1 && in_grid(qz, qx, nz, nx);
+        const C bq = ok ? cconv<C>(lb[k]) : czero<C>();
+        const C wq = ok ? lw[k] : czero<C>();
+        const typename OP::Row r = ok ? A.make_row(lr[k], qz, qx) : OP::zero_row();
+        const int d = i < n1 ? i : TRASH;
+        sb[d] = bq;
+        sw[d] = wq;
+        srow[d] = r;
+        s1[d] = cmul(bq, wq);
     }
     __syncthreads();
     // phase 2: x2 on the x1 region shrunk by one node (stored at the same local index)
@@ -261,54 +297,73 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
     out = rhs_nn(out, rb, bs);
     constexpr int WX = TX + 4, WZ = TZ + 4;
     constexpr int W3X = TX + 2, W3Z = TZ + 2;
-    __shared__ C sp[WX * WZ];                         // x' (tile + 2)
+    constexpr int TRASH = WX * WZ, TRASH3 = W3X * W3Z;   // slots for stores past the regions
+    __shared__ C sp[WX * WZ + 1];                     // x' (tile + 2)
     __shared__ C s3[WX * WZ];                         // x3 (tile + 1)
-    __shared__ C sbb[W3X * W3Z];                      // b on the tile + 1
-    __shared__ C sw[W3X * W3Z];                       // omega_J / diag on the tile + 1
-    __shared__ typename OP::Row srow[W3X * W3Z];      // rows on the tile + 1
+    __shared__ C sbb[W3X * W3Z + 1];                  // b on the tile + 1
+    __shared__ C sw[W3X * W3Z + 1];                   // omega_J / diag on the tile + 1
+    __shared__ typename OP::Row srow[W3X * W3Z + 1];  // rows on the tile + 1
     const int nz = A.nz(), nx = A.nx();
     const int tile = xcd_tile(blockIdx.x, ntiles);
     const int fx0 = (tile % ntx) * TX, fz0 = (tile / ntx) * TZ;
     const int ox = fx0 - 2, oz = fz0 - 2;
     constexpr int SL = (WX * WZ + NT - 1) / NT;
     constexpr int SL3 = (W3X * W3Z + NT - 1) / NT;
-    // phase 1: x' = x2 + P e on the tile + 2; b and rows on the tile + 1
+    // phase 1: x' = x2 + P e on the tile + 2; b and rows on the tile + 1.
+    // Every load of the thread is issued before any value is used (nodes
+    // outside the grid or the regions read node 0 and take zero values by
+    // selection; stores past a region go to a spare slot).
+    C le[SL][4], lx[SL];
+    SB lb[SL3];
+    C lw[SL3];
+    typename OP::Raw lr[SL3];
 #pragma unroll
     for (int k = 0; k < SL; ++k) {
         const int i = threadIdx.x + k * NT;
-        if (i < WX * WZ) {
-            const int qz = oz + i / WX, qx = ox + i % WX;
-            C v = czero<C>();
-            if (in_grid(qz, qx, nz, nx)) {
-                int z0, z1, x0, x1;
-                T wz0, wz1, wx0, wx1;
-                interp2(qz, hz, z0, z1, wz0, wz1);
-                interp2(qx, hx, x0, x1, wx0, wx1);
-                const C e00 = e[cg.at(z0, x0)], e01 = e[cg.at(z0, x1)];
-                const C e10 = e[cg.at(z1, x0)], e11 = e[cg.at(z1, x1)];
-                const C pe = cadd(cadd(cscale(e00, wz0 * wx0), cscale(e01, wz0 * wx1)),
-                                  cadd(cscale(e10, wz1 * wx0), cscale(e11, wz1 * wx1)));
-                v = cadd(x2[(int64_t)qz * nx + qx], pe);
-            }
-            sp[i] = v;
-        }
+        const int qz = oz + i / WX, qx = ox + i % WX;
+        const bool ok = i < WX * WZ && in_grid(qz, qx, nz, nx);
+        int z0, z1, x0, x1;
+        T wz0, wz1, wx0, wx1;
+        interp2(qz, hz, z0, z1, wz0, wz1);
+        interp2(qx, hx, x0, x1, wx0, wx1);
+        le[k][0] = e[ok ? cg.at(z0, x0) : 0];
+        le[k][1] = e[ok ? cg.at(z0, x1) : 0];
+        le[k][2] = e[ok ? cg.at(z1, x0) : 0];
+        le[k][3] = e[ok ? cg.at(z1, x1) : 0];
+        lx[k] = x2[ok ? (int64_t)qz * nx + qx : 0];
     }
 #pragma unroll
     for (int k = 0; k < SL3; ++k) {
         const int j = threadIdx.x + k * NT;
-        if (j < W3X * W3Z) {
-            const int qz = fz0 - 1 + j / W3X, qx = fx0 - 1 + j % W3X;
-            typename OP::Row r = OP::zero_row();
-            C bq = czero<C>(), wq = czero<C>();
-            if (in_grid(qz, qx, nz, nx)) {
-                r = A.row(qz, qx);
-                bq = cconv<C>(b[(int64_t)qz * nx + qx]);
-                wq = A.wd(qz, qx);
-            }
-            srow[j] = r;
-            sbb[j] = bq;
-            sw[j] = wq;
-        }
+        const int qz = fz0 - 1 + j / W3X, qx = fx0 - 1 + j % W3X;
+        const bool ok = j < W3X * W3Z && in_grid(qz, qx, nz, nx);
+        const int64_t q = ok ? (int64_t)qz * nx + qx : 0;
+        lb[k] = b[q];
+        lw[k] = A.wd_at(q);
+        lr[k] = A.load_raw(q);
+    }
+#pragma unroll
+    for (int k = 0; k < SL; ++k) {
+        const int i = threadIdx.x + k * NT;
+        const int qz = oz + i / WX, qx = ox + i % WX;
+        const bool ok = i < WX * WZ && in_grid(qz, qx, nz, nx);
+        int z0, z1, x0, x1;
+        T wz0, wz1, wx0, wx1;
+        interp2(qz, hz, z0, z1, wz0, wz1);
+        interp2(qx, hx, x0, x1, wx0, wx1);
+        const C pe = cadd(cadd(cscale(le[k][0], wz0 * wx0), cscale(le[k][1], wz0 * wx1)),
+                          cadd(cscale(le[k][2], wz1 * wx0), cscale(le[k][3], wz1 * wx1)));
+        sp[i < WX * WZ ? i : TRASH] = ok ? cadd(lx[k], pe) : czero<C>();
+    }
+#pragma unroll
+    for (int k = 0; k < SL3; ++k) {
+        const int j = threadIdx.x + k * NT;
+        const int qz = fz0 - 1 + j / W3X, qx = fx0 - 1 + j % W3X;
+        const bool ok = j < W3X * W3Z && in_grid(qz, qx, nz, nx);
+        const int d = j < W3X * W3Z ? j : TRASH3;
+        srow[d] = ok ? A.make_row(lr[k], qz, qx) : OP::zero_row();
+        sbb[d] = ok ? cconv<C>(lb[k]) : czero<C>();
+        sw[d] = ok ? lw[k] : czero<C>();
     }
     __syncthreads();
     // phase 2: x3 on the tile plus one node
