@@ -51,10 +51,12 @@ def parse():
     ap.add_argument("--kernel", default="auto",
                     help="kernel class for the roofline figure; 'auto' (default) times every "
                          "class over one warm-up solve and takes the one with the most device time")
-    ap.add_argument("--tiles", default="auto", choices=["auto", "default"],
+    ap.add_argument("--tiles", default=None, choices=["auto", "default"],
                     help="tile shapes of the multigrid legs: 'auto' times every shape on the "
                          "workload's hierarchy during set-up (hh_autotune), 'default' keeps the "
-                         "fixed rule")
+                         "fixed rule. Unset: 'auto' for the batched workload (measured faster), "
+                         "'default' for single sources (the tuner's picks there are within the "
+                         "timing noise and may differ from run to run)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200,
                     help="serving: requests in the Poisson stream (mean 200/s)")
@@ -67,7 +69,10 @@ def parse():
                          "(a plain copy kernel of known size, to scale hardware byte counters)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall-clock budget of the CPU oracle sample")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.tiles is None:
+        a.tiles = "auto" if a.workload == "grf_801x301_batch" else "default"
+    return a
 
 
 def measured_traffic(workload_name: str, kernel: str):
