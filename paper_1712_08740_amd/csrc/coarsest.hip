@@ -1,6 +1,7 @@
 // Coarsest-level solve of the V-cycle: z = A^{-1} b with the explicit inverse
 // computed at set-up, as a dense complex matrix-vector product with a
-// fixed-order reduction.
+// fixed-order reduction; for a batch of sources, as one complex matrix product
+// on the matrix cores (k_coarsest_mfma).
 #include "helmholtz.h"
 #include "hh_internal.h"
 
@@ -46,7 +47,7 @@ __global__ void __launch_bounds__(256) k_gemv_pred(int n, const C* __restrict__ 
 // Several right-hand sides with x of another precision than A (the fine grid
 // is itself the coarsest level and x is the complex128 Krylov vector): one
 // workgroup per (row, right-hand side). The same-precision batched product
-// goes to a library GEMM in the solve driver.
+// is k_coarsest_mfma below.
 template <class C, class X>
 __global__ void __launch_bounds__(256) k_gemv_batch(int n, const C* __restrict__ A,
                                                     const X* __restrict__ x, C* __restrict__ y,
