@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grf_401x201",
                     choices=["grf_401x201", "layered_1d_well", "grf_1201x401",
-                             "grf_801x301_batch", "serving"],
+                             "grf_801x301_batch", "serving", "stream_probe"],
                     help="grf_801x301_batch: 32 top-row sources x 4 frequencies, one batched "
                          "solve of 32 sources per frequency (a step = all 128 solves)")
     ap.add_argument("--max-coarse", type=int, default=None,
@@ -377,6 +377,33 @@ def main_serving(a, hh, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def main_stream_probe(torch, dev):
+    """The HBM bandwidth plain streaming kernels reach on this device (PyTorch's
+    own copy, sum and axpy over 1 GiB float64 vectors, best of five, events on
+    the stream): the practical ceiling beside the 8 TB/s peak."""
+    n = (1 << 30) // 8
+    x = torch.ones(n, dtype=torch.float64, device=dev)
+    y = torch.empty_like(x)
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: y.copy_(x), 16 * n),
+                             ("sum", lambda: x.sum(), 8 * n),
+                             ("axpy", lambda: y.add_(x, alpha=2.0), 24 * n)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(5):
+            s0.record()
+            fn()
+            s1.record()
+            torch.cuda.synchronize()
+            best = min(best, s0.elapsed_time(s1))
+        out[name] = {"GB/s": nbytes / (best * 1e-3) / 1e9, "ms": best, "bytes": nbytes}
+    print(json.dumps({"metric": "device streaming bandwidth (practical ceiling)",
+                      "peak_GB/s": HBM_PEAK_GBS, "kernels": out}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -397,6 +424,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.workload == "stream_probe":
+        return main_stream_probe(torch, dev)
     if a.workload == "grf_801x301_batch":
         return main_batch(a, hh, torch, dev)
     if a.workload == "serving":
