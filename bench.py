@@ -57,6 +57,11 @@ def parse():
                          "fixed rule. Unset: 'auto' for the batched workload (measured faster), "
                          "'default' for single sources (the tuner's picks there are within the "
                          "timing noise and may differ from run to run)")
+    ap.add_argument("--batch-streams", type=int, default=1,
+                    help="batched workload: the frequencies' batches run concurrently on this "
+                         "many streams, one host thread each (default 1: one after another, so "
+                         "that the roofline times each kernel without contention; 2-4 streams "
+                         "measured 2% more solves/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=200,
                     help="serving: requests in the Poisson stream (mean 200/s)")
@@ -206,11 +211,32 @@ def main_batch(a, hh, torch, dev):
     t_tune = time.perf_counter() - t_tune
     wss = [torch.empty(P.workspace_bytes_batch(restart, len(sources)), dtype=torch.uint8,
                        device=dev) for P in probs]
-    U = torch.empty_like(Ft)
+    Us = [torch.empty_like(Ft) for _ in probs]
+    # one stream (default priority) and host thread per frequency: the batches
+    # are independent problems, so their kernels may overlap on the device
+    nstreams = max(1, min(a.batch_streams, len(probs)))
+    streams = [torch.cuda.Stream(device=dev) for _ in range(nstreams)]
+    torch.cuda.synchronize()
+
+    def solve_group(g):
+        return [P.solve_batch(Ft, tol=tol, restart=restart, max_iters=2000, precond_f32=mixed,
+                              U=Us[i], workspace=wss[i], stream=streams[g])
+                for i, P in enumerate(probs) if i % nstreams == g]
+
+    pool = None
+    if nstreams > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        pool = ThreadPoolExecutor(max_workers=nstreams)
 
     def one():
-        return [P.solve_batch(Ft, tol=tol, restart=restart, max_iters=2000, precond_f32=mixed,
-                              U=U, workspace=ws) for P, ws in zip(probs, wss)]
+        if pool is None:
+            return solve_group(0)
+        groups = list(pool.map(solve_group, range(nstreams)))
+        out = [None] * len(probs)
+        for g, rs in enumerate(groups):
+            for j, r in enumerate(rs):
+                out[g + j * nstreams] = r
+        return out
 
     for _ in range(a.warmup):
         one()
@@ -286,7 +312,7 @@ def main_batch(a, hh, torch, dev):
             "workload": "grf2d_801x301_s4_32src_x_4freq",
             "grid_nx_nz": [nx, nz], "h_m": 10.0, "freq_hz": freqs, "alpha": 0.01,
             "beta": [1.0, 0.5], "tol": tol, "restart": restart, "sources_per_batch": len(sources),
-            "solves_per_step": n_solves, "max_coarse": max_coarse,
+            "solves_per_step": n_solves, "max_coarse": max_coarse, "streams": nstreams,
             "precond": "V(2,2) omega-Jacobi, Galerkin coarse operators, dense coarsest inverse"
                        + (", complex64 inside FP64 FGMRES" if mixed else ", complex128"),
             "levels_nz_nx": [[list(P.level_info(l)[0]) for l in range(P.num_levels)]
