@@ -593,6 +593,20 @@ def test_batch_two_source_groups_ragged_coarsest(hh, kw, shape):
     assert np.all(res.status == 0)
 
 
+@pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
+def test_batch_is_bitwise_reproducible(hh, f32):
+    """The batched coarsest product (matrix cores, split over k) adds its terms
+    and partial sums in a fixed order: two batched solves give the same bits."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    F = _t(_batch_sources(w.shape, [(5, 200), (100, 37), (200, 400), (0, 0), (150, 300)]))
+    a = P.solve_batch(F, tol=w.tol, restart=w.restart, precond_f32=f32)
+    ua = _np(a.u).copy()
+    b = P.solve_batch(F, tol=w.tol, restart=w.restart, precond_f32=f32)
+    assert np.array_equal(a.iterations, b.iterations)
+    assert np.array_equal(_np(b.u), ua)
+
+
 @pytest.mark.parametrize("shape", [(1001,), (3, 3)], ids=str)
 def test_batch_1d_and_single_level(hh, shape):
     if len(shape) == 1:
