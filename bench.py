@@ -393,6 +393,26 @@ def main_serving(a, hh, torch, dev):
     for (_, rq), r in zip(reqs, results):
         key = f"{rq.slowness.shape[1]}x{rq.slowness.shape[0]}"
         by_grid.setdefault(key, []).append(r.latency * 1e3)
+    precision = None
+    if a.precision == "mixed":
+        # after the stream: every request again with the complex128 cycle
+        import dataclasses
+        diffs, worst = [], None
+        for (_, rq), r in zip(reqs, results):
+            ref = serve.solve_one(dataclasses.replace(rq, precond_f32=False), dev,
+                                  torch.cuda.current_stream())
+            d = float(np.linalg.norm(r.u - ref.u) / np.linalg.norm(ref.u))
+            diffs.append(d)
+            if worst is None or d > worst["rel_diff"]:
+                worst = {"rel_diff": d, "grid_nx_nz": [rq.slowness.shape[1], rq.slowness.shape[0]],
+                         "freq_hz": rq.freq_hz, "iterations_c64": r.iterations,
+                         "iterations_c128": ref.iterations,
+                         "true_rel_res_c64": r.true_rel_res, "true_rel_res_c128": ref.true_rel_res}
+        precision = {"rel_diff_vs_fp64_solve_max": max(diffs),
+                     "rel_diff_vs_fp64_solve_median": float(np.median(diffs)),
+                     "requests": len(diffs), "largest": worst,
+                     "reference": "each request solved again with the complex128 "
+                                  "preconditioner, same tol and restart"}
     out = {
         "metric": METRIC,
         "value": st["solves_per_s"],
@@ -407,7 +427,7 @@ def main_serving(a, hh, torch, dev):
                    "h_m": 10.0, "alpha": 0.01, "tol": 1e-6, "restart": 30,
                    "workers": a.serve_workers, "budget_gib": a.serve_budget_gib,
                    "converged": st["converged"], "max_iterations": st["max_iterations"],
-                   "model_generation_s": t_gen},
+                   "model_generation_s": t_gen, "precision_check": precision},
         "latency_ms": {"p50": st["latency_p50_ms"], "p99": st["latency_p99_ms"],
                        "queue_p50": st["queue_p50_ms"], "queue_p99": st["queue_p99_ms"],
                        "p50_by_grid": {k: float(np.percentile(v, 50)) for k, v in by_grid.items()},
