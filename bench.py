@@ -298,6 +298,30 @@ def main_batch(a, hh, torch, dev):
         precision = {"max_rel_diff_vs_fp64_solve_by_freq": diffs,
                      "reference": "hh_solve_batch with the complex128 preconditioner, same "
                                   "tol and restart"}
+    # the plain solver on the same sources: single sources one at a time with
+    # the complex128 cycle and the default dense coarsest limit (8 sources per
+    # frequency; problems set up outside the timing, as the batch's), after the
+    # timed region
+    sample = list(range(0, len(sources), max(1, len(sources) // 8)))[:8]
+    plain_probs = [hh.Problem(m, 2 * np.pi * fz, 0.01, 10.0) for fz in freqs]
+    plain_ws = [Q.workspace(restart) for Q in plain_probs]
+    plain_its = []
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter()
+    for Q, ws1 in zip(plain_probs, plain_ws):
+        for i in sample:
+            r1 = Q.solve(Ft[i], tol=tol, restart=restart, max_iters=2000, workspace=ws1)
+            if r1.status != hh.HH_OK:
+                print("plain solve did not converge", file=sys.stderr)
+                sys.exit(1)
+            plain_its.append(r1.iterations)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t_plain
+    plain = {"solves_per_s": len(plain_its) / t_plain,
+             "iterations_min_max": [min(plain_its), max(plain_its)],
+             "sample": f"{len(sample)} sources per frequency, one hh_solve each, complex128 "
+                       "preconditioner, default dense coarsest limit, same tol and restart"}
+    del plain_probs, plain_ws
     achieved = (kbytes / (kms * 1e-3)) / 1e9 if kms > 0 else 0.0
     if kernel == "gemv":
         # a dense contraction on the matrix cores: priced against the MFMA peak
@@ -336,6 +360,7 @@ def main_batch(a, hh, torch, dev):
             "true_rel_res_max": max(res),
             "setup_ms": 1e3 * t_setup,
             "precision_check": precision,
+            "plain_fp64_one_at_a_time": plain,
             "tiles_down_up_by_freq": [_tile_names(hh, t, a.tiles) for t in tiles],
             "autotune_ms": 1e3 * t_tune,
         },
