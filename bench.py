@@ -418,11 +418,13 @@ def main_serving(a, hh, torch, dev):
     for (_, rq), r in zip(reqs, results):
         key = f"{rq.slowness.shape[1]}x{rq.slowness.shape[0]}"
         by_grid.setdefault(key, []).append(r.latency * 1e3)
-    precision = None
+    precision = plain = None
     if a.precision == "mixed":
         # after the stream: every request again with the complex128 cycle
         import dataclasses
         diffs, worst = [], None
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter()
         for (_, rq), r in zip(reqs, results):
             ref = serve.solve_one(dataclasses.replace(rq, precond_f32=False), dev,
                                   torch.cuda.current_stream())
@@ -433,6 +435,12 @@ def main_serving(a, hh, torch, dev):
                          "freq_hz": rq.freq_hz, "iterations_c64": r.iterations,
                          "iterations_c128": ref.iterations,
                          "true_rel_res_c64": r.true_rel_res, "true_rel_res_c128": ref.true_rel_res}
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t_plain
+        plain = {"solves_per_s": len(diffs) / t_plain,
+                 "what": "the same requests one at a time, set-up included, complex128 "
+                         "preconditioner, on one stream, back to back (no arrival gaps); "
+                         "includes copying each result to the host"}
         precision = {"rel_diff_vs_fp64_solve_max": max(diffs),
                      "rel_diff_vs_fp64_solve_median": float(np.median(diffs)),
                      "requests": len(diffs), "largest": worst,
@@ -452,7 +460,8 @@ def main_serving(a, hh, torch, dev):
                    "h_m": 10.0, "alpha": 0.01, "tol": 1e-6, "restart": 30,
                    "workers": a.serve_workers, "budget_gib": a.serve_budget_gib,
                    "converged": st["converged"], "max_iterations": st["max_iterations"],
-                   "model_generation_s": t_gen, "precision_check": precision},
+                   "model_generation_s": t_gen, "precision_check": precision,
+                   "plain_fp64_one_at_a_time": plain},
         "latency_ms": {"p50": st["latency_p50_ms"], "p99": st["latency_p99_ms"],
                        "queue_p50": st["queue_p50_ms"], "queue_p99": st["queue_p99_ms"],
                        "p50_by_grid": {k: float(np.percentile(v, 50)) for k, v in by_grid.items()},
