@@ -252,6 +252,39 @@ def test_unpreconditioned_matches_oracle(hh):
     assert np.all(np.abs(res.history[:n] - r) <= 1e-6 * r)
 
 
+def test_long_cycles_generic_basis_paths(hh):
+    """Restart 80 without preconditioner on a 2D grid: the fused apply and the
+    basis pass run their generic paths (more than 48 basis vectors, chunks of 8),
+    the last column of a full cycle gets its own projections, and the cycle-end
+    substitution runs its multi-wavefront form (restart > 32). Against the
+    oracle's GMRES with the same parameters; a 3-source batch of the same runs
+    the same kernels per source (no coarsest product) and equals its solves alone
+    to the bit."""
+    shape, h, freq = (17, 33), 10.0, 3.0
+    m = _model(shape, h, seed=4)
+    omega = 2 * np.pi * freq
+    P = _problem(hh, m, omega, 0.01, h)
+    f = np.zeros(shape, complex)
+    f[8, 16] = 1.0
+    kw = dict(tol=1e-6, restart=80, max_iters=1000, no_precond=True)
+    res = P.solve(_t(f), **kw)
+    ref = solver.solve(m, omega, 0.01, h, f, tol=1e-6, restart=80, maxiter=1000,
+                       precond="none")
+    print(f"restart 80 without preconditioner: {res.iterations} iterations "
+          f"(oracle {ref.iterations})")
+    assert res.iterations > 80                  # at least one full cycle
+    assert res.status == ref.status == 0
+    assert abs(res.iterations - ref.iterations) <= 1
+    assert res.true_rel_res <= 1e-6
+    n = min(80, len(res.history), len(ref.history))    # the first cycle step by step
+    r = np.asarray(ref.history[:n])
+    assert np.all(np.abs(res.history[:n] - r) <= 1e-6 * r)
+    u = _np(res.u)
+    assert np.linalg.norm(u - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+    F = _batch_sources(shape, [(8, 16), (0, 0), (16, 32)])
+    _assert_batch_equals_single(P, F, exact=True, **kw)
+
+
 def test_zero_source_and_budget(hh):
     w = wl.layered_1d(101, 5.0, 10.0, src=10)
     P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
