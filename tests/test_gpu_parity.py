@@ -285,6 +285,46 @@ def test_long_cycles_generic_basis_paths(hh):
     _assert_batch_equals_single(P, F, exact=True, **kw)
 
 
+def test_restart_at_its_maximum(hh):
+    """restart = 1024 (the largest accepted): the basis and least-squares storage
+    take their largest layout; unpreconditioned on a 2D grid the solve ends
+    inside the one cycle, as the oracle's full GMRES does."""
+    shape, h, freq = (17, 33), 10.0, 3.0
+    m = _model(shape, h, seed=4)
+    omega = 2 * np.pi * freq
+    P = _problem(hh, m, omega, 0.01, h)
+    f = np.zeros(shape, complex)
+    f[8, 16] = 1.0
+    res = P.solve(_t(f), tol=1e-6, restart=1024, max_iters=1000, no_precond=True)
+    ref = solver.solve(m, omega, 0.01, h, f, tol=1e-6, restart=1024, maxiter=1000,
+                       precond="none")
+    assert res.status == ref.status == 0
+    assert abs(res.iterations - ref.iterations) <= 1
+    u = _np(res.u)
+    assert np.linalg.norm(u - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+def test_batch_at_its_maximum_size(hh):
+    """HH_MAX_BATCH sources of one small problem in one batch (32 groups of the
+    batched coarsest product, the largest source grid dimension): every source
+    converges and sampled sources equal their solves alone to rounding."""
+    shape, h, freq = (9, 17), 10.0, 5.0
+    m = _model(shape, h, seed=6)
+    P = _problem(hh, m, 2 * np.pi * freq, 0.01, h)
+    assert P.num_levels >= 3
+    nrhs = hh.HH_MAX_BATCH
+    F = np.stack([wl.random_complex(shape, 1000 + i) for i in range(nrhs)])
+    kw = dict(tol=1e-8, restart=10)
+    res = P.solve_batch(_t(F), **kw)
+    assert res.overall == 0 and np.all(res.status == 0)
+    U = _np(res.u)
+    for i in (0, 1, 31, 32, 511, 640, 1022, 1023):
+        one = P.solve(_t(F[i]), **kw)
+        assert abs(int(res.iterations[i]) - one.iterations) <= 1, i
+        bound = BATCH_REL if res.iterations[i] == one.iterations else 1e-6
+        assert np.linalg.norm(U[i] - _np(one.u)) <= bound * np.linalg.norm(_np(one.u)), i
+
+
 def test_zero_source_and_budget(hh):
     w = wl.layered_1d(101, 5.0, 10.0, src=10)
     P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
