@@ -63,6 +63,10 @@ def parse():
                          "that the roofline times each kernel without contention; 2-4 streams "
                          "measured 2% more solves/s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-checks", action="store_true",
+                    help="skip the comparisons run after the timed region (error against the "
+                         "FP64 solve, plain FP64 throughput): for profiler runs whose kernel "
+                         "classes should hold the timed workload's launches only")
     ap.add_argument("--requests", type=int, default=200,
                     help="serving: requests in the Poisson stream (mean 200/s)")
     ap.add_argument("--serve-workers", type=int, default=4,
@@ -284,7 +288,7 @@ def main_batch(a, hh, torch, dev):
         kflops += n_k * 8.0 * float(nz_c * nx_c) ** 2 * len(sources)
         P.kernel_timer_start("none")
     precision = None
-    if mixed:
+    if mixed and not a.no_checks:
         # after the timed region: every source again with the complex128 cycle
         diffs = []
         for i, P in enumerate(probs):
@@ -303,7 +307,9 @@ def main_batch(a, hh, torch, dev):
     # frequency; problems set up outside the timing, as the batch's), after the
     # timed region
     sample = list(range(0, len(sources), max(1, len(sources) // 8)))[:8]
-    plain_probs = [hh.Problem(m, 2 * np.pi * fz, 0.01, 10.0) for fz in freqs]
+    if a.no_checks:
+        sample = []
+    plain_probs = [hh.Problem(m, 2 * np.pi * fz, 0.01, 10.0) for fz in freqs] if sample else []
     plain_ws = [Q.workspace(restart) for Q in plain_probs]
     plain_its = []
     torch.cuda.synchronize()
@@ -317,7 +323,8 @@ def main_batch(a, hh, torch, dev):
             plain_its.append(r1.iterations)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t_plain
-    plain = {"solves_per_s": len(plain_its) / t_plain,
+    plain = None if not plain_its else {
+             "solves_per_s": len(plain_its) / t_plain,
              "iterations_min_max": [min(plain_its), max(plain_its)],
              "sample": f"{len(sample)} sources per frequency, one hh_solve each, complex128 "
                        "preconditioner, default dense coarsest limit, same tol and restart"}
@@ -419,7 +426,7 @@ def main_serving(a, hh, torch, dev):
         key = f"{rq.slowness.shape[1]}x{rq.slowness.shape[0]}"
         by_grid.setdefault(key, []).append(r.latency * 1e3)
     precision = plain = None
-    if a.precision == "mixed":
+    if a.precision == "mixed" and not a.no_checks:
         # after the stream: every request again with the complex128 cycle
         import dataclasses
         diffs, worst = [], None
@@ -581,7 +588,7 @@ def main():
     launches, kms, kbytes = P.kernel_timer_read()
     P.kernel_timer_start("none")
     precision = None
-    if mixed:
+    if mixed and not a.no_checks:
         # after the timed region: the same solve with the complex128 cycle, the
         # FP64 reference the complex64 result is stated against
         u32 = u.clone()

@@ -32,7 +32,10 @@ CLASSES = {
     "vc_up": ("k_up<Fine5", ["vcycle_tiled.hip", "hh_internal.h"]),
     "vc_down_coarse": ("k_down<Coarse9", ["vcycle_tiled.hip", "hh_internal.h"]),
     "vc_up_coarse": ("k_up<Coarse9", ["vcycle_tiled.hip", "hh_internal.h"]),
-    "gemv": ("k_gemv_pred", ["coarsest.hip", "hh_internal.h"]),
+    # one launch of the class: the single-source product, or for a batch the
+    # matrix-core product and the sum of its k-split partials
+    "gemv": (("k_gemv_pred", "k_coarsest_mfma", "k_coarsest_sum"),
+             ["coarsest.hip", "hh_internal.h"]),
     "apply_dot": ("k_apply_dot", ["krylov.hip", "hh_internal.h", "givens.h"]),
     "axpy_dot": ("k_axpy_dcgs", ["krylov.hip", "hh_internal.h", "givens.h"]),
     "axpy_norm": ("k_dot_blocks", ["krylov.hip", "hh_internal.h", "givens.h"]),
@@ -96,18 +99,28 @@ def traffic(fetch_db: str, write_db: str, workload: str, cmd_f: str, cmd_w: str)
            "| kernel class | launches | fetch KiB/launch | write KiB/launch | scaled MB/launch |",
            "|---|---:|---:|---:|---:|"]
     table = {}
-    for cls, (prefix, _) in CLASSES.items():
-        fv = [v for k, vs in f.items() if k.startswith(prefix) for v in vs]
-        wv = [v for k, vs in w.items() if k.startswith(prefix) for v in vs]
-        if not fv or not wv:
+    for cls, (prefixes, _) in CLASSES.items():
+        if isinstance(prefixes, str):
+            prefixes = (prefixes,)
+        # a launch of the class dispatches each of its kernels once: sum their means
+        fk = wk = 0.0
+        n = 0
+        for prefix in prefixes:
+            fv = [v for k, vs in f.items() if k.startswith(prefix) for v in vs]
+            wv = [v for k, vs in w.items() if k.startswith(prefix) for v in vs]
+            if not fv or not wv:
+                continue
+            # launches of steps the device had already closed return at once: drop them
+            fv = [v for v in fv if v > 0.05 * max(fv)]
+            wv = [v for v in wv if v > 0.05 * max(wv)]
+            fk += statistics.mean(fv)
+            wk += statistics.mean(wv)
+            n = max(n, len(fv))
+        if n == 0:
             continue
-        # launches of steps the device had already closed return at once: drop them
-        fv = [v for v in fv if v > 0.05 * max(fv)]
-        wv = [v for v in wv if v > 0.05 * max(wv)]
-        fk, wk = statistics.mean(fv), statistics.mean(wv)
         b = (fk * ff + wk * fw) * 1024.0
         table[cls] = {"bytes_per_launch": b, "digest": source_digest(cls)}
-        out.append(f"| {cls} | {len(fv)} | {fk:.1f} | {wk:.1f} | {b / 1e6:.3f} |")
+        out.append(f"| {cls} | {n} | {fk:.1f} | {wk:.1f} | {b / 1e6:.3f} |")
     out += ["", "```json", json.dumps({workload: table}, indent=1), "```", ""]
     return "\n".join(out)
 
