@@ -13,6 +13,9 @@
 // The operator of a level is a policy: Fine5 (level 0: the matrix-free
 // 5-point stencil of M with absorbing rows, coefficients from m^2) or Coarse9
 // (Galerkin levels: 9 complex coefficient planes).
+// Every tile shape must give the same bits: the node arithmetic below uses
+// explicit fused multiply-adds, and nothing else in this file is contracted.
+#pragma clang fp contract(off)
 #include "hh_internal.h"
 
 namespace hh {
@@ -20,6 +23,39 @@ namespace hh {
 namespace {
 
 constexpr int NT = 128;    // threads per block
+
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// a b
+template <class C>
+__device__ __forceinline__ C xmul(C a, C b) {
+    C r;
+    r.x = fmad(a.x, b.x, -(a.y * b.y));
+    r.y = fmad(a.x, b.y, a.y * b.x);
+    return r;
+}
+// acc + a b
+template <class C>
+__device__ __forceinline__ C xmuladd(C acc, C a, C b) {
+    C r;
+    r.x = fmad(a.x, b.x, fmad(-a.y, b.y, acc.x));
+    r.y = fmad(a.x, b.y, fmad(a.y, b.x, acc.y));
+    return r;
+}
+// acc + s a (s real)
+template <class C, class T>
+__device__ __forceinline__ C xaxpy(C acc, C a, T s) {
+    C r;
+    r.x = fmad(a.x, s, acc.x);
+    r.y = fmad(a.y, s, acc.y);
+    return r;
+}
+// one Jacobi update of a node: x + (b - (A x)) w
+template <class C>
+__device__ __forceinline__ C jacobi(C x, C b, C ax, C w) {
+    return xmuladd(x, csub(b, ax), w);
+}
 
 // The flag may be cleared by a Givens step running as another workgroup of
 // the same launch (the fine down leg hosts it): read it atomically. Blocks
@@ -73,11 +109,13 @@ struct Fine5 {
         r.cx = r.cz = 0;
         return r;
     }
+    // (A x)_q from the node value c and the sums of its x and z neighbours
+    __device__ __forceinline__ static C apply5(const Row& r, C c, C sx, C sz) {
+        return xaxpy(xaxpy(xmul(r.diag, c), sx, -r.cx), sz, -r.cz);
+    }
     // (A x)_q from an LDS field s with row stride ld at local index i
     __device__ __forceinline__ C apply(const Row& r, const C* s, int i, int ld) const {
-        const C sx = cadd(s[i - 1], s[i + 1]);
-        const C sz = cadd(s[i - ld], s[i + ld]);
-        return csub(csub(cmul(r.diag, s[i]), cscale(sx, r.cx)), cscale(sz, r.cz));
+        return apply5(r, s[i], cadd(s[i - 1], s[i + 1]), cadd(s[i - ld], s[i + ld]));
     }
 };
 
@@ -127,7 +165,7 @@ struct Coarse9 {
     __device__ __forceinline__ C apply(const Row& r, const C* s, int i, int ld) const {
         C acc = czero<C>();
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc = cadd(acc, cmul(r.a[t], s[i + (t / 3 - 1) * ld + (t % 3 - 1)]));
+        for (int t = 0; t < 9; ++t) acc = xmuladd(acc, r.a[t], s[i + (t / 3 - 1) * ld + (t % 3 - 1)]);
         return acc;
     }
 };
@@ -208,7 +246,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
         sb[d] = bq;
         sw[d] = wq;
         srow[d] = r;
-        s1[d] = cmul(bq, wq);
+        s1[d] = xmul(bq, wq);
     }
     __syncthreads();
     // phase 2: x2 on the x1 region shrunk by one node (stored at the same local index)
@@ -224,7 +262,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
             if (in_grid(qz, qx, nz, nx)) {
                 const typename OP::Row& r = srow[i];
                 const C ax = A.apply(r, s1, i, wx);
-                x2 = cadd(s1[i], cmul(csub(sb[i], ax), sw[i]));
+                x2 = jacobi(s1[i], sb[i], ax, sw[i]);
                 if (qz >= olz && qz <= ohz && qx >= olx && qx <= ohx)
                     x2out[(int64_t)qz * nx + qx] = x2;
             }
@@ -259,7 +297,7 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
             for (int dx = -1; dx <= 1; ++dx) {
                 if ((dz != 0 && !hz) || (dx != 0 && !hx)) continue;
                 const T w = (dz == 0 ? (T)1 : (T)0.5) * (dx == 0 ? (T)1 : (T)0.5);
-                acc = cadd(acc, cscale(s1[(lz + dz) * wx + (lx + dx)], w));
+                acc = xaxpy(acc, s1[(lz + dz) * wx + (lx + dx)], w);
             }
         }
         bc[cg.at(Iz, Ix)] = cscale(acc, (T)rscale);
@@ -351,8 +389,8 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
         T wz0, wz1, wx0, wx1;
         interp2(qz, hz, z0, z1, wz0, wz1);
         interp2(qx, hx, x0, x1, wx0, wx1);
-        const C pe = cadd(cadd(cscale(le[k][0], wz0 * wx0), cscale(le[k][1], wz0 * wx1)),
-                          cadd(cscale(le[k][2], wz1 * wx0), cscale(le[k][3], wz1 * wx1)));
+        const C pe = xaxpy(xaxpy(xaxpy(cscale(le[k][0], wz0 * wx0), le[k][1], wz0 * wx1),
+                                 le[k][2], wz1 * wx0), le[k][3], wz1 * wx1);
         sp[i < WX * WZ ? i : TRASH] = ok ? cadd(lx[k], pe) : czero<C>();
     }
 #pragma unroll
@@ -378,7 +416,7 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
             if (in_grid(qz, qx, nz, nx)) {
                 const typename OP::Row& r = srow[j];
                 const C ax = A.apply(r, sp, i, WX);
-                v = cadd(sp[i], cmul(csub(sbb[j], ax), sw[j]));
+                v = jacobi(sp[i], sbb[j], ax, sw[j]);
             }
             s3[i] = v;
         }
@@ -397,7 +435,7 @@ __global__ void __launch_bounds__(NT) k_up(OP A, int hz, int hx,
             if (in_grid(qz, qx, nz, nx)) {
                 const typename OP::Row& r = srow[j];
                 const C ax = A.apply(r, s3, i, WX);
-                out[(int64_t)qz * nx + qx] = cadd(s3[i], cmul(csub(sbb[j], ax), sw[j]));
+                out[(int64_t)qz * nx + qx] = jacobi(s3[i], sbb[j], ax, sw[j]);
             }
         }
     }
