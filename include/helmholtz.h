@@ -121,13 +121,17 @@ int hh_set_max_coarse(hh_problem p, int max_coarse);
  * and an up leg (prolongation, two post-smoothing sweeps; tiles of level-l
  * nodes), one kernel each. Every shape computes every node with the same
  * arithmetic, so the choice changes the speed of a solve, never its bits.
- * HH_TILE_DEFAULT (-1) is a fixed rule: down 4 x 4, up 8 x 4 (32 x 8 on a fine
- * grid of at least 200000 nodes). A rebuilt hierarchy starts from the default.
+ * HH_TILE_DOWN_ZMARCH is not a tile: on the fine level (when both axes halve)
+ * each block marches along z over a strip of columns; on other levels it
+ * means 4 x 4. HH_TILE_DEFAULT (-1) is a fixed rule: down 4 x 4 (z-marching on
+ * a fine grid of at least 200000 nodes), up 8 x 4 (32 x 8 on such a fine
+ * grid). A rebuilt hierarchy starts from the default.
  */
 #define HH_TILE_DEFAULT (-1)
 #define HH_TILE_DOWN_4X4 0
 #define HH_TILE_DOWN_8X4 1
-#define HH_TILE_DOWN_COUNT 2
+#define HH_TILE_DOWN_ZMARCH 2
+#define HH_TILE_DOWN_COUNT 3
 #define HH_TILE_UP_8X4 0
 #define HH_TILE_UP_16X8 1
 #define HH_TILE_UP_32X8 2

@@ -305,6 +305,118 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
 }
 
 // ---------------------------------------------------------------------------
+// down leg of the fine 5-point level marching along z (both axes halved): one
+// wavefront per block, its 64 lanes the fine columns x0 - 3 .. x0 + 60 of a
+// strip whose 58 middle columns it owns, over the 8 rows z0 .. z0 + 7 it owns
+// plus 3 rows above and 2 below. Every load of the block is issued first;
+// x-neighbours come from the adjacent lanes (shuffles), z-neighbours from the
+// lane's own registers, so there is no LDS and no barrier. Each node is
+// computed with the same operations in the same order as in k_down: the two
+// give the same bits.
+constexpr int ZM_COLS = 58, ZM_ROWS = 8;
+
+template <class T>
+__device__ __forceinline__ typename Cx<T>::type lane_c(typename Cx<T>::type v, int src) {
+    typename Cx<T>::type r;
+    r.x = __shfl(v.x, src, 64);
+    r.y = __shfl(v.y, src, 64);
+    return r;
+}
+
+template <class T, class SC>
+__global__ void __launch_bounds__(64) k_down_zmarch(FineOpT<T> op, const SC* __restrict__ src,
+                                                    typename Cx<T>::type* __restrict__ x2out,
+                                                    CGrid cg, typename Cx<T>::type* __restrict__ bc,
+                                                    double rscale, const int* __restrict__ active,
+                                                    int nstrips, int64_t bs) {
+    typedef typename Cx<T>::type C;
+    typedef Fine5<T> OP;
+    constexpr int NR = ZM_ROWS + 5;                  // rows z0 - 3 .. z0 + ZM_ROWS + 1
+    const int rb = blockIdx.y;
+    active = rhs_at(active, rb, bs);
+    if (inactive(active)) return;
+    src = rhs_nn(src, rb, bs);
+    x2out = rhs_nn(x2out, rb, bs);
+    bc = rhs_nn(bc, rb, bs);
+    const int lane = threadIdx.x;
+    const int x0 = (blockIdx.x % nstrips) * ZM_COLS, z0 = (blockIdx.x / nstrips) * ZM_ROWS;
+    const int x = x0 - 3 + lane;
+    const int nz = op.nz, nx = op.nx;
+    OP A;
+    A.op = op;
+    SC lb[NR];
+    typename OP::Raw lr[NR];
+    C lw[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int z = z0 - 3 + k;
+        const bool ok = in_grid(z, x, nz, nx);
+        const int64_t q = ok ? (int64_t)z * nx + x : 0;
+        lb[k] = src[q];
+        lr[k] = A.load_raw(q);
+        lw[k] = A.wd_at(q);
+    }
+    const int lw1 = lane > 0 ? lane - 1 : 0, le1 = lane < 63 ? lane + 1 : 63;
+    C b[NR], w[NR], x1[NR], x2[NR], r[NR];
+    typename OP::Row rw[NR];
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        const int z = z0 - 3 + k;
+        const bool ok = in_grid(z, x, nz, nx);
+        b[k] = ok ? cconv<C>(lb[k]) : czero<C>();
+        w[k] = ok ? lw[k] : czero<C>();
+        rw[k] = ok ? A.make_row(lr[k], z, x) : OP::zero_row();
+        x1[k] = xmul(b[k], w[k]);
+    }
+    // x2 on rows 1 .. NR - 2 (lanes 1 .. 62 hold valid values)
+#pragma unroll
+    for (int k = 1; k < NR - 1; ++k) {
+        const int z = z0 - 3 + k;
+        const bool ok = in_grid(z, x, nz, nx);
+        const C sx = cadd(lane_c<T>(x1[k], lw1), lane_c<T>(x1[k], le1));
+        const C ax = OP::apply5(rw[k], x1[k], sx, cadd(x1[k - 1], x1[k + 1]));
+        x2[k] = ok ? jacobi(x1[k], b[k], ax, w[k]) : czero<C>();
+        if (ok && k >= 3 && k < 3 + ZM_ROWS && lane >= 3 && lane < 3 + ZM_COLS)
+            x2out[(int64_t)z * nx + x] = x2[k];
+    }
+    // residual on rows 2 .. NR - 3 (lanes 2 .. 61)
+#pragma unroll
+    for (int k = 2; k < NR - 2; ++k) {
+        const int z = z0 - 3 + k;
+        const bool ok = in_grid(z, x, nz, nx);
+        const C sx = cadd(lane_c<T>(x2[k], lw1), lane_c<T>(x2[k], le1));
+        r[k] = ok ? csub(b[k], OP::apply5(rw[k], x2[k], sx, cadd(x2[k - 1], x2[k + 1])))
+                  : czero<C>();
+    }
+    // b_c = R r: coarse row z0/2 + i at fine row k = 3 + 2i, coarse column at lane 3 + 2j
+    const bool own = lane >= 3 && lane < 3 + ZM_COLS && ((lane - 3) & 1) == 0;
+#pragma unroll
+    for (int i = 0; i < ZM_ROWS / 2; ++i) {
+        const int k = 3 + 2 * i;
+        const int I = (z0 >> 1) + i, J = (x0 >> 1) + ((lane - 3) >> 1);
+        C rv[3][3];                                       // [dz + 1][dx + 1]
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            rv[d][0] = lane_c<T>(r[k - 1 + d], lw1);
+            rv[d][1] = r[k - 1 + d];
+            rv[d][2] = lane_c<T>(r[k - 1 + d], le1);
+        }
+        if (own && I < cg.nz && J < cg.nx) {
+            C acc = czero<C>();
+#pragma unroll
+            for (int dz = -1; dz <= 1; ++dz) {
+#pragma unroll
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const T wv = (dz == 0 ? (T)1 : (T)0.5) * (dx == 0 ? (T)1 : (T)0.5);
+                    acc = xaxpy(acc, rv[dz + 1][dx + 1], wv);
+                }
+            }
+            bc[cg.at(I, J)] = cscale(acc, (T)rscale);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // up leg. A block owns a TX x TZ tile of fine nodes: x' on the tile plus two
 // nodes, x3 on the tile plus one, x4 on the tile.
 // ---------------------------------------------------------------------------
@@ -465,15 +577,30 @@ hipError_t down_launch(const OP& A, const SC* src, typename OP::C* x2, int hz, i
 }
 
 // Tile shapes of the down leg (coarse nodes): 0 = 4 x 4 (an 8 x 8 fine block
-// and its halo), 1 = 8 x 4. The default (tile < 0) is 4 x 4 on every level:
-// the legs are latency-bound up to a few 100k nodes, where more blocks in
-// flight beat the extra halo work, and past that the down leg still gains
-// (measured on the 401 x 201 and 1201 x 401 hierarchies). Every shape computes
-// every node with the same arithmetic: the choice changes speed, not results.
+// and its halo), 1 = 8 x 4, 2 = the fine level marching along z (k_down_zmarch;
+// other levels, or a fine level not halved in both axes, take 4 x 4). The
+// default (tile < 0): 4 x 4 tiles, which beat larger ones up to a few 100k
+// nodes (more blocks in flight against the latency, measured on the 401 x 201
+// and 1201 x 401 hierarchies), except on 5-point fine grids of at least
+// kBigLevel nodes, where marching along z is faster (1201 x 401: 16.0 -> 13.1 us
+// in complex128, 11.4 -> 8.3 us in complex64; slower on 401 x 201). Every shape
+// computes every node with the same arithmetic: the choice changes speed, not
+// results.
 template <class OP, class SC>
 hipError_t down_dispatch(const OP& A, const SC* src, typename OP::C* x2, int hz, int hx, CGrid cg,
                          typename OP::C* bc, const int* active, hipStream_t s,
                          const Batch& bt, int tile) {
+    if constexpr (sizeof(typename OP::Row) <= 32) {      // the fine 5-point level
+        if (tile < 0) tile = big_tiles(A) ? 2 : 0;
+        if (tile == 2 && hz && hx) {
+            const int nstrips = (A.nx() + ZM_COLS - 1) / ZM_COLS;
+            const int nchunks = (A.nz() + ZM_ROWS - 1) / ZM_ROWS;
+            HH_LAUNCH((k_down_zmarch<typename OP::real, SC>), dim3(nstrips * nchunks, bt.n),
+                      dim3(64), 0, s, A.op, src, x2, cg, bc, inv2dc(hz, hx), active, nstrips,
+                      bt.bs);
+            return hipGetLastError();
+        }
+    }
     if (tile == 1) return down_launch<OP, SC, 8, 4>(A, src, x2, hz, hx, cg, bc, active, s, bt);
     return down_launch<OP, SC, 4, 4>(A, src, x2, hz, hx, cg, bc, active, s, bt);
 }

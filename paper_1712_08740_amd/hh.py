@@ -36,10 +36,11 @@ HH_MAX_COARSE_LIMIT = 32768
 HH_MAX_1D = 1024
 HH_MAX_BATCH = 1024
 HH_TILE_DEFAULT = -1
-HH_TILE_DOWN_COUNT = 2
+HH_TILE_DOWN_COUNT = 3
 HH_TILE_UP_COUNT = 3
-# tile shapes by id: down legs in coarse nodes, up legs in level nodes (x by z)
-TILE_DOWN_SHAPES = ("4x4", "8x4")
+# tile shapes by id: down legs in coarse nodes, up legs in level nodes (x by z);
+# "zmarch": the fine level's down leg marching along z (4x4 on other levels)
+TILE_DOWN_SHAPES = ("4x4", "8x4", "zmarch")
 TILE_UP_SHAPES = ("8x4", "16x8", "32x8")
 HH_KERNEL_NONE = 0
 HH_KERNEL_APPLY_DOT = 1
