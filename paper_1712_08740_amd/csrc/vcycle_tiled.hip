@@ -313,8 +313,6 @@ __global__ void __launch_bounds__(NT) k_down(OP A, const SC* __restrict__ src,
 // lane's own registers, so there is no LDS and no barrier. Each node is
 // computed with the same operations in the same order as in k_down: the two
 // give the same bits.
-// (8 owned rows: 6 ran the 1201 x 401 leg 5% faster but a 32-source batch's 10%
-// slower, 12 the reverse)
 constexpr int ZM_COLS = 58, ZM_ROWS = 8;
 
 template <class T>
