@@ -829,6 +829,33 @@ def test_every_tile_shape_gives_the_same_bits(hh):
             P.set_tiles(l, -1, -1)
 
 
+@pytest.mark.parametrize("shape", [(9, 9), (5, 129), (13, 21), (33, 65), (65, 117)], ids=str)
+def test_marching_down_leg_gives_the_tiled_bits(hh, shape):
+    """The fine level's down leg marching along z (58-column strips, 8-row
+    chunks) against the 4 x 4 tiles on grids smaller than one strip or chunk
+    and ragged against both: the same bits, complex128 and complex64, and for a
+    batch of sources."""
+    h, freq = 10.0, 6.0
+    m = _model(shape, h, seed=9)
+    P = _problem(hh, m, 2 * np.pi * freq, 0.01, h)
+    if P.num_levels < 2:
+        pytest.skip("single-level hierarchy")
+    v = _t(wl.random_complex(shape, 31))
+    for f32 in (False, True):
+        P.set_tiles(0, 0, -1)                       # 4 x 4 tiles
+        z0 = _np(P.apply_precond(v, f32=f32))
+        P.set_tiles(0, 2, -1)                       # marching along z
+        assert np.array_equal(_np(P.apply_precond(v, f32=f32)), z0), f32
+    F = _t(np.stack([wl.random_complex(shape, 40 + i) for i in range(3)]))
+    P.set_tiles(0, 0, -1)
+    a = P.solve_batch(F, tol=1e-8, restart=10, precond_f32=True)
+    ua = _np(a.u).copy()
+    P.set_tiles(0, 2, -1)
+    b = P.solve_batch(F, tol=1e-8, restart=10, precond_f32=True)
+    assert np.array_equal(a.iterations, b.iterations)
+    assert np.array_equal(_np(b.u), ua)
+
+
 def test_autotune_keeps_results_and_caches_choices(hh, tmp_path):
     """The tuner picks a valid shape per leg (or keeps the default); a solve with the tuned shapes
     gives the bits of the default ones; a second handle on the same hierarchy
