@@ -11,6 +11,11 @@
         roofline ``traffic`` field (with a digest of the kernel sources: a
         changed source makes the figure stale, and bench reports null).
 
+    python profile_summary.py mfma DB KERNEL SIMDS COMMAND
+        matrix-core counters of one kernel (a ``--pmc`` run with
+        SQ_INSTS_VALU_MFMA_MOPS_F32, SQ_INSTS_VALU_MFMA_F32,
+        SQ_VALU_MFMA_BUSY_CYCLES, SQ_BUSY_CYCLES, GRBM_GUI_ACTIVE)
+
 Only reads the databases; runs nothing.
 """
 from __future__ import annotations
@@ -125,10 +130,42 @@ def traffic(fetch_db: str, write_db: str, workload: str, cmd_f: str, cmd_w: str)
     return "\n".join(out)
 
 
+def mfma(db: str, kernel: str, simds: int, cmd: str) -> str:
+    """Matrix-core counters of one kernel (mean per dispatch): the flops its MFMA
+    ops stand for (SQ_INSTS_VALU_MFMA_MOPS_F32 counts units of 512) and the share
+    of SIMD cycles the matrix cores were busy (SQ_VALU_MFMA_BUSY_CYCLES summed
+    over the SIMDs, GRBM_GUI_ACTIVE summed over the 8 XCDs)."""
+    con = sqlite3.connect(db)
+    d = collections.defaultdict(list)
+    for name, c, v in con.execute("select kernel_name, counter_name, value "
+                                  "from counters_collection"):
+        if _short(name).startswith(kernel):
+            d[c].append(v)
+    m = {c: statistics.mean(v) for c, v in d.items()}
+    n = len(next(iter(d.values())))
+    gflop = m["SQ_INSTS_VALU_MFMA_MOPS_F32"] * 512 / 1e9
+    cycles = m["GRBM_GUI_ACTIVE"] / 8
+    busy = m["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * cycles)
+    out = [f"# Matrix-core counters of {kernel}", "", "Command (on the MI355X, from /tmp with "
+           "TMPDIR=/tmp):", "", f"    {cmd}", "",
+           f"Mean over {n} dispatches.", "",
+           "| counter | mean per dispatch |", "|---|---:|"]
+    for c in sorted(m):
+        out.append(f"| {c} | {m[c]:.0f} |")
+    out += ["", f"MFMA work: {gflop:.2f} GFLOP per dispatch (MOPS x 512); "
+            f"{m['SQ_INSTS_VALU_MFMA_F32']:.0f} MFMA instructions x 2048 flops = "
+            f"{m['SQ_INSTS_VALU_MFMA_F32'] * 2048 / 1e9:.2f} GFLOP.",
+            f"Duration: {cycles:.0f} cycles per XCD = {cycles / 2.4e3:.0f} us at 2.4 GHz.",
+            f"Matrix cores busy: {100 * busy:.1f}% of the SIMD cycles ({simds} SIMDs).", ""]
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "kernels":
         sys.stdout.write(kernels(*sys.argv[2:5]))
     elif sys.argv[1] == "traffic":
         sys.stdout.write(traffic(*sys.argv[2:7]))
+    elif sys.argv[1] == "mfma":
+        sys.stdout.write(mfma(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5]))
     else:
         raise SystemExit(__doc__)
