@@ -601,6 +601,23 @@ def main():
             "reference": "hh_solve with the complex128 preconditioner, same tol and restart "
                          "(the parity tests pin it to the oracle's LU solution within 1e-6)"}
 
+    comparison = None
+    if not a.no_checks:
+        # after the timed region: the paper's comparison, GMRES on the Helmholtz
+        # operator itself (no preconditioner), same restart, capped iterations
+        cap = 4000
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        rn = P.solve(f, tol=w.tol, restart=w.restart, max_iters=cap, workspace=ws,
+                     no_precond=True, hist_cap=0)
+        torch.cuda.synchronize()
+        comparison = {
+            "unpreconditioned_gmres": {
+                "iterations": int(rn.iterations), "status": int(rn.status),
+                "converged": rn.status == hh.HH_OK, "true_rel_res": float(rn.true_rel_res),
+                "ms": 1e3 * (time.perf_counter() - t1), "max_iters": cap},
+            "preconditioned_iterations": int(np.median(its))}
+
     avg_us = 1e3 * kms / max(launches, 1)
     achieved = (kbytes / (kms * 1e-3)) / 1e9 if kms > 0 else 0.0
     # whole-solve effective bandwidth from the byte model of all kernels is not
@@ -633,6 +650,7 @@ def main():
             "true_rel_res_max": float(max(res)),
             "setup_ms": 1e3 * t_setup,
             "precision_check": precision,
+            "precond_comparison": comparison,
             "tiles_down_up": _tile_names(hh, tiles, a.tiles),
             "autotune_ms": 1e3 * t_tune,
         },
