@@ -291,7 +291,7 @@ Layout layout(const hh_problem_s* p, int m, size_t es = sizeof(cplx)) {
             }
         }
     }
-    L.nbA = apply_blocks(op_H(p));
+    L.nbA = apply_blocks(op_H(p), 1);   // a batch resets it (solve_impl)
     L.nbN = node_blocks(p->N);
     L.nbR = residual_blocks(op_H(p));
     L.nbmax = std::max(std::max(L.nbA, L.nbN), L.nbR);
@@ -1107,7 +1107,10 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
     const int m = restart;
     const bool no_prec = (flags & HH_NO_PRECOND) != 0;
     const bool f32 = (flags & HH_PRECOND_F32) != 0;
-    const Layout L = layout(p, m, f32 ? sizeof(cplxf) : sizeof(cplx));
+    Layout L = layout(p, m, f32 ? sizeof(cplxf) : sizeof(cplx));
+    // blocks of the fused apply for this many sources: never more than
+    // node_blocks(N), which sized the partial sums
+    L.nbA = apply_blocks(op_H(p), nrhs);
     if (workspace_bytes < (size_t)nrhs * L.total) return fail(HH_EINVAL, "workspace too small");
     CHK(ensure_host_buffers(p, max_iters, nrhs));
     if (nrhs > 1 && p->ndim == 2 && p->levels.size() >= 2) {

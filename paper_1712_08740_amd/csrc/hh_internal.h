@@ -297,14 +297,14 @@ struct HostRecord {
 
 // ---- fused, predicated Arnoldi kernels (krylov.hip) -----------------------
 // w = H z and, with u = V_{k-1}, partial[i*nb + blk] = block sums of conj(V_i) u
-// and partial[(k+i)*nb + blk] = block sums of conj(V_i) w, i < k (nb = apply_blocks)
+// and partial[(k+i)*nb + blk] = block sums of conj(V_i) w, i < k (nb = apply_blocks(op, nrhs))
 hipError_t launch_apply_dot(const FineOp& op, const cplx* z, cplx* w, const cplx* V, int k,
                             cplx* partial, const int* active, hipStream_t s,
                             const Batch& bt = Batch());
 hipError_t launch_apply_dot(const FineOp& op, const cplxf* z, cplx* w, const cplx* V, int k,
                             cplx* partial, const int* active, hipStream_t s,
                             const Batch& bt = Batch());
-int apply_blocks(const FineOp& op);
+int apply_blocks(const FineOp& op, int nrhs);
 // partials of launch_residual_norm (one per 64 x 4 tile in 2D)
 int residual_blocks(const FineOp& op);
 int node_blocks(int64_t n);

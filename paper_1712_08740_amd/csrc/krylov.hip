@@ -173,10 +173,11 @@ __device__ __forceinline__ cplx wave_sum16(cplx (&v)[16], int lane) {
 // products, then the sums are reduced over each wavefront (wave_sum16) and
 // over the four wavefronts in LDS. For k <= KMAX the basis values of a node
 // are loaded up front (all in flight together); beyond, in chunks of 8.
-// Two nodes per thread halve the reductions where the grid is small enough
-// for them to matter; on large grids one node per thread keeps two
-// wavefronts per SIMD in flight (ad_npt).
-inline int ad_npt(int64_t n) { return n < 262144 ? 2 : 1; }
+// Two nodes per thread halve the reductions where the launch is small enough
+// for them to matter; on large launches one node per thread keeps two
+// wavefronts per SIMD in flight (ad_npt, of the nodes over all right-hand
+// sides: a batch of sources on a small grid is a large launch).
+inline int ad_npt(int64_t nodes) { return nodes < 262144 ? 2 : 1; }
 
 template <int NDIM, int KMAX, class ZC, int AD_NPT>
 __global__ void __launch_bounds__(256) k_apply_dot(FineOp op, const ZC* __restrict__ z,
@@ -819,8 +820,8 @@ static void apply_dot_dispatch(dim3 g, dim3 b, const FineOp& op, const ZC* z, cp
 template <class ZC>
 hipError_t apply_dot(const FineOp& op, const ZC* z, cplx* w, const cplx* V, int k, cplx* partial,
                      const int* active, hipStream_t s, const Batch& bt) {
-    const dim3 g(apply_blocks(op), bt.n), b(256);
-    const bool two = ad_npt((int64_t)op.nz * op.nx) == 2;
+    const dim3 g(apply_blocks(op, bt.n), bt.n), b(256);
+    const bool two = ad_npt((int64_t)op.nz * op.nx * bt.n) == 2;
     if (op.ndim == 2 && two)
         apply_dot_dispatch<2, ZC, 2>(g, b, op, z, w, V, k, partial, active, bt.bs, s);
     else if (op.ndim == 2)
@@ -842,9 +843,9 @@ hipError_t launch_apply_dot(const FineOp& op, const cplxf* z, cplx* w, const cpl
 int residual_blocks(const FineOp& op) {
     return op.ndim == 2 ? ((op.nx + 63) / 64) * ((op.nz + 3) / 4) : (op.nx + 255) / 256;
 }
-int apply_blocks(const FineOp& op) {
+int apply_blocks(const FineOp& op, int nrhs) {
     const int64_t n = (int64_t)op.nz * op.nx;
-    const int npt = ad_npt(n);
+    const int npt = ad_npt(n * nrhs);
     return (int)((n + 256 * npt - 1) / (256 * npt));
 }
 int node_blocks(int64_t n) { return (int)((n + 255) / 256); }

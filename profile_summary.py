@@ -33,7 +33,9 @@ CSRC = os.path.join(ROOT, "paper_1712_08740_amd", "csrc")
 
 # kernel class of the solve's kernel timer -> (kernel-name prefix, source files)
 CLASSES = {
-    "vc_down": ("k_down<Fine5", ["vcycle_tiled.hip", "hh_internal.h"]),
+    # the fine down leg is a tiled kernel or, on large grids, the marching one:
+    # a launch is either (one component, pooled over its alternatives)
+    "vc_down": ((("k_down<Fine5", "k_down_zmarch"),), ["vcycle_tiled.hip", "hh_internal.h"]),
     "vc_up": ("k_up<Fine5", ["vcycle_tiled.hip", "hh_internal.h"]),
     "vc_down_coarse": ("k_down<Coarse9", ["vcycle_tiled.hip", "hh_internal.h"]),
     "vc_up_coarse": ("k_up<Coarse9", ["vcycle_tiled.hip", "hh_internal.h"]),
@@ -110,7 +112,7 @@ def traffic(fetch_db: str, write_db: str, workload: str, cmd_f: str, cmd_w: str)
         # a launch of the class dispatches each of its kernels once: sum their means
         fk = wk = 0.0
         n = 0
-        for prefix in prefixes:
+        for prefix in prefixes:     # a str, or a tuple of alternative kernels
             fv = [v for k, vs in f.items() if k.startswith(prefix) for v in vs]
             wv = [v for k, vs in w.items() if k.startswith(prefix) for v in vs]
             if not fv or not wv:
