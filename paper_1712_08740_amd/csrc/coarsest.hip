@@ -213,9 +213,9 @@ __global__ void __launch_bounds__(256) k_coarsest_mfma(int n, const typename Cx<
             }
         }
     };
-    // one register buffer: the waves sharing a SIMD (3 in complex64, 5 in
+    // one register buffer: the waves sharing a SIMD (5 in complex64, 3 in
     // complex128) hide each other's load latency (measured faster than a
-    // second buffer, which costs occupancy)
+    // second buffer, or than 64 rows per wave, both of which cost occupancy)
     const int nfull = n / MF_KC;              // steps that lie inside the matrix
     const int kf = max(kc0, min(kc1, nfull)); // this range's unmasked steps: [kc0, kf)
     C a0[2][4], x0[2][4];
