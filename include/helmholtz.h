@@ -57,7 +57,7 @@ enum hh_status {
     HH_ENOMEM        = -2,  /* device allocation failed                           */
     HH_EDEVICE       = -3,  /* a HIP runtime call failed                          */
     HH_ENUMERIC      = -4,  /* NaN/Inf in a residual norm or breakdown quantity   */
-    HH_EUNSUPPORTED  = -5   /* valid input outside what this build implements     */
+    HH_EUNSUPPORTED  = -5   /* valid input outside what the library implements   */
 };
 
 /* hh_solve flags */
