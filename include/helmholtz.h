@@ -70,6 +70,13 @@ enum hh_status {
                                residual recomputation, solution update) stays complex128.
                                Flexible GMRES takes any fixed preconditioner, so the
                                tolerance is met in full precision. Excludes HH_NO_PRECOND. */
+#define HH_INITIAL_GUESS 4u /* u_dev holds the initial guess x0 on entry (default x0 = 0).
+                               GMRES restarts from the iterate alone, so a solve that
+                               stopped with HH_NOT_CONVERGED resumes from its returned u:
+                               stopped at the end of a cycle (max_iters a multiple of
+                               restart), the resumed solve gives the same bits as one
+                               uninterrupted solve. hist[0] is then ||W f - H x0|| / ||W f||;
+                               W f = 0 still returns u = 0. */
 
 /* Default largest coarsest-grid size (unknowns) inverted densely, and the
  * largest that hh_set_max_coarse accepts (a 32768^2 complex128 inverse is 17 GB). */
@@ -186,15 +193,18 @@ int hh_footprint_bytes(int ndim, const int64_t* shape, double omega, double max_
 int hh_workspace_bytes(hh_problem p, int restart, size_t* bytes);
 
 /*
- * hh_solve -- right-preconditioned FGMRES(restart) on H u = W f, x0 = 0.
+ * hh_solve -- right-preconditioned FGMRES(restart) on H u = W f, x0 = 0 (or u_dev on
+ *   entry with HH_INITIAL_GUESS).
  *   f_dev     : complex128 source, grid-shaped (not modified).
  *   tol       : relative tolerance in (0, 1) on ||W f - H u||_2 / ||W f||_2.
  *   restart   : Krylov basis length per cycle, 1..1024.
  *   max_iters : budget of preconditioned operator applications, >= 1.
- *   flags     : 0, HH_NO_PRECOND or HH_PRECOND_F32.
+ *   flags     : 0, HH_NO_PRECOND or HH_PRECOND_F32, each with or without
+ *               HH_INITIAL_GUESS.
  *   workspace_dev / workspace_bytes : caller-owned device scratch of at least
  *               hh_workspace_bytes(p, restart) bytes; contents are overwritten.
- *   u_dev     : complex128 output wavefield, grid-shaped (caller-owned).
+ *   u_dev     : complex128 output wavefield, grid-shaped (caller-owned); the
+ *               initial guess on entry with HH_INITIAL_GUESS.
  *   iterations: number of Arnoldi steps taken (may be NULL).
  *   true_rel_res : recomputed ||W f - H u|| / ||W f|| at exit (may be NULL).
  *   hist_host : host array; hist[0] = 1, hist[k] = Givens residual estimate
@@ -224,7 +234,8 @@ int hh_workspace_bytes_batch(hh_problem p, int restart, int nrhs, size_t* bytes)
  * has stopped). Each result is the one hh_solve gives for that source alone.
  *   nrhs      : 1..HH_MAX_BATCH.
  *   f_dev     : complex128 sources, nrhs grids back to back (not modified).
- *   u_dev     : complex128 wavefields, nrhs grids back to back (caller-owned).
+ *   u_dev     : complex128 wavefields, nrhs grids back to back (caller-owned;
+ *               the initial guesses on entry with HH_INITIAL_GUESS).
  *   workspace : at least hh_workspace_bytes_batch(p, restart, nrhs) bytes.
  *   iterations, true_rel_res, status : host arrays of nrhs entries (may be NULL);
  *               status[i] is HH_OK, HH_NOT_CONVERGED or HH_ENUMERIC for source i.

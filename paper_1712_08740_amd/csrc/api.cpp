@@ -863,7 +863,8 @@ int hh_footprint_bytes(int ndim, const int64_t* shape, double omega, double max_
         return fail(HH_EINVAL, "max_coarse must be in [1, HH_MAX_COARSE_LIMIT]");
     if (restart < 1 || restart > kMaxRestart) return fail(HH_EINVAL, "restart must be in [1, 1024]");
     if (nrhs < 1 || nrhs > HH_MAX_BATCH) return fail(HH_EINVAL, "nrhs must be in [1, HH_MAX_BATCH]");
-    if (flags & ~(HH_NO_PRECOND | HH_PRECOND_F32)) return fail(HH_EINVAL, "unknown flag");
+    if (flags & ~(HH_NO_PRECOND | HH_PRECOND_F32 | HH_INITIAL_GUESS))
+        return fail(HH_EINVAL, "unknown flag");
     hh_problem_s q;                 // host-side plan only: nothing is allocated
     q.ndim = ndim;
     q.nz = ndim == 2 ? (int)shape[0] : 1;
@@ -1107,6 +1108,7 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
     const int m = restart;
     const bool no_prec = (flags & HH_NO_PRECOND) != 0;
     const bool f32 = (flags & HH_PRECOND_F32) != 0;
+    const bool warm = (flags & HH_INITIAL_GUESS) != 0;
     Layout L = layout(p, m, f32 ? sizeof(cplxf) : sizeof(cplx));
     // blocks of the fused apply for this many sources: never more than
     // node_blocks(N), which sized the partial sums
@@ -1151,12 +1153,12 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
     std::memset(p->rec, 0, (size_t)nrhs * sizeof(HostRecord));
     p->kt.pending.clear();
 
-    // prologue: b = W f, ||b||, u = 0
+    // prologue: b = W f, ||b||, u = 0 (or the caller's initial guess)
     HIPCHK(launch_weight_rhs(H, f, b, s, bt));
     HIPCHK(launch_dot_blocks(b, N, 1, b, partial, s, bt));
     HIPCHK(launch_solve_init(st, partial, L.nbN, m, max_iters, tol, drec, dhist, p->hist_stride,
-                             s, bt));
-    HIPCHK(hipMemsetAsync(u, 0, (size_t)nrhs * N * sizeof(cplx), s));
+                             warm ? u : nullptr, N, s, bt));
+    if (!warm) HIPCHK(hipMemsetAsync(u, 0, (size_t)nrhs * N * sizeof(cplx), s));
 
     // Arnoldi with delayed reorthogonalisation: step j preconditions and applies
     // H to u_j = V_j (projected once, not yet normalised), reduces the
@@ -1175,7 +1177,8 @@ int solve_impl(hh_problem_s* p, int nrhs, const cplx* f, double tol, int restart
     for (int cycle = 1;; ++cycle) {
         p->kt.cycle = cycle;
         HIPCHK(launch_residual_norm(H, b, u, V, partial, &st->done, s, bt));   // u_0 = r
-        HIPCHK(launch_cycle_start(st, partial, L.nbR, g, drec, s, bt));
+        HIPCHK(launch_cycle_start(st, partial, L.nbR, g, drec, dhist, p->hist_stride, warm, s,
+                                  bt));
         // close to convergence: learn whether this cycle opens before enqueuing it
         if (min_est <= tol)
             CHK(wait_for(p, nrhs, s,
@@ -1284,7 +1287,8 @@ int check_solve_args(hh_problem p, const void* f_dev, const void* u_dev, const v
     if (!(tol > 0.0 && tol < 1.0)) return fail(HH_EINVAL, "tol must be in (0, 1)");
     if (restart < 1 || restart > kMaxRestart) return fail(HH_EINVAL, "restart must be in [1, 1024]");
     if (max_iters < 1 || max_iters > (1 << 28)) return fail(HH_EINVAL, "max_iters must be in [1, 2^28]");
-    if (flags & ~(HH_NO_PRECOND | HH_PRECOND_F32)) return fail(HH_EINVAL, "unknown flag");
+    if (flags & ~(HH_NO_PRECOND | HH_PRECOND_F32 | HH_INITIAL_GUESS))
+        return fail(HH_EINVAL, "unknown flag");
     if ((flags & HH_NO_PRECOND) && (flags & HH_PRECOND_F32))
         return fail(HH_EINVAL, "HH_NO_PRECOND and HH_PRECOND_F32 exclude each other");
     if (f_dev == u_dev) return fail(HH_EINVAL, "f_dev and u_dev must be distinct");

@@ -325,8 +325,11 @@ hipError_t launch_reduce_pred(const cplx* partial, int nb, int k, cplx* out, con
 hipError_t launch_residual_norm(const FineOp& op, const cplx* b, const cplx* u, cplx* r,
                                 cplx* partial, const int* done, hipStream_t s,
                                 const Batch& bt = Batch());
+// warm: the solve started from a given guess; the first cycle records its
+// relative residual as hist[0]
 hipError_t launch_cycle_start(SolveState* st, const cplx* partial, int nb, cplx* g,
-                              HostRecord* rec, hipStream_t s, const Batch& bt = Batch());
+                              HostRecord* rec, double* hist, int64_t hist_stride, bool warm,
+                              hipStream_t s, const Batch& bt = Batch());
 struct GivensArgs;
 // Arnoldi step with delayed reorthogonalisation, second pass (see krylov.hip):
 // V_j <- reorthogonalised, normalised u = V_j; V_{j+1} <- w projected once;
@@ -345,9 +348,11 @@ hipError_t launch_cycle_finish(SolveState* st, int m, const cplx* R, const cplx*
 hipError_t launch_cycle_finish(SolveState* st, int m, const cplx* R, const cplx* g,
                                const double* zs, cplx* y, const cplxf* Z, int64_t n, cplx* x,
                                hipStream_t s, const Batch& bt = Batch());
+// u_warm: the caller's initial guesses (zeroed for a zero right-hand side), or
+// null when the solve starts from zero; n nodes per wavefield
 hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
                              double tol, HostRecord* rec, double* hist, int64_t hist_stride,
-                             hipStream_t s, const Batch& bt = Batch());
+                             cplx* u_warm, int64_t n, hipStream_t s, const Batch& bt = Batch());
 
 // ---- V-cycle kernels (vcycle_tiled.hip, coarsest.hip) ------------------------
 // coarsest level: y = A x (one right-hand side), or for every right-hand side

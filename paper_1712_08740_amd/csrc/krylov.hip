@@ -581,21 +581,26 @@ __device__ __forceinline__ double block_sum_partials(const cplx* partial, int nb
 }
 
 // Start of a restart cycle: beta = ||b - H u||; decide whether the solve is
-// finished; otherwise reset the least-squares state and open the cycle.
+// finished; otherwise reset the least-squares state and open the cycle. From
+// a given initial guess (warm), the first cycle's relative residual is the
+// history's first entry.
 __global__ void __launch_bounds__(256) k_cycle_start(SolveState* st, const cplx* __restrict__ partial,
                                                      int nb, cplx* __restrict__ g,
-                                                     HostRecord* rec, int64_t bs) {
+                                                     HostRecord* rec, int64_t bs, double* hist,
+                                                     int64_t hist_stride, int warm) {
     const int rb = blockIdx.x;
     st = rhs_nn(st, rb, bs);
     partial = rhs_nn(partial, rb, bs);
     g = rhs_nn(g, rb, bs);
     rec += rb;
+    hist += (int64_t)rb * hist_stride;
     if (st->done) return;
     __shared__ double sh[4];
     const double beta = sqrt(block_sum_partials(partial, nb, sh));
     if (threadIdx.x != 0) return;
     const double rel = beta / st->beta0;
     st->rel = rel;
+    if (warm && st->it == 0) hist[0] = rel;
     int done = 0, status = 0;
     if (!isfinite(rel)) { done = 1; status = -4; }
     else if (rel <= st->tol) { done = 1; status = 0; }
@@ -739,11 +744,14 @@ __global__ void k_cycle_end(SolveState* st, int64_t bs) {
     if (threadIdx.x == 0) rhs_at(st, (int)blockIdx.x, bs)->k = 0;
 }
 
-// solve prologue: beta0 = ||b|| from partials; sets done when b == 0 or not finite
+// solve prologue: beta0 = ||b|| from partials; sets done when b == 0 or not
+// finite. b == 0 has the solution u = 0, also from a given initial guess
+// (u_warm: the guess, zeroed here in that case; null when u starts at 0).
 __global__ void __launch_bounds__(256) k_solve_init(SolveState* st, const cplx* __restrict__ partial,
                                                     int nb, int m, int max_iters, double tol,
                                                     HostRecord* rec, double* hist, int64_t bs,
-                                                    int64_t hist_stride) {
+                                                    int64_t hist_stride, cplx* u_warm, int64_t n,
+                                                    int64_t fs) {
     const int rb = blockIdx.x;
     st = rhs_nn(st, rb, bs);
     partial = rhs_nn(partial, rb, bs);
@@ -751,6 +759,10 @@ __global__ void __launch_bounds__(256) k_solve_init(SolveState* st, const cplx* 
     hist += (int64_t)rb * hist_stride;
     __shared__ double sh[4];
     const double b2 = block_sum_partials(partial, nb, sh);
+    if (u_warm && b2 == 0.0) {
+        cplx* u = u_warm + (int64_t)rb * fs;
+        for (int64_t p = threadIdx.x; p < n; p += 256) u[p] = mk(0.0, 0.0);
+    }
     if (threadIdx.x != 0) return;
     const double beta0 = sqrt(b2);
     st->beta0 = beta0;
@@ -894,8 +906,10 @@ hipError_t launch_residual_norm(const FineOp& op, const cplx* b, const cplx* u, 
     return hipGetLastError();
 }
 hipError_t launch_cycle_start(SolveState* st, const cplx* partial, int nb, cplx* g,
-                              HostRecord* rec, hipStream_t s, const Batch& bt) {
-    HH_LAUNCH(k_cycle_start, dim3(bt.n), dim3(256), 0, s, st, partial, nb, g, rec, bt.bs);
+                              HostRecord* rec, double* hist, int64_t hist_stride, bool warm,
+                              hipStream_t s, const Batch& bt) {
+    HH_LAUNCH(k_cycle_start, dim3(bt.n), dim3(256), 0, s, st, partial, nb, g, rec, bt.bs, hist,
+              hist_stride, warm ? 1 : 0);
     return hipGetLastError();
 }
 hipError_t launch_givens_tail(const GivensArgs& a, hipStream_t s, const Batch& bt) {
@@ -948,9 +962,9 @@ hipError_t launch_cycle_finish(SolveState* st, int m, const cplx* R, const cplx*
 }
 hipError_t launch_solve_init(SolveState* st, const cplx* partial, int nb, int m, int max_iters,
                              double tol, HostRecord* rec, double* hist, int64_t hist_stride,
-                             hipStream_t s, const Batch& bt) {
+                             cplx* u_warm, int64_t n, hipStream_t s, const Batch& bt) {
     HH_LAUNCH(k_solve_init, dim3(bt.n), dim3(256), 0, s, st, partial, nb, m, max_iters, tol,
-              rec, hist, bt.bs, hist_stride);
+              rec, hist, bt.bs, hist_stride, u_warm, n, bt.fs);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ HH_EDEVICE = -3
 HH_ENUMERIC = -4
 HH_EUNSUPPORTED = -5
 HH_NO_PRECOND = 1
+HH_INITIAL_GUESS = 4
 HH_PRECOND_F32 = 2
 HH_MAX_COARSE = 4096
 HH_MAX_COARSE_LIMIT = 32768
@@ -312,8 +313,10 @@ class Problem:
     def solve_batch(self, F: torch.Tensor, tol: float = 1e-6, restart: int = 30,
                     max_iters: int = 2000, no_precond: bool = False, precond_f32: bool = False,
                     U: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
-                    stream=None, hist_cap: int = 0) -> BatchResult:
-        """``hh_solve_batch``: F is (nrhs, *shape) complex128, one source per row."""
+                    stream=None, hist_cap: int = 0,
+                    X0: Optional[torch.Tensor] = None) -> BatchResult:
+        """``hh_solve_batch``: F is (nrhs, *shape) complex128, one source per row.
+        ``X0`` (same shape) are initial guesses (HH_INITIAL_GUESS), copied into U."""
         if F.dim() != len(self.shape) + 1:
             raise ValueError(f"F must have shape (nrhs, {self.shape})")
         nrhs = F.shape[0]
@@ -322,6 +325,10 @@ class Problem:
             U = torch.empty_like(F)
         else:
             _dev_tensor(U, torch.complex128, (nrhs,) + tuple(self.shape), "U")
+        if X0 is not None:
+            _dev_tensor(X0, torch.complex128, (nrhs,) + tuple(self.shape), "X0")
+            if X0.data_ptr() != U.data_ptr():
+                U.copy_(X0)
         need = self.workspace_bytes_batch(restart, nrhs)
         ws = workspace if workspace is not None else torch.empty(need, dtype=torch.uint8,
                                                                  device=self.device)
@@ -332,6 +339,7 @@ class Problem:
         sts = (ctypes.c_int * nrhs)()
         hist = np.zeros((nrhs, max(hist_cap, 1)), dtype=np.float64)
         flags = (HH_NO_PRECOND if no_precond else 0) | (HH_PRECOND_F32 if precond_f32 else 0)
+        flags |= HH_INITIAL_GUESS if X0 is not None else 0
         st = _check(_lib.hh_solve_batch(self._handle, nrhs, _vp(F.data_ptr()), float(tol),
                                         int(restart), int(max_iters), flags, _vp(ws.data_ptr()),
                                         ws.numel() * ws.element_size(), _vp(U.data_ptr()), its,
@@ -446,14 +454,21 @@ class Problem:
     def solve(self, f: torch.Tensor, tol: float = 1e-6, restart: int = 30,
               max_iters: int = 2000, no_precond: bool = False, u: Optional[torch.Tensor] = None,
               workspace: Optional[torch.Tensor] = None, stream=None,
-              hist_cap: Optional[int] = None, precond_f32: bool = False) -> SolveResult:
+              hist_cap: Optional[int] = None, precond_f32: bool = False,
+              x0: Optional[torch.Tensor] = None) -> SolveResult:
         """Right-preconditioned FGMRES(restart) to ``tol`` (``hh_solve``).
-        ``precond_f32`` runs the preconditioner in complex64 (HH_PRECOND_F32)."""
+        ``precond_f32`` runs the preconditioner in complex64 (HH_PRECOND_F32).
+        ``x0`` is an initial guess (HH_INITIAL_GUESS), copied into ``u``: a solve
+        that returned HH_NOT_CONVERGED resumes from its ``u``."""
         _dev_tensor(f, torch.complex128, self.shape, "f")
         if u is None:
             u = torch.empty_like(f)
         else:
             _dev_tensor(u, torch.complex128, self.shape, "u")
+        if x0 is not None:
+            _dev_tensor(x0, torch.complex128, self.shape, "x0")
+            if x0.data_ptr() != u.data_ptr():
+                u.copy_(x0)
         ws = workspace if workspace is not None else self.workspace(restart)
         need = self.workspace_bytes(restart)
         if ws.numel() * ws.element_size() < need:
@@ -464,6 +479,7 @@ class Problem:
         rel = ctypes.c_double()
         hlen = ctypes.c_int()
         flags = (HH_NO_PRECOND if no_precond else 0) | (HH_PRECOND_F32 if precond_f32 else 0)
+        flags |= HH_INITIAL_GUESS if x0 is not None else 0
         st = _check(_lib.hh_solve(self._handle, _vp(f.data_ptr()), float(tol), int(restart),
                                   int(max_iters), flags, _vp(ws.data_ptr()),
                                   ws.numel() * ws.element_size(), _vp(u.data_ptr()),

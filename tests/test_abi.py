@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_constants_match_header(lib):
     src = open(HEADER).read()
-    for name in ("HH_MAX_COARSE", "HH_MAX_1D", "HH_NO_PRECOND"):
+    for name in ("HH_MAX_COARSE", "HH_MAX_1D", "HH_NO_PRECOND", "HH_PRECOND_F32", "HH_INITIAL_GUESS"):
         v = int(re.search(rf"#define {name} (\d+)", src).group(1))
         assert getattr(lib, name) == v
     for name, val in re.findall(r"(HH_[A-Z_]+)\s*=\s*(-?\d+)", src):

@@ -919,3 +919,81 @@ def test_tile_argument_checks(hh):
     assert Q.autotune() == []
     with pytest.raises(hh.HHError):
         Q.get_tiles(0)
+
+
+# ---------------------------------------------------------------------------
+# initial guess: resuming a stopped solve (HH_INITIAL_GUESS)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
+def test_resume_at_a_cycle_boundary_gives_the_same_bits(hh, f32):
+    """Restarted GMRES carries nothing across a restart but the iterate: a
+    solve stopped by its budget at the end of a cycle and resumed from the
+    returned u gives the uninterrupted solve's bits, the iterations adding up;
+    the resumed history starts at the stopped solve's true residual."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    f = _t(w.source)
+    kw = dict(tol=w.tol, restart=10, precond_f32=f32)
+    full = P.solve(f, max_iters=2000, **kw)
+    assert full.status == hh.HH_OK and full.iterations > 20
+    part = P.solve(f, max_iters=20, **kw)
+    assert part.status == hh.HH_NOT_CONVERGED and part.iterations == 20
+    rest = P.solve(f, max_iters=2000, x0=part.u.clone(), **kw)
+    assert rest.status == hh.HH_OK
+    assert rest.iterations + 20 == full.iterations
+    assert np.array_equal(_np(rest.u), _np(full.u))
+    assert rest.history[0] == pytest.approx(part.true_rel_res, rel=1e-12)
+    assert rest.true_rel_res == full.true_rel_res
+
+
+def test_initial_guess_edge_cases(hh):
+    """From the converged solution no iteration is taken and u keeps its bits;
+    a zero source returns u = 0 whatever the guess; from a guess stopped in the
+    middle of a cycle the solve still meets the tolerance on the residual."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    f = _t(w.source)
+    done = P.solve(f, tol=w.tol, restart=w.restart)
+    again = P.solve(f, tol=w.tol, restart=w.restart, x0=done.u.clone())
+    assert again.status == hh.HH_OK and again.iterations == 0
+    assert np.array_equal(_np(again.u), _np(done.u))
+    assert again.history[0] == pytest.approx(done.true_rel_res, rel=1e-12)
+    junk = _t(wl.random_complex(w.shape, 11))
+    zero = P.solve(torch.zeros_like(f), tol=w.tol, restart=w.restart, x0=junk)
+    assert zero.status == hh.HH_OK and zero.iterations == 0
+    assert not torch.any(zero.u != 0)
+    mid = P.solve(f, tol=w.tol, restart=w.restart, max_iters=13)
+    assert mid.status == hh.HH_NOT_CONVERGED
+    rest = P.solve(f, tol=w.tol, restart=w.restart, x0=mid.u.clone())
+    assert rest.status == hh.HH_OK and rest.true_rel_res <= w.tol
+    # the residual recomputed in FP64 by the oracle's operator
+    H = op.helmholtz(w.slowness, w.omega, w.alpha, w.h)
+    b = op.weighted_rhs(w.source).ravel()
+    r = np.linalg.norm(b - H @ _np(rest.u).ravel())
+    assert r <= w.tol * (1 + 1e-6) * np.linalg.norm(b)
+
+
+def test_batch_resume_at_a_cycle_boundary(hh):
+    """The batch resumes the same way, source by source: a source that had
+    converged stays converged with no iteration, a zero source returns zero from
+    a non-zero guess, and the rest give the uninterrupted batch's bits."""
+    w = wl.grf_401x201()
+    P = _problem(hh, w.slowness, w.omega, w.alpha, w.h)
+    F = _t(_batch_sources(w.shape, [(5, 200), (100, 37), None, (200, 400)]))
+    kw = dict(tol=w.tol, restart=10)
+    full = P.solve_batch(F, max_iters=2000, **kw)
+    assert full.overall == 0 and full.iterations[2] == 0
+    part = P.solve_batch(F, max_iters=20, **kw)
+    X0 = part.u.clone()
+    X0[2] = _t(wl.random_complex(w.shape, 12))
+    rest = P.solve_batch(F, max_iters=2000, X0=X0, **kw)
+    assert rest.overall == 0 and np.all(rest.status == 0)
+    assert not torch.any(rest.u[2] != 0) and rest.iterations[2] == 0
+    for i in (0, 1, 3):
+        if part.status[i] == hh.HH_OK:
+            assert rest.iterations[i] == 0
+            assert np.array_equal(_np(rest.u[i]), _np(part.u[i])), i
+        else:
+            assert part.iterations[i] == 20
+            assert rest.iterations[i] + 20 == full.iterations[i], i
+            assert np.array_equal(_np(rest.u[i]), _np(full.u[i])), i
