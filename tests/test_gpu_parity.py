@@ -962,6 +962,11 @@ def test_initial_guess_edge_cases(hh):
     zero = P.solve(torch.zeros_like(f), tol=w.tol, restart=w.restart, x0=junk)
     assert zero.status == hh.HH_OK and zero.iterations == 0
     assert not torch.any(zero.u != 0)
+    bad = done.u.clone()
+    bad[3, 7] = complex(float("nan"), 0.0)
+    with pytest.raises(hh.HHError) as e:       # a non-finite guess is a non-finite residual
+        P.solve(f, tol=w.tol, restart=w.restart, x0=bad)
+    assert e.value.status == hh.HH_ENUMERIC
     mid = P.solve(f, tol=w.tol, restart=w.restart, max_iters=13)
     assert mid.status == hh.HH_NOT_CONVERGED
     rest = P.solve(f, tol=w.tol, restart=w.restart, x0=mid.u.clone())
